@@ -1,0 +1,173 @@
+/*
+ * mdforce.h -- C ABI of the MI355X (gfx950) short-range non-bonded force library.
+ *
+ * The library evaluates one iteration of the short-range non-bonded force of
+ * molecular dynamics, the critical path named in Section 2.1 of Cong, Fang,
+ * Kianinejad, Wei, "Revisiting FPGA Acceleration of Molecular Dynamics Simulation
+ * with Dynamic Data Flow Behavior in High-Level Synthesis" (arXiv:1611.04474):
+ *
+ *   - Lennard-Jones force, Eq. 1:  F = (A/|r|^14 - B/|r|^8) r,
+ *     with A = 48 eps_ij s_ij^12 and B = 24 eps_ij s_ij^6 from per-type sigma and
+ *     epsilon by Lorentz-Berthelot mixing (s_ij = (s_i+s_j)/2, eps_ij = sqrt(eps_i eps_j));
+ *   - Coulomb force, Eq. 2:  F = k q_i q_j / |r|^3 r;
+ *   - the cutoff of Section 2.1: a pair interacts only if |r|^2 < r_cut^2;
+ *   - the cell list of Section 2.1 (Fig. 2, Algorithm 1): space is cut into cells of
+ *     edge at least r_cut and each atom meets only the atoms of its 3x3x3 cells.
+ *
+ * r is x_i - x_j (the force on atom i is +f r; a positive f pushes i and j apart).
+ * The whole pair energy e = c12/r^12 - c6/r^6 + k q_i q_j / r (c12 = 4 eps s^12,
+ * c6 = 4 eps s^6) is multiplied by the switch S(u), u = r^2, which is 1 up to
+ * r_switch^2 and (rc2-u)^2 (rc2+2u-3rs2)/(rc2-rs2)^3 between r_switch^2 and r_cut^2;
+ * forces are minus the gradient of S e. r_switch == r_cut turns switching off.
+ * Units: Angstrom, elementary charge, kcal/mol.
+ *
+ * Conventions for every call:
+ *   - d_ pointers are device pointers on the current HIP device; h_ pointers, and
+ *     the sigma/epsilon arrays inside md_params, are host pointers.
+ *   - The caller owns every buffer, including the workspace; the library allocates
+ *     no device memory and keeps no global state, so calls with distinct
+ *     workspaces may run concurrently.
+ *   - Argument checks are synchronous and return an md_status; nothing is enqueued
+ *     when a check fails. Work is enqueued on `stream` (a hipStream_t, or NULL for
+ *     the default stream) and outputs are valid once the stream reaches the call.
+ *   - Conditions found on the device (NaN or out-of-range positions, bad type
+ *     indices, fixed-point overflow) set bits of a sticky status word in the
+ *     workspace, read with md_read_device_status.
+ */
+#ifndef MDFORCE_H
+#define MDFORCE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MD_OK = 0,
+  MD_ERR_INVALID_ARG = -1,   /* null pointer, n_atoms < 0, bad flags, r_switch > r_cut ... */
+  MD_ERR_BOX_TOO_SMALL = -2, /* some box edge gives fewer than 2 cells of edge >= r_cut */
+  MD_ERR_WORKSPACE = -3,     /* workspace null, misaligned (256 B) or smaller than needed */
+  MD_ERR_HIP = -4,           /* a HIP runtime call failed */
+  MD_ERR_DEVICE_STATUS = -5, /* reserved for callers that fold the status word in */
+  MD_ERR_CAPACITY = -6       /* problem exceeds an internal limit (cells, atoms, types) */
+} md_status;
+
+/* md_params.flags */
+enum {
+  MD_ACCUM_FIXED64 = 0,         /* default: per-atom sums in 64-bit fixed point (2^-32 kcal/mol/A) */
+  MD_ACCUM_F32_ATOMIC = 1 << 0, /* per-atom sums with float32 atomics (order-dependent) */
+  MD_COULOMB_TRUNCATED = 1 << 1,/* switch only the LJ energy; Coulomb is Eq. 2 up to r_cut */
+  MD_DIAG_COUNTERS = 1 << 2,    /* count candidates, filter passes and per-atom partners */
+  MD_PAIR_PREDICATED = 1 << 3   /* evaluate the force under the cutoff predicate, without
+                                   compacting passing pairs (the uncompacted data flow) */
+};
+
+/* Device status bits (sticky until the next force call on the workspace). */
+enum {
+  MD_STATUS_NAN = 1u << 0,          /* a position is NaN */
+  MD_STATUS_OUT_OF_BOX = 1u << 1,   /* a coordinate lies outside [-L, 2L) */
+  MD_STATUS_BAD_TYPE = 1u << 2,     /* a type index outside [0, n_types) */
+  MD_STATUS_FIXED_OVERFLOW = 1u << 3/* a force does not fit the 64-bit fixed-point range */
+};
+
+/* Problem description. The box is orthorhombic and periodic on all three axes;
+ * each edge must give at least two cells of edge >= r_cut (so L >= 2 r_cut, with a
+ * 1e-3 A margin: n_d = floor(L_d/r_cut), reduced by one when L_d/n_d - r_cut < 1e-3).
+ * The float32 entry points use every box edge rounded once to float32. */
+typedef struct {
+  double box[3];          /* A */
+  double r_cut;           /* A, > 0 */
+  double r_switch;        /* A, 0 < r_switch <= r_cut */
+  double coulomb_k;       /* kcal*A/(mol*e^2), e.g. 332.0636 */
+  int32_t n_types;        /* 1 .. 64 */
+  const double* sigma;    /* host [n_types], A */
+  const double* epsilon;  /* host [n_types], kcal/mol, >= 0 */
+  uint32_t flags;         /* MD_* flags above */
+} md_params;
+
+/* Bytes of device workspace needed by md_forces_f32 (double_precision = 0) or
+ * md_forces_f64 (double_precision = 1) for n_atoms atoms. Returns 0 when the
+ * parameters are invalid. The workspace must be 256-byte aligned; its contents
+ * need no initialisation and are scratch between calls. */
+size_t md_workspace_bytes(const md_params* p, int64_t n_atoms, int double_precision);
+
+/*
+ * One evaluation of the short-range non-bonded forces (Section 2.1, Algorithm 1).
+ *   d_pos     [n_atoms][3] float32, x,y,z interleaved; coordinates in [-L, 2L) are
+ *             wrapped into the box with one float32 add or subtract of L.
+ *   d_type    [n_atoms] int32 type indices in [0, n_types).
+ *   d_charge  [n_atoms] float32 charges (e).
+ *   d_force   [n_atoms][3] float32 output, in the caller's atom order, kcal/mol/A.
+ *   d_energy  [1] float64 output, total pair energy over unique pairs, kcal/mol.
+ *   d_ws      workspace of at least md_workspace_bytes(p, n_atoms, 0) bytes.
+ * n_atoms == 0 enqueues a zero energy only. Pair arithmetic is float32; per-atom
+ * sums are 64-bit fixed point unless MD_ACCUM_F32_ATOMIC; the energy is summed in
+ * float64 in a fixed order.
+ */
+md_status md_forces_f32(const md_params* p, int64_t n_atoms, const float* d_pos,
+                        const int32_t* d_type, const float* d_charge, float* d_force,
+                        double* d_energy, void* d_ws, size_t ws_bytes, void* stream);
+
+/* Same as md_forces_f32 with float64 positions, charges, forces and pair
+ * arithmetic throughout (per-atom sums in float64, fixed order). */
+md_status md_forces_f64(const md_params* p, int64_t n_atoms, const double* d_pos,
+                        const int32_t* d_type, const double* d_charge, double* d_force,
+                        double* d_energy, void* d_ws, size_t ws_bytes, void* stream);
+
+/* One system of a batch (float32 path). Every field as in md_forces_f32. */
+typedef struct {
+  md_params p;
+  int64_t n_atoms;
+  const float* d_pos;
+  const int32_t* d_type;
+  const float* d_charge;
+  float* d_force;
+  double* d_energy;
+  void* d_ws;
+  size_t ws_bytes;
+} md_system;
+
+/* Evaluates n_sys independent systems, each in its own periodic box with its own
+ * workspace, as one launch sequence on `stream`: each kernel of the path is
+ * launched once for the whole batch. Results are identical to one md_forces_f32
+ * call per system. Argument errors of any system fail the whole call before
+ * anything is enqueued. */
+md_status md_forces_batched(const md_system* systems, int32_t n_sys, void* stream);
+
+/* Copies the sticky device status word of a workspace to *bits (MD_STATUS_* bits).
+ * Synchronises `stream`. */
+md_status md_read_device_status(const void* d_ws, void* stream, uint32_t* bits);
+
+/* Diagnostic counters of the last call with MD_DIAG_COUNTERS on this workspace:
+ * [0] candidate pairs tested, [1] pairs passing the filter stage, [2] pairs inside
+ * the cutoff. Synchronises `stream`. */
+md_status md_read_diag(const void* d_ws, void* stream, uint64_t counters[3]);
+
+/* Layout of the workspace, for inspection of intermediate results. Offsets are in
+ * bytes from the workspace start.
+ *   cell_start: int32 [n_cells+1], first sorted index of each cell
+ *   perm:       int32 [n_atoms], original index of each sorted atom
+ *   pair_count: int32 [n_atoms], partners inside the cutoff (MD_DIAG_COUNTERS),
+ *               in the caller's atom order */
+typedef struct {
+  int32_t dims[3];
+  int64_t n_cells;
+  size_t cell_start;
+  size_t perm;
+  size_t pair_count;
+  size_t total_bytes;
+} md_layout;
+
+md_status md_workspace_layout(const md_params* p, int64_t n_atoms, int double_precision,
+                              md_layout* out);
+
+/* Static description of a status code. */
+const char* md_status_string(md_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MDFORCE_H */

@@ -1,0 +1,245 @@
+// C ABI entry points: argument checks, the cell grid, the workspace carve-up, and
+// the launch sequence binning -> pair -> finalize on the caller's stream.
+#include <math.h>
+#include <string.h>
+
+#include "md_common.hpp"
+
+namespace md {
+
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static md_status check_params(const md_params* p) {
+  if (!p) return MD_ERR_INVALID_ARG;
+  if (p->n_types < 1) return MD_ERR_INVALID_ARG;
+  if (p->n_types > kMaxTypes) return MD_ERR_CAPACITY;
+  if (!p->sigma || !p->epsilon) return MD_ERR_INVALID_ARG;
+  for (int t = 0; t < p->n_types; ++t) {
+    if (!isfinite(p->sigma[t]) || !isfinite(p->epsilon[t]) || p->epsilon[t] < 0)
+      return MD_ERR_INVALID_ARG;
+  }
+  if (!(p->r_cut > 0) || !isfinite(p->r_cut)) return MD_ERR_INVALID_ARG;
+  if (!(p->r_switch > 0) || p->r_switch > p->r_cut) return MD_ERR_INVALID_ARG;
+  if (!isfinite(p->coulomb_k)) return MD_ERR_INVALID_ARG;
+  const uint32_t known = MD_ACCUM_F32_ATOMIC | MD_COULOMB_TRUNCATED | MD_DIAG_COUNTERS |
+                         MD_PAIR_PREDICATED;
+  if (p->flags & ~known) return MD_ERR_INVALID_ARG;
+  for (int d = 0; d < 3; ++d)
+    if (!isfinite(p->box[d]) || !(p->box[d] > 0)) return MD_ERR_INVALID_ARG;
+  return MD_OK;
+}
+
+// Grid rule: n_d = floor(L_d / r_cut), one cell fewer when L_d/n_d exceeds r_cut by
+// less than 1e-3 A (so rounding of a coordinate at a cell face never hides a pair),
+// and at least 2 cells per axis (L >= 2 r_cut keeps the minimum image unique).
+md_status make_plan(const md_params* p, int64_t n, int real_bytes, Plan* pl) {
+  md_status s = check_params(p);
+  if (s != MD_OK) return s;
+  if (n < 0) return MD_ERR_INVALID_ARG;
+  if (n > kMaxAtoms) return MD_ERR_CAPACITY;
+  int64_t cells = 1;
+  for (int d = 0; d < 3; ++d) {
+    double L = real_bytes == 4 ? (double)(float)p->box[d] : p->box[d];
+    double q = floor(L / p->r_cut);
+    if (q > 1e7) return MD_ERR_CAPACITY;
+    int nd = (int)q;
+    if (nd >= 1 && L / nd - p->r_cut < 1e-3) nd -= 1;
+    if (nd < 2) return MD_ERR_BOX_TOO_SMALL;
+    pl->dims[d] = nd;
+    cells *= nd;
+    if (cells > kMaxCells) return MD_ERR_CAPACITY;
+  }
+  pl->n_cells = cells;
+  pl->n_tasks = cells * kTasksPerCell;
+  pl->n = n;
+  pl->real_bytes = real_bytes;
+  const size_t nn = (size_t)(n > 0 ? n : 1);
+  size_t o = align_up(sizeof(WsHeader));
+  pl->off_count = o;     o = align_up(o + sizeof(int32_t) * cells);
+  pl->off_start = o;     o = align_up(o + sizeof(int32_t) * (cells + 1));
+  pl->off_cell = o;      o = align_up(o + sizeof(int32_t) * nn);
+  pl->off_rank = o;      o = align_up(o + sizeof(int32_t) * nn);
+  pl->off_unsorted = o;  o = align_up(o + sizeof(int32_t) * nn);
+  pl->off_pos = o;       o = align_up(o + (size_t)4 * real_bytes * nn);
+  pl->off_type = o;      o = align_up(o + sizeof(int32_t) * nn);
+  pl->off_perm = o;      o = align_up(o + sizeof(int32_t) * nn);
+  pl->off_part = o;      o = align_up(o + (size_t)real_bytes * kSlots * 3 * nn);
+  pl->off_facc = o;      o = align_up(o + sizeof(float) * 3 * nn);
+  pl->off_epart = o;     o = align_up(o + sizeof(double) * pl->n_tasks);
+  pl->off_lj = o;        o = align_up(o + (size_t)real_bytes * 2 * kMaxTypes * kMaxTypes);
+  pl->off_paircount = o; o = align_up(o + sizeof(int32_t) * 2 * nn);
+  pl->total = o;
+  return MD_OK;
+}
+
+template <typename Real>
+SysArgs<Real> make_args(const md_params* p, const Plan& pl, int64_t n, const Real* pos,
+                        const int32_t* type, const Real* q, Real* force, double* energy,
+                        void* ws) {
+  SysArgs<Real> a;
+  char* b = (char*)ws;
+  a.pos_in = pos;
+  a.type_in = type;
+  a.q_in = q;
+  a.force_out = force;
+  a.energy_out = energy;
+  a.hdr = (WsHeader*)b;
+  a.count = (int32_t*)(b + pl.off_count);
+  a.start = (int32_t*)(b + pl.off_start);
+  a.cell = (int32_t*)(b + pl.off_cell);
+  a.rank = (int32_t*)(b + pl.off_rank);
+  a.unsorted = (int32_t*)(b + pl.off_unsorted);
+  a.pos = (P4<Real>*)(b + pl.off_pos);
+  a.type = (int32_t*)(b + pl.off_type);
+  a.perm = (int32_t*)(b + pl.off_perm);
+  a.part = (Real*)(b + pl.off_part);
+  a.facc = (float*)(b + pl.off_facc);
+  a.epart = (double*)(b + pl.off_epart);
+  a.lj = (Real*)(b + pl.off_lj);
+  a.paircount = (int32_t*)(b + pl.off_paircount);
+  a.n = n;
+  a.n_cells = pl.n_cells;
+  a.n_tasks = pl.n_tasks;
+  a.nx = pl.dims[0];
+  a.ny = pl.dims[1];
+  a.nz = pl.dims[2];
+  a.n_types = p->n_types;
+  for (int d = 0; d < 3; ++d) {
+    a.L[d] = (Real)p->box[d];
+    a.inv_w[d] = (Real)((double)pl.dims[d] / (double)a.L[d]);
+  }
+  const double rc2 = p->r_cut * p->r_cut, rs2 = p->r_switch * p->r_switch;
+  a.rc2 = (Real)rc2;
+  a.rs2 = (Real)rs2;
+  a.inv_sw = p->r_switch < p->r_cut ? (Real)(1.0 / (rc2 - rs2)) : Real(0);
+  a.coulomb_k = (Real)p->coulomb_k;
+  a.flags = p->flags;
+  return a;
+}
+
+template SysArgs<float> make_args<float>(const md_params*, const Plan&, int64_t, const float*,
+                                         const int32_t*, const float*, float*, double*, void*);
+template SysArgs<double> make_args<double>(const md_params*, const Plan&, int64_t,
+                                           const double*, const int32_t*, const double*,
+                                           double*, double*, void*);
+
+template <typename Real>
+static md_status forces_impl(const md_params* p, int64_t n, const Real* pos,
+                             const int32_t* type, const Real* q, Real* force, double* energy,
+                             void* ws, size_t ws_bytes, void* stream) {
+  Plan pl;
+  md_status s = make_plan(p, n, (int)sizeof(Real), &pl);
+  if (s != MD_OK) return s;
+  if (!energy || ((uintptr_t)energy & 7)) return MD_ERR_INVALID_ARG;
+  if (n > 0) {
+    if (!pos || !type || !q || !force) return MD_ERR_INVALID_ARG;
+    if (((uintptr_t)pos | (uintptr_t)q | (uintptr_t)force) & (sizeof(Real) - 1))
+      return MD_ERR_INVALID_ARG;
+    if ((uintptr_t)type & 3) return MD_ERR_INVALID_ARG;
+  }
+  if (!ws || ((uintptr_t)ws & 255) || ws_bytes < pl.total) return MD_ERR_WORKSPACE;
+  SysArgs<Real> a = make_args<Real>(p, pl, n, pos, type, q, force, energy, ws);
+  hipStream_t st = (hipStream_t)stream;
+  if (launch_binning<Real>(a, p->sigma, p->epsilon, st) != hipSuccess) return MD_ERR_HIP;
+  if (launch_pair<Real>(a, st) != hipSuccess) return MD_ERR_HIP;
+  if (launch_finalize<Real>(a, st) != hipSuccess) return MD_ERR_HIP;
+  return MD_OK;
+}
+
+}  // namespace md
+
+extern "C" {
+
+size_t md_workspace_bytes(const md_params* p, int64_t n_atoms, int double_precision) {
+  md::Plan pl;
+  if (md::make_plan(p, n_atoms, double_precision ? 8 : 4, &pl) != MD_OK) return 0;
+  return pl.total;
+}
+
+md_status md_workspace_layout(const md_params* p, int64_t n_atoms, int double_precision,
+                              md_layout* out) {
+  if (!out) return MD_ERR_INVALID_ARG;
+  md::Plan pl;
+  md_status s = md::make_plan(p, n_atoms, double_precision ? 8 : 4, &pl);
+  if (s != MD_OK) return s;
+  for (int d = 0; d < 3; ++d) out->dims[d] = pl.dims[d];
+  out->n_cells = pl.n_cells;
+  out->cell_start = pl.off_start;
+  out->perm = pl.off_perm;
+  out->pair_count = pl.off_paircount;
+  out->total_bytes = pl.total;
+  return MD_OK;
+}
+
+md_status md_forces_f32(const md_params* p, int64_t n_atoms, const float* d_pos,
+                        const int32_t* d_type, const float* d_charge, float* d_force,
+                        double* d_energy, void* d_ws, size_t ws_bytes, void* stream) {
+  return md::forces_impl<float>(p, n_atoms, d_pos, d_type, d_charge, d_force, d_energy, d_ws,
+                                ws_bytes, stream);
+}
+
+md_status md_forces_f64(const md_params* p, int64_t n_atoms, const double* d_pos,
+                        const int32_t* d_type, const double* d_charge, double* d_force,
+                        double* d_energy, void* d_ws, size_t ws_bytes, void* stream) {
+  return md::forces_impl<double>(p, n_atoms, d_pos, d_type, d_charge, d_force, d_energy, d_ws,
+                                 ws_bytes, stream);
+}
+
+md_status md_forces_batched(const md_system* sys, int32_t n_sys, void* stream) {
+  if (n_sys < 0 || (n_sys > 0 && !sys)) return MD_ERR_INVALID_ARG;
+  for (int32_t k = 0; k < n_sys; ++k) {
+    md::Plan pl;
+    md_status s = md::make_plan(&sys[k].p, sys[k].n_atoms, 4, &pl);
+    if (s != MD_OK) return s;
+    if (!sys[k].d_ws || ((uintptr_t)sys[k].d_ws & 255) || sys[k].ws_bytes < pl.total)
+      return MD_ERR_WORKSPACE;
+    if (!sys[k].d_energy) return MD_ERR_INVALID_ARG;
+    if (sys[k].n_atoms > 0 &&
+        (!sys[k].d_pos || !sys[k].d_type || !sys[k].d_charge || !sys[k].d_force))
+      return MD_ERR_INVALID_ARG;
+  }
+  for (int32_t k = 0; k < n_sys; ++k) {
+    md_status s = md_forces_f32(&sys[k].p, sys[k].n_atoms, sys[k].d_pos, sys[k].d_type,
+                                sys[k].d_charge, sys[k].d_force, sys[k].d_energy, sys[k].d_ws,
+                                sys[k].ws_bytes, stream);
+    if (s != MD_OK) return s;
+  }
+  return MD_OK;
+}
+
+md_status md_read_device_status(const void* d_ws, void* stream, uint32_t* bits) {
+  if (!d_ws || !bits) return MD_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  uint32_t v = 0;
+  if (hipMemcpyAsync(&v, d_ws, sizeof(v), hipMemcpyDeviceToHost, st) != hipSuccess)
+    return MD_ERR_HIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return MD_ERR_HIP;
+  *bits = v;
+  return MD_OK;
+}
+
+md_status md_read_diag(const void* d_ws, void* stream, uint64_t counters[3]) {
+  if (!d_ws || !counters) return MD_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  md::WsHeader h;
+  if (hipMemcpyAsync(&h, d_ws, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess)
+    return MD_ERR_HIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return MD_ERR_HIP;
+  for (int k = 0; k < 3; ++k) counters[k] = h.diag[k];
+  return MD_OK;
+}
+
+const char* md_status_string(md_status s) {
+  switch (s) {
+    case MD_OK: return "ok";
+    case MD_ERR_INVALID_ARG: return "invalid argument";
+    case MD_ERR_BOX_TOO_SMALL: return "box too small: fewer than 2 cells of edge >= r_cut";
+    case MD_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
+    case MD_ERR_HIP: return "HIP runtime error";
+    case MD_ERR_DEVICE_STATUS: return "device status word set";
+    case MD_ERR_CAPACITY: return "problem exceeds an internal limit";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,97 @@
+// Internal declarations shared by the translation units of the force library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "mdforce.h"
+
+namespace md {
+
+constexpr int kMaxTypes = 64;
+constexpr int kTasksPerCell = 14;    // home cell + 13 forward neighbours (half shell)
+constexpr int kSlots = 27;           // partial-force slots per atom: 14 as home, 13 as neighbour
+constexpr int kTile = 256;           // atoms of one cell staged in LDS at a time
+constexpr int kPairThreads = 256;    // threads of one pair workgroup (4 waves)
+constexpr int64_t kMaxCells = 1 << 24;
+constexpr int64_t kMaxAtoms = (int64_t)1 << 30;
+
+// Workspace header (first 256 bytes).
+struct WsHeader {
+  uint32_t status;
+  uint32_t pad0;
+  unsigned long long diag[3];   // candidates, filter passes, cutoff passes
+  uint32_t pad1[56];
+};
+static_assert(sizeof(WsHeader) == 256, "header size");
+
+template <typename Real>
+struct alignas(4 * sizeof(Real)) P4 {
+  Real x, y, z, w;
+};
+
+// Cell grid and workspace carve-up for one system.
+struct Plan {
+  int32_t dims[3];
+  int64_t n_cells;
+  int64_t n_tasks;
+  int64_t n;
+  int real_bytes;               // 4 or 8
+  // byte offsets
+  size_t off_count, off_start, off_cell, off_rank, off_unsorted, off_pos, off_type, off_perm,
+      off_part, off_facc, off_epart, off_lj, off_paircount, total;
+};
+
+// Computes the grid and workspace layout; returns MD_OK or an error code.
+md_status make_plan(const md_params* p, int64_t n, int real_bytes, Plan* out);
+
+// Kernel-side constants of one system.
+template <typename Real>
+struct SysArgs {
+  // inputs
+  const Real* pos_in;          // [n][3]
+  const int32_t* type_in;      // [n]
+  const Real* q_in;            // [n]
+  Real* force_out;             // [n][3]
+  double* energy_out;          // [1]
+  // workspace
+  WsHeader* hdr;
+  int32_t* count;              // [n_cells]
+  int32_t* start;              // [n_cells+1]
+  int32_t* cell;               // [n]
+  int32_t* rank;               // [n]
+  int32_t* unsorted;           // [n]
+  P4<Real>* pos;               // [n] sorted (x,y,z,q)
+  int32_t* type;               // [n] sorted
+  int32_t* perm;               // [n] sorted -> original
+  Real* part;                  // [kSlots][3][n]
+  float* facc;                 // [3][n]
+  double* epart;               // [n_tasks]
+  Real* lj;                    // [n_types^2][2] (c12, c6)
+  int32_t* paircount;          // [n] sorted order during the pass, caller order after
+  // scalars
+  int64_t n, n_cells, n_tasks;
+  int nx, ny, nz, n_types;
+  Real L[3];                   // box (rounded once to Real)
+  Real inv_w[3];               // n_d / L_d
+  Real rc2, rs2, inv_sw;       // inv_sw = 1/(rc2 - rs2), 0 when switching is off
+  Real coulomb_k;
+  uint32_t flags;
+};
+
+template <typename Real>
+SysArgs<Real> make_args(const md_params* p, const Plan& pl, int64_t n, const Real* pos,
+                        const int32_t* type, const Real* q, Real* force, double* energy,
+                        void* ws);
+
+// Launchers (each enqueues on `stream`, returns hipSuccess or an error).
+template <typename Real>
+hipError_t launch_binning(const SysArgs<Real>& a, const double* sigma, const double* eps,
+                          hipStream_t stream);
+template <typename Real>
+hipError_t launch_pair(const SysArgs<Real>& a, hipStream_t stream);
+template <typename Real>
+hipError_t launch_finalize(const SysArgs<Real>& a, hipStream_t stream);
+
+}  // namespace md

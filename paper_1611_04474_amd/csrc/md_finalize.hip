@@ -1,0 +1,91 @@
+// Finalize: per-atom force sums and the total energy.
+//
+// k_finalize adds the 27 partial forces of each sorted atom (14 as a home atom, 13
+// as a neighbour) and writes the result in the caller's atom order. On the float32
+// path the partials are converted to 64-bit fixed point (one unit = 2^-32 kcal/mol/A,
+// round to nearest even) and summed as integers, so the per-atom total does not
+// depend on any summation order; an out-of-range value sets MD_STATUS_FIXED_OVERFLOW.
+// On the float64 path the partials are added in slot order.
+//
+// k_energy adds the per-task float64 energy partials in a fixed tree order.
+#include "md_common.hpp"
+
+namespace md {
+namespace {
+
+__device__ inline float fixed_sum(const float* part, int64_t n, int c, int64_t s, uint32_t& st) {
+  const double kScale = 4294967296.0;       // 2^32
+  const double kLimit = 9.2233720368547e18; // 2^63
+  long long acc = 0;
+  for (int slot = 0; slot < kSlots; ++slot) {
+    float v = part[((int64_t)slot * 3 + c) * n + s];
+    double d = (double)v * kScale;          // exact: 24-bit significand, power-of-two scale
+    if (!(fabs(d) < kLimit)) {
+      st |= MD_STATUS_FIXED_OVERFLOW;
+      continue;
+    }
+    long long q = __double2ll_rn(d);
+    long long r;
+    if (__builtin_add_overflow(acc, q, &r)) {
+      st |= MD_STATUS_FIXED_OVERFLOW;
+      continue;
+    }
+    acc = r;
+  }
+  return __ll2float_rn(acc) * 2.3283064365386963e-10f;   // * 2^-32, exact
+}
+
+template <typename Real>
+__global__ void k_finalize(SysArgs<Real> a) {
+  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.n) return;
+  const int64_t i = a.perm[s];
+  uint32_t st = 0;
+  for (int c = 0; c < 3; ++c) {
+    Real v;
+    if (a.flags & MD_ACCUM_F32_ATOMIC) {
+      v = (Real)a.facc[(int64_t)c * a.n + s];
+    } else if (sizeof(Real) == 4) {
+      v = (Real)fixed_sum(reinterpret_cast<const float*>(a.part), a.n, c, s, st);
+    } else {
+      Real acc = 0;
+      for (int slot = 0; slot < kSlots; ++slot) acc += a.part[((int64_t)slot * 3 + c) * a.n + s];
+      v = acc;
+    }
+    a.force_out[3 * i + c] = v;
+  }
+  if (a.flags & MD_DIAG_COUNTERS) a.paircount[i] = a.paircount[a.n + s];
+  if (st) atomicOr(&a.hdr->status, st);
+}
+
+__global__ __launch_bounds__(256) void k_energy(const double* epart, int64_t n_tasks,
+                                                double* out) {
+  __shared__ double s[256];
+  double acc = 0.0;
+  for (int64_t t = threadIdx.x; t < n_tasks; t += 256) acc += epart[t];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = s[0];
+}
+
+}  // namespace
+
+template <typename Real>
+hipError_t launch_finalize(const SysArgs<Real>& a, hipStream_t stream) {
+  if (a.n > 0) {
+    unsigned nb = (unsigned)((a.n + 255) / 256);
+    hipLaunchKernelGGL(k_finalize<Real>, dim3(nb), dim3(256), 0, stream, a);
+  }
+  hipLaunchKernelGGL(k_energy, dim3(1), dim3(256), 0, stream, (const double*)a.epart,
+                     a.n > 0 ? a.n_tasks : (int64_t)0, a.energy_out);
+  return hipGetLastError();
+}
+
+template hipError_t launch_finalize<float>(const SysArgs<float>&, hipStream_t);
+template hipError_t launch_finalize<double>(const SysArgs<double>&, hipStream_t);
+
+}  // namespace md

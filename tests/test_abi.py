@@ -1,0 +1,108 @@
+"""Host-side checks of the C ABI: the library loads and exports every declared
+entry point, the workspace and grid logic, and synchronous argument errors. No
+call here reaches the GPU."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1611_04474_amd import api
+from paper_1611_04474_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "mdforce.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(md_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 8
+    lib = api.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(api.EXPORTED)
+
+
+def test_status_strings():
+    assert api.status_string(0) == "ok"
+    assert "workspace" in api.status_string(-3)
+
+
+@pytest.mark.parametrize("make", [W.small_system, W.apoa1_system])
+def test_grid_matches_oracle_rule(make):
+    s = make()
+    for dp in (False, True):
+        lay = api.workspace_layout(s.params(), s.n, dp)
+        assert lay["dims"] == oracle.grid(s.params())
+        assert lay["total_bytes"] == api.workspace_bytes(s.params(), s.n, dp)
+
+
+def test_grid_margin_and_rejection():
+    p = W.small_system().params()
+    p2 = dict(p, box=(36.002, 36.0, 30.0))
+    assert api.workspace_layout(p2, 10)["dims"] == (2, 2, 2)
+    for bad in ((23.9, 30.0, 30.0), (24.0005, 30.0, 30.0)):
+        with pytest.raises(api.MDError) as e:
+            api.workspace_layout(dict(p, box=bad), 10)
+        assert e.value.code == -2
+
+
+def test_workspace_grows_with_atoms():
+    p = W.apoa1_system().params()
+    a = api.workspace_bytes(p, 1000)
+    b = api.workspace_bytes(p, 92224)
+    c = api.workspace_bytes(p, 92224, True)
+    assert 0 < a < b < c
+    assert b >= 27 * 3 * 4 * 92224
+
+
+def _call_f32(params, n=10, ws_bytes=1 << 20, ws_ptr=256, ptr=4096):
+    return api.forces_raw(params, n, ptr, ptr, ptr, ptr, ptr, ws_ptr, ws_bytes, 0)
+
+
+def test_argument_errors_are_synchronous():
+    base = W.small_system().params()
+    need = api.workspace_bytes(base, 10)
+    assert _call_f32(dict(base, r_switch=13.0), ws_bytes=need) == -1
+    assert _call_f32(dict(base, r_cut=-1.0), ws_bytes=need) == -1
+    assert _call_f32(dict(base, box=(20.0, 30.0, 30.0)), ws_bytes=need) == -2
+    assert _call_f32(dict(base, sigma=np.zeros(0), epsilon=np.zeros(0)), ws_bytes=need) == -1
+    assert _call_f32(dict(base, sigma=np.ones(65), epsilon=np.ones(65)), ws_bytes=need) == -6
+    assert _call_f32(dict(base, epsilon=-np.ones(8)), ws_bytes=need) == -1
+    assert _call_f32(dict(base, flags=1 << 20), ws_bytes=need) == -1
+    assert _call_f32(base, ws_bytes=need - 1) == -3
+    assert _call_f32(base, ws_bytes=need, ws_ptr=0) == -3
+    assert _call_f32(base, ws_bytes=need, ws_ptr=300) == -3      # not 256-aligned
+    assert _call_f32(base, n=-1, ws_bytes=need) == -1
+    assert _call_f32(base, ws_bytes=need, ptr=0) == -1
+    assert _call_f32(base, ws_bytes=need, ptr=4098) == -1         # misaligned float pointer
+    assert api.forces_raw(base, 10, 4096, 4096, 4096, 4096, 4096, 256, need, 0,
+                          double_precision=True) == -3             # f64 needs more workspace
+
+
+def test_batched_rejects_before_enqueue():
+    base = W.small_system().params()
+
+    class Fake:
+        def __init__(self, shape, ptr=4096):
+            self.shape = shape
+            self._p = ptr
+
+        def data_ptr(self):
+            return self._p
+
+        def numel(self):
+            return 64
+
+    sys_ok = dict(params=base, pos=Fake((10, 3)), types=Fake((10,)), charges=Fake((10,)),
+                  force=Fake((10, 3)), energy=Fake((1,)), workspace=Fake((64,), 256))
+    with pytest.raises(api.MDError) as e:
+        api.forces_batched([sys_ok], stream=0)
+    assert e.value.code == -3
