@@ -110,6 +110,20 @@ md_status md_forces_f32(const md_params* p, int64_t n_atoms, const float* d_pos,
                         const int32_t* d_type, const float* d_charge, float* d_force,
                         double* d_energy, void* d_ws, size_t ws_bytes, void* stream);
 
+/* Stages of one evaluation, for callers that time or interleave them:
+ *   MD_STAGE_BIN       clear counters, wrap positions, counting-sort binning;
+ *   MD_STAGE_PAIR      cutoff filter and force over all cell-pair tasks;
+ *   MD_STAGE_FINALIZE  per-atom sums in the caller's order and the total energy.
+ * Enqueuing the stages in this order on one workspace and stream gives exactly the
+ * result of md_forces_f32 with the same arguments; the arguments must not change
+ * between the stages of one evaluation. */
+enum { MD_STAGE_BIN = 1, MD_STAGE_PAIR = 2, MD_STAGE_FINALIZE = 4, MD_STAGE_ALL = 7 };
+
+md_status md_forces_f32_stages(const md_params* p, int64_t n_atoms, const float* d_pos,
+                               const int32_t* d_type, const float* d_charge, float* d_force,
+                               double* d_energy, void* d_ws, size_t ws_bytes,
+                               uint32_t stages, void* stream);
+
 /* Same as md_forces_f32 with float64 positions, charges, forces and pair
  * arithmetic throughout (per-atom sums in float64, fixed order). */
 md_status md_forces_f64(const md_params* p, int64_t n_atoms, const double* d_pos,
@@ -150,13 +164,16 @@ md_status md_read_diag(const void* d_ws, void* stream, uint64_t counters[3]);
  *   cell_start: int32 [n_cells+1], first sorted index of each cell
  *   perm:       int32 [n_atoms], original index of each sorted atom
  *   pair_count: int32 [n_atoms], partners inside the cutoff (MD_DIAG_COUNTERS),
- *               in the caller's atom order */
+ *               in the caller's atom order
+ *   energy_partials: float64 [n_energy_partials], per-workgroup energy sums */
 typedef struct {
   int32_t dims[3];
   int64_t n_cells;
   size_t cell_start;
   size_t perm;
   size_t pair_count;
+  size_t energy_partials;
+  int64_t n_energy_partials;
   size_t total_bytes;
 } md_layout;
 

@@ -53,7 +53,8 @@ class _System(C.Structure):
 
 class _Layout(C.Structure):
     _fields_ = [("dims", C.c_int32 * 3), ("n_cells", C.c_int64), ("cell_start", C.c_size_t),
-                ("perm", C.c_size_t), ("pair_count", C.c_size_t), ("total_bytes", C.c_size_t)]
+                ("perm", C.c_size_t), ("pair_count", C.c_size_t), ("energy_partials", C.c_size_t),
+                ("n_energy_partials", C.c_int64), ("total_bytes", C.c_size_t)]
 
 
 _lib = None
@@ -77,6 +78,9 @@ def lib():
             f = getattr(L, name)
             f.argtypes = [pp, C.c_int64, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
             f.restype = C.c_int
+        L.md_forces_f32_stages.argtypes = [pp, C.c_int64, vp, vp, vp, vp, vp, vp, C.c_size_t,
+                                           C.c_uint32, vp]
+        L.md_forces_f32_stages.restype = C.c_int
         L.md_forces_batched.argtypes = [C.POINTER(_System), C.c_int32, vp]
         L.md_forces_batched.restype = C.c_int
         L.md_read_device_status.argtypes = [vp, vp, C.POINTER(C.c_uint32)]
@@ -89,7 +93,8 @@ def lib():
     return _lib
 
 
-EXPORTED = ("md_workspace_bytes", "md_forces_f32", "md_forces_f64", "md_forces_batched",
+EXPORTED = ("md_workspace_bytes", "md_forces_f32", "md_forces_f32_stages", "md_forces_f64",
+            "md_forces_batched",
             "md_read_device_status", "md_read_diag", "md_workspace_layout", "md_status_string")
 
 
@@ -138,7 +143,9 @@ def workspace_layout(params, n_atoms, double_precision=False):
     if rc != MD_OK:
         raise MDError(rc, "md_workspace_layout")
     return dict(dims=tuple(out.dims), n_cells=int(out.n_cells), cell_start=int(out.cell_start),
-                perm=int(out.perm), pair_count=int(out.pair_count), total_bytes=int(out.total_bytes))
+                perm=int(out.perm), pair_count=int(out.pair_count),
+                energy_partials=int(out.energy_partials),
+                n_energy_partials=int(out.n_energy_partials), total_bytes=int(out.total_bytes))
 
 
 def _stream_ptr(stream):
@@ -217,6 +224,21 @@ def forces(params, pos, types, charges, *, flags=None, force=None, energy=None, 
     if rc != MD_OK:
         raise MDError(rc, "md_forces_f64" if dp else "md_forces_f32")
     return force, energy
+
+
+STAGE_BIN, STAGE_PAIR, STAGE_FINALIZE, STAGE_ALL = 1, 2, 4, 7
+
+
+def forces_stages(params, pos, types, charges, force, energy, workspace, stages, stream=None):
+    """Enqueues the given stages of one float32 evaluation (see md_forces_f32_stages)."""
+    p = _as_params(params)
+    rc = lib().md_forces_f32_stages(p.ref(), int(pos.shape[0]), C.c_void_p(pos.data_ptr()),
+                                    C.c_void_p(types.data_ptr()), C.c_void_p(charges.data_ptr()),
+                                    C.c_void_p(force.data_ptr()), C.c_void_p(energy.data_ptr()),
+                                    C.c_void_p(workspace.data_ptr()), int(workspace.numel()),
+                                    int(stages), _stream_ptr(stream))
+    if rc != MD_OK:
+        raise MDError(rc, "md_forces_f32_stages")
 
 
 def forces_raw(params, n, pos_ptr, type_ptr, q_ptr, force_ptr, energy_ptr, ws_ptr, ws_bytes,

@@ -97,6 +97,8 @@ SysArgs<Real> make_args(const md_params* p, const Plan& pl, int64_t n, const Rea
   a.epart = (double*)(b + pl.off_epart);
   a.lj = (Real*)(b + pl.off_lj);
   a.paircount = (int32_t*)(b + pl.off_paircount);
+  a.acc64 = (long long*)(b + pl.off_part);   // the full-shell path reuses the partial buffer
+  a.work = nullptr;
   a.n = n;
   a.n_cells = pl.n_cells;
   a.n_tasks = pl.n_tasks;
@@ -114,6 +116,7 @@ SysArgs<Real> make_args(const md_params* p, const Plan& pl, int64_t n, const Rea
   a.inv_sw = p->r_switch < p->r_cut ? (Real)(1.0 / (rc2 - rs2)) : Real(0);
   a.coulomb_k = (Real)p->coulomb_k;
   a.flags = p->flags;
+  a.full_shell = (sizeof(Real) == 4 && !(p->flags & MD_PAIR_PREDICATED)) ? 1 : 0;
   return a;
 }
 
@@ -126,7 +129,9 @@ template SysArgs<double> make_args<double>(const md_params*, const Plan&, int64_
 template <typename Real>
 static md_status forces_impl(const md_params* p, int64_t n, const Real* pos,
                              const int32_t* type, const Real* q, Real* force, double* energy,
-                             void* ws, size_t ws_bytes, void* stream) {
+                             void* ws, size_t ws_bytes, void* stream,
+                             uint32_t stages = MD_STAGE_ALL) {
+  if (stages & ~(uint32_t)MD_STAGE_ALL) return MD_ERR_INVALID_ARG;
   Plan pl;
   md_status s = make_plan(p, n, (int)sizeof(Real), &pl);
   if (s != MD_OK) return s;
@@ -140,9 +145,11 @@ static md_status forces_impl(const md_params* p, int64_t n, const Real* pos,
   if (!ws || ((uintptr_t)ws & 255) || ws_bytes < pl.total) return MD_ERR_WORKSPACE;
   SysArgs<Real> a = make_args<Real>(p, pl, n, pos, type, q, force, energy, ws);
   hipStream_t st = (hipStream_t)stream;
-  if (launch_binning<Real>(a, p->sigma, p->epsilon, st) != hipSuccess) return MD_ERR_HIP;
-  if (launch_pair<Real>(a, st) != hipSuccess) return MD_ERR_HIP;
-  if (launch_finalize<Real>(a, st) != hipSuccess) return MD_ERR_HIP;
+  if ((stages & MD_STAGE_BIN) && launch_binning<Real>(a, p->sigma, p->epsilon, st) != hipSuccess)
+    return MD_ERR_HIP;
+  if ((stages & MD_STAGE_PAIR) && launch_pair<Real>(a, st) != hipSuccess) return MD_ERR_HIP;
+  if ((stages & MD_STAGE_FINALIZE) && launch_finalize<Real>(a, st) != hipSuccess)
+    return MD_ERR_HIP;
   return MD_OK;
 }
 
@@ -167,6 +174,10 @@ md_status md_workspace_layout(const md_params* p, int64_t n_atoms, int double_pr
   out->cell_start = pl.off_start;
   out->perm = pl.off_perm;
   out->pair_count = pl.off_paircount;
+  out->energy_partials = pl.off_epart;
+  out->n_energy_partials =
+      (!double_precision && !(p->flags & MD_PAIR_PREDICATED)) ? pl.n_cells * md::kFsSplit
+                                                             : pl.n_tasks;
   out->total_bytes = pl.total;
   return MD_OK;
 }
@@ -176,6 +187,14 @@ md_status md_forces_f32(const md_params* p, int64_t n_atoms, const float* d_pos,
                         double* d_energy, void* d_ws, size_t ws_bytes, void* stream) {
   return md::forces_impl<float>(p, n_atoms, d_pos, d_type, d_charge, d_force, d_energy, d_ws,
                                 ws_bytes, stream);
+}
+
+md_status md_forces_f32_stages(const md_params* p, int64_t n_atoms, const float* d_pos,
+                               const int32_t* d_type, const float* d_charge, float* d_force,
+                               double* d_energy, void* d_ws, size_t ws_bytes, uint32_t stages,
+                               void* stream) {
+  return md::forces_impl<float>(p, n_atoms, d_pos, d_type, d_charge, d_force, d_energy, d_ws,
+                                ws_bytes, stream, stages);
 }
 
 md_status md_forces_f64(const md_params* p, int64_t n_atoms, const double* d_pos,

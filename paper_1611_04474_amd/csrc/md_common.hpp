@@ -13,7 +13,8 @@ constexpr int kMaxTypes = 64;
 constexpr int kTasksPerCell = 14;    // home cell + 13 forward neighbours (half shell)
 constexpr int kSlots = 27;           // partial-force slots per atom: 14 as home, 13 as neighbour
 constexpr int kTile = 256;           // atoms of one cell staged in LDS at a time
-constexpr int kPairThreads = 256;    // threads of one pair workgroup (4 waves)
+constexpr int kPairThreads = 256;    // threads of one half-shell pair workgroup (4 waves)
+constexpr int kFsSplit = 2;          // full-shell workgroups per home cell
 constexpr int64_t kMaxCells = 1 << 24;
 constexpr int64_t kMaxAtoms = (int64_t)1 << 30;
 
@@ -69,7 +70,9 @@ struct SysArgs {
   float* facc;                 // [3][n]
   double* epart;               // [n_tasks]
   Real* lj;                    // [n_types^2][2] (c12, c6)
-  int32_t* paircount;          // [n] sorted order during the pass, caller order after
+  int32_t* paircount;          // [2][n]: caller order (after finalize), sorted order (pass)
+  long long* acc64;            // [3][n] per-atom fixed-point sums (full-shell path)
+  unsigned int* work;          // [8] per-XCD work counters of the full-shell kernel
   // scalars
   int64_t n, n_cells, n_tasks;
   int nx, ny, nz, n_types;
@@ -78,6 +81,7 @@ struct SysArgs {
   Real rc2, rs2, inv_sw;       // inv_sw = 1/(rc2 - rs2), 0 when switching is off
   Real coulomb_k;
   uint32_t flags;
+  int full_shell;              // 1: per-atom sums come from the full-shell pair kernel
 };
 
 template <typename Real>
@@ -93,5 +97,7 @@ template <typename Real>
 hipError_t launch_pair(const SysArgs<Real>& a, hipStream_t stream);
 template <typename Real>
 hipError_t launch_finalize(const SysArgs<Real>& a, hipStream_t stream);
+hipError_t launch_pair_fs(const SysArgs<float>& a, hipStream_t stream);
+size_t pair_fs_lds_bytes(int n_types);
 
 }  // namespace md

@@ -45,6 +45,8 @@ __global__ void k_finalize(SysArgs<Real> a) {
     Real v;
     if (a.flags & MD_ACCUM_F32_ATOMIC) {
       v = (Real)a.facc[(int64_t)c * a.n + s];
+    } else if (a.full_shell) {
+      v = (Real)(__ll2float_rn(a.acc64[(int64_t)c * a.n + s]) * 2.3283064365386963e-10f);
     } else if (sizeof(Real) == 4) {
       v = (Real)fixed_sum(reinterpret_cast<const float*>(a.part), a.n, c, s, st);
     } else {
@@ -59,7 +61,8 @@ __global__ void k_finalize(SysArgs<Real> a) {
 }
 
 __global__ __launch_bounds__(256) void k_energy(const double* epart, int64_t n_tasks,
-                                                double* out) {
+                                                double* out, WsHeader* hdr, int halve_diag) {
+  if (halve_diag && threadIdx.x < 3) hdr->diag[threadIdx.x] /= 2;
   __shared__ double s[256];
   double acc = 0.0;
   for (int64_t t = threadIdx.x; t < n_tasks; t += 256) acc += epart[t];
@@ -80,8 +83,10 @@ hipError_t launch_finalize(const SysArgs<Real>& a, hipStream_t stream) {
     unsigned nb = (unsigned)((a.n + 255) / 256);
     hipLaunchKernelGGL(k_finalize<Real>, dim3(nb), dim3(256), 0, stream, a);
   }
+  const int64_t n_part = a.full_shell ? a.n_cells * kFsSplit : a.n_tasks;
+  const int halve = (a.full_shell && (a.flags & MD_DIAG_COUNTERS) && a.n > 0) ? 1 : 0;
   hipLaunchKernelGGL(k_energy, dim3(1), dim3(256), 0, stream, (const double*)a.epart,
-                     a.n > 0 ? a.n_tasks : (int64_t)0, a.energy_out);
+                     a.n > 0 ? n_part : (int64_t)0, a.energy_out, a.hdr, halve);
   return hipGetLastError();
 }
 

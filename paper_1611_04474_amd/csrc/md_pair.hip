@@ -317,6 +317,9 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_predicated(SysArgs<Real> 
 template <typename Real>
 hipError_t launch_pair(const SysArgs<Real>& a, hipStream_t stream) {
   if (a.n == 0) return hipSuccess;
+  if constexpr (sizeof(Real) == 4) {
+    if (a.full_shell) return launch_pair_fs(a, stream);
+  }
   const int64_t blocks = 8 * ((a.n_tasks + 7) / 8);
   const size_t shmem = sizeof(Real) * 2 * a.n_types * a.n_types;
   const bool swc = !(a.flags & MD_COULOMB_TRUNCATED);
