@@ -28,9 +28,11 @@ namespace {
 constexpr int kNW = 16;             // waves per workgroup
 constexpr int kThreads = 64 * kNW;
 constexpr int kQ = 4;               // home atoms filtered together by one wave, one FIFO each
-constexpr int kFifo = 128;          // FIFO entries: (neighbour type << 16) | neighbour index
+constexpr int kDrain = 2;           // force batches of 64 drained together from a full FIFO
+constexpr int kFifo = 64 * (kDrain + 1);  // FIFO entries: (neighbour type << 16) | index
 constexpr int kSplit = kFsSplit;    // workgroups per home cell
 constexpr int kLdsBytes = 160 * 1024;
+constexpr float kMargin = 0.05f;    // A^2 added to rc^2 by the expanded-form prefilter
 constexpr float kFar = 1.0e18f;     // |coordinate| that fails every cutoff test; absent home
                                     // atoms use +kFar, absent neighbours -kFar
 
@@ -50,7 +52,8 @@ struct Img {
 };
 
 struct StaticLds {
-  uint32_t fifo[kNW][kQ][kFifo];    // per home atom: passing neighbours
+  uint32_t fifo[kNW][kQ * kFifo + 64];  // per home atom: passing neighbours; last 64: lanes
+                                        // that did not pass write here (never read)
   Img img[27];
   int grp_begin[9];                 // neighbour-list position where group g starts
   int next;                         // next group of home atoms to hand out
@@ -112,13 +115,22 @@ __device__ inline float pair_f(float u, float c12, float c6, float qq, float rs2
   return (S * flj + ec) * r2 + g * elj;
 }
 
+// v = bit `lane` of mask ? a : b, as one v_cndmask on the mask (keeps the compiler from
+// turning the select into exec-masked branches)
+__device__ inline int select_by_mask(unsigned long long mask, int a, int b) {
+  int r;
+  __asm__ volatile("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(b), "v"(a), "s"(mask));
+  return r;
+}
+
 __device__ inline int64_t xcd_unit(int64_t b, int64_t n_units) {
   int64_t per = (n_units + 7) / 8;
   return (b % 8) * per + b / 8;
 }
 
 template <bool kSwitchCoulomb>
-__global__ __launch_bounds__(kThreads) void k_pair_fs(SysArgs<float> a, int cap) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
+void k_pair_fs(SysArgs<float> a, int cap) {
   // dynamic LDS: neighbour (x,y,z,q) [cap] | neighbour type [cap] | LJ table [2 nt^2]
   extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
   float4* sJ = reinterpret_cast<float4*>(s_dyn);
@@ -146,38 +158,39 @@ __global__ __launch_bounds__(kThreads) void k_pair_fs(SysArgs<float> a, int cap)
   const int ib0 = (int)(((int64_t)half * nA) / kSplit);
   const int ib1 = (int)(((int64_t)(half + 1) * nA) / kSplit);
 
-  if (tid == 0) {
+  // image table: one lane per image (independent loads), then the group order
+  if (tid < 27) {
     const int nd[3] = {a.nx, a.ny, a.nz};
     const int ac[3] = {(int)(cellA % a.nx), (int)((cellA / a.nx) % a.ny),
                        (int)(cellA / ((int64_t)a.nx * a.ny))};
-    for (int m = 0; m < 27; ++m) {
-      int b[3], grp = 0, jsh = 0;
-      for (int d = 0; d < 3; ++d) {
-        b[d] = ac[d] + c_img[m][d];
-        if (b[d] >= nd[d]) {
-          b[d] -= nd[d];
-          grp |= 1 << d;
-        } else if (b[d] < 0) {
-          b[d] += nd[d];
-          jsh |= 1 << d;
-        }
+    int b[3], grp = 0, jsh = 0;
+    for (int d = 0; d < 3; ++d) {
+      b[d] = ac[d] + c_img[tid][d];
+      if (b[d] >= nd[d]) {
+        b[d] -= nd[d];
+        grp |= 1 << d;
+      } else if (b[d] < 0) {
+        b[d] += nd[d];
+        jsh |= 1 << d;
       }
-      const int64_t cb = ((int64_t)b[2] * a.ny + b[1]) * a.nx + b[0];
-      S.img[m].start = a.start[cb];
-      S.img[m].count = a.start[cb + 1] - a.start[cb];
-      S.img[m].grp = grp;
-      S.img[m].jsh = jsh;
     }
-    int run = 0;
-    for (int g = 0; g < 8; ++g) {   // images ordered by group, the home image first
-      S.grp_begin[g] = run;
-      for (int m = 0; m < 27; ++m)
-        if (S.img[m].grp == g) {
-          S.img[m].off = run;
-          run += S.img[m].count;
-        }
+    const int64_t cb = ((int64_t)b[2] * a.ny + b[1]) * a.nx + b[0];
+    const int st0 = a.start[cb], st1 = a.start[cb + 1];
+    S.img[tid].start = st0;
+    S.img[tid].count = st1 - st0;
+    S.img[tid].grp = grp;
+    S.img[tid].jsh = jsh;
+    // position in the neighbour list: images ordered by group, then by image index
+    // (the home image, group 0, first)
+    int off = 0, gb = 0;
+    for (int mm = 0; mm < 27; ++mm) {
+      const int gm = __builtin_amdgcn_readlane(grp, mm);
+      const int cm = __builtin_amdgcn_readlane(st1 - st0, mm);
+      off += (gm < grp || (gm == grp && mm < tid)) ? cm : 0;
+      gb += (tid < 9 && gm < tid) ? cm : 0;      // lane g < 9: start of group g
     }
-    S.grp_begin[8] = run;
+    S.img[tid].off = off;
+    if (tid < 9) S.grp_begin[tid] = gb;
   }
   __syncthreads();
 
@@ -186,23 +199,36 @@ __global__ __launch_bounds__(kThreads) void k_pair_fs(SysArgs<float> a, int cap)
   double e_wave = 0.0;
   unsigned long long pass_count = 0;
   uint32_t st = 0;
-  uint32_t* fifo = &S.fifo[w][0][0];
+  uint32_t* fifo = &S.fifo[w][0];
 
   for (int P0 = 0; P0 < total; P0 += cap) {
     const int P1 = min(total, P0 + cap);
-    for (int m = 0; m < 27; ++m) {   // stage the neighbour-list slice [P0, P1)
+    // stage the neighbour-list slice [P0, P1): wave w copies images w and w + 16, issuing
+    // all loads of an image (up to 4 x 64 atoms per round) before its LDS stores
+    for (int m = w; m < 27; m += kNW) {
       const Img im = S.img[m];
       const int lo = max(im.off, P0), hi = min(im.off + im.count, P1);
-      for (int e = lo + tid; e < hi; e += kThreads) {
-        const int src = im.start + (e - im.off);
-        const P4<float> p = a.pos[src];
-        float4 v;
-        v.x = (im.jsh & 1) ? p.x - L0 : p.x;
-        v.y = (im.jsh & 2) ? p.y - L1 : p.y;
-        v.z = (im.jsh & 4) ? p.z - L2 : p.z;
-        v.w = p.w;
-        sJ[e - P0] = v;
-        sT[e - P0] = (uint8_t)a.type[src];
+      for (int e0 = lo; e0 < hi; e0 += 4 * 64) {
+        P4<float> v[4];
+        int tv[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int e = e0 + 64 * r + lane;
+          const int src = im.start + (min(e, hi - 1) - im.off);
+          v[r] = a.pos[src];
+          tv[r] = a.type[src];
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int e = e0 + 64 * r + lane;
+          if (e < hi) {
+            const float x = (im.jsh & 1) ? v[r].x - L0 : v[r].x;
+            const float y = (im.jsh & 2) ? v[r].y - L1 : v[r].y;
+            const float z = (im.jsh & 4) ? v[r].z - L2 : v[r].z;
+            sJ[e - P0] = make_float4(x, y, z, v[r].w);
+            sT[e - P0] = (uint8_t)tv[r];
+          }
+        }
       }
     }
     if (tid == 0) S.next = 0;
@@ -240,33 +266,58 @@ __global__ __launch_bounds__(kThreads) void k_pair_fs(SysArgs<float> a, int cap)
         const int r0 = G0 - P0, r1 = G1 - P0;
         // home coordinates in this group's frame: subtract L where the images lie at +L
         float xs[kQ], ys[kQ], zs[kQ];
+        // prefilter terms relative to the origin o (the home cell's first atom, this frame):
+        // |x_i - x_j|^2 = c_i + c_j - 2 r_i . r_j with r = x - o, c = |r|^2
+        float ax[kQ], ay[kQ], az[kQ], thr[kQ];
+        const float ox = xi[0] - ((g & 1) ? L0 : 0.f), oy = yi[0] - ((g & 2) ? L1 : 0.f),
+                    oz = zi[0] - ((g & 4) ? L2 : 0.f);
 #pragma unroll
         for (int k = 0; k < kQ; ++k) {
           xs[k] = (g & 1) ? xi[k] - L0 : xi[k];
           ys[k] = (g & 2) ? yi[k] - L1 : yi[k];
           zs[k] = (g & 4) ? zi[k] - L2 : zi[k];
+          const float rx = xs[k] - ox, ry = ys[k] - oy, rz = zs[k] - oz;
+          ax[k] = -2.f * rx;
+          ay[k] = -2.f * ry;
+          az[k] = -2.f * rz;
+          thr[k] = (rc2 + kMargin) - fmaf(rz, rz, fmaf(ry, ry, rx * rx));
         }
 
-        // one dense force pass over the first c entries of FIFO k
+        // dense force passes over the first c entries of FIFO k (c <= 64 * kDrain): the exact
+        // cutoff test (u < rc^2; u > 0 drops the home atom itself) and the force. All LDS
+        // reads of the kDrain batches are issued before any arithmetic.
         auto force = [&](int k, int c) __attribute__((always_inline)) {
-          const bool lv = lane < c;
-          const uint32_t ent = fifo[k * kFifo + lane];
-          const int jj = lv ? (int)(ent & 0xffffu) : r0;
-          const int tj = lv ? (int)(ent >> 16) : 0;
-          const float4 pj = sJ[jj];
-          const int e2 = 2 * (ti[k] + tj);
-          const float c12 = sLJ[e2], c6 = sLJ[e2 + 1];
-          const float dx = xs[k] - pj.x, dy = ys[k] - pj.y, dz = zs[k] - pj.z;
-          const float u = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-          float e;
-          float f = pair_f<kSwitchCoulomb>(u, c12, c6, kq[k] * pj.w, rs2, inv_sw, sw12, e);
-          f = lv ? f : 0.f;
-          e = lv ? e : 0.f;
-          fx[k] = fmaf(f, dx, fx[k]);
-          fy[k] = fmaf(f, dy, fy[k]);
-          fz[k] = fmaf(f, dz, fz[k]);
-          e_lane += e;
-          cnt[k] += c;
+          uint32_t ent[kDrain];
+          float4 pj[kDrain];
+          float c12[kDrain], c6[kDrain];
+#pragma unroll
+          for (int b = 0; b < kDrain; ++b) ent[b] = fifo[k * kFifo + 64 * b + lane];
+#pragma unroll
+          for (int b = 0; b < kDrain; ++b) {
+            const bool in = 64 * b + lane < c;
+            const int jj = in ? (int)(ent[b] & 0xffffu) : r0;
+            const int tj = in ? (int)(ent[b] >> 16) : 0;
+            pj[b] = sJ[jj];
+            const int e2 = 2 * (ti[k] + tj);
+            c12[b] = sLJ[e2];
+            c6[b] = sLJ[e2 + 1];
+          }
+#pragma unroll
+          for (int b = 0; b < kDrain; ++b) {
+            const bool in = 64 * b + lane < c;
+            const float dx = xs[k] - pj[b].x, dy = ys[k] - pj[b].y, dz = zs[k] - pj[b].z;
+            const float u = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+            const bool lv = in && u < rc2 && u > 0.f;
+            float e;
+            float f = pair_f<kSwitchCoulomb>(u, c12[b], c6[b], kq[k] * pj[b].w, rs2, inv_sw, sw12, e);
+            f = lv ? f : 0.f;
+            e = lv ? e : 0.f;
+            fx[k] = fmaf(f, dx, fx[k]);
+            fy[k] = fmaf(f, dy, fy[k]);
+            fz[k] = fmaf(f, dz, fz[k]);
+            e_lane += e;
+            cnt[k] += __builtin_popcountll(__builtin_amdgcn_ballot_w64(lv));
+          }
           // drop the first c entries; the remainder (fewer than 64) moves to the front
           const int rem = tl[k] - c;
           if (rem > 0) {
@@ -277,44 +328,52 @@ __global__ __launch_bounds__(kThreads) void k_pair_fs(SysArgs<float> a, int cap)
           tl[k] = rem;
         };
 
+        // software pipeline: the next batch's neighbour is loaded one batch ahead
+        int jr = min(r0 + lane, r1 - 1);
+        float4 pn = sJ[jr];
+        uint32_t cn = ((uint32_t)sT[jr] << 16) | (uint32_t)jr;
         for (int jb = r0; jb < r1; jb += 64) {
           const int jv = jb + lane;
           const bool last = jb + 64 >= r1;
-          const int jr = jv < r1 ? jv : r1 - 1;
-          float4 pj = sJ[jr];
-          const uint32_t code = ((uint32_t)sT[jr] << 16) | (uint32_t)jr;
-          if (last) pj.x = jv < r1 ? pj.x : -kFar;   // opposite sign to the absent-home sentinel
-          float u[kQ];
-#pragma unroll
-          for (int k = 0; k < kQ; ++k) {
-            const float dx = xs[k] - pj.x, dy = ys[k] - pj.y, dz = zs[k] - pj.z;
-            u[k] = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+          float4 pj = pn;
+          const uint32_t code = cn;
+          if (!last) {
+            const int jn = min(jv + 64, r1 - 1);
+            pn = sJ[jn];
+            cn = ((uint32_t)sT[jn] << 16) | (uint32_t)jn;
           }
+          if (last) pj.x = jv < r1 ? pj.x : -kFar;   // opposite sign to the absent-home sentinel
+          const float rx = pj.x - ox, ry = pj.y - oy, rz = pj.z - oz;
+          const float cj = fmaf(rz, rz, fmaf(ry, ry, rx * rx));
+          float t[kQ];
+#pragma unroll
+          for (int k = 0; k < kQ; ++k) t[k] = fmaf(ax[k], rx, cj);
+#pragma unroll
+          for (int k = 0; k < kQ; ++k) t[k] = fmaf(ay[k], ry, t[k]);
+#pragma unroll
+          for (int k = 0; k < kQ; ++k) t[k] = fmaf(az[k], rz, t[k]);
           unsigned long long m[kQ];
 #pragma unroll
-          for (int k = 0; k < kQ; ++k) m[k] = __builtin_amdgcn_ballot_w64(u[k] < rc2);
-          // the home atoms sit in the home image: drop each from its own mask
-          const int self0 = ib - P0 - jb;
-          if (g == 0 && self0 > -kQ && self0 < 64) {
-#pragma unroll
-            for (int k = 0; k < kQ; ++k) {
-              const int sl = self0 + k;
-              if (sl >= 0 && sl < 64) m[k] &= ~(1ull << sl);
-            }
-          }
+          for (int k = 0; k < kQ; ++k) m[k] = __builtin_amdgcn_ballot_w64(t[k] < thr[k]);
+          // every lane writes: passing lanes to their FIFO slot, the others to their own
+          // dump slot, so no exec-mask changes are needed
+          int idx[kQ];
 #pragma unroll
           for (int k = 0; k < kQ; ++k) {
-            const unsigned rank = __builtin_amdgcn_mbcnt_hi(
+            const int rank = (int)__builtin_amdgcn_mbcnt_hi(
                 (unsigned)(m[k] >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m[k], 0u));
-            if (__builtin_amdgcn_inverse_ballot_w64(m[k])) fifo[k * kFifo + tl[k] + (int)rank] = code;
-            tl[k] += __builtin_popcountll(m[k]);
+            idx[k] = select_by_mask(m[k], k * kFifo + tl[k] + rank, kQ * kFifo + lane);
           }
-          // drain full FIFOs; on the group's last batch drain everything (the home side
-          // changes frame in the next group)
-          const int thr = last ? 1 : 64;
+#pragma unroll
+          for (int k = 0; k < kQ; ++k) fifo[idx[k]] = code;
+#pragma unroll
+          for (int k = 0; k < kQ; ++k) tl[k] += __builtin_popcountll(m[k]);
+          // drain full FIFOs (kDrain batches at a time); on the group's last batch drain
+          // everything (the home side changes frame in the next group)
+          const int thr_n = last ? 1 : 64 * kDrain;
 #pragma unroll
           for (int k = 0; k < kQ; ++k) {
-            while (tl[k] >= thr) force(k, tl[k] < 64 ? tl[k] : 64);
+            while (tl[k] >= thr_n) force(k, tl[k] < 64 * kDrain ? tl[k] : 64 * kDrain);
           }
         }
       }
