@@ -69,7 +69,7 @@ def main():
     # candidate and pair counts of this workload, from the kernel's own counters
     api.forces(P.with_flags(flags | api.DIAG_COUNTERS), pos, typ, q, force=force, energy=energy,
                workspace=ws)
-    n_cand, n_filter, n_pairs = api.read_diag(ws)
+    n_cand, n_filter, n_pairs, n_slots = api.read_diag(ws)
     flop_per_launch = FLOP_PER_CANDIDATE * n_cand + FLOP_PER_PAIR * n_pairs
 
     def step(evs=None):

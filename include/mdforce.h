@@ -154,10 +154,18 @@ md_status md_forces_batched(const md_system* systems, int32_t n_sys, void* strea
  * Synchronises `stream`. */
 md_status md_read_device_status(const void* d_ws, void* stream, uint32_t* bits);
 
-/* Diagnostic counters of the last call with MD_DIAG_COUNTERS on this workspace:
- * [0] candidate pairs tested, [1] pairs passing the filter stage, [2] pairs inside
- * the cutoff. Synchronises `stream`. */
-md_status md_read_diag(const void* d_ws, void* stream, uint64_t counters[3]);
+/* Diagnostic counters of the last call with MD_DIAG_COUNTERS on this workspace, all
+ * per unique pair:
+ *   [0] candidate pairs of the cell list (every pair of atoms in neighbouring cells,
+ *       Algorithm 1), the work a filter that tests them all would do;
+ *   [1] pairs passing the filter stage (the conservative prefilter of the compacted
+ *       kernel, the cutoff test itself for the predicated one);
+ *   [2] pairs inside the cutoff;
+ *   [3] candidate pairs the filter stage actually examined (the compacted kernel skips
+ *       neighbours outside an x-window of its home atoms; equal to [0] otherwise).
+ * For the float32 compacted kernel, which sees every pair from both atoms, [1] and [3]
+ * are half of its per-atom counts. Synchronises `stream`. */
+md_status md_read_diag(const void* d_ws, void* stream, uint64_t counters[4]);
 
 /* Layout of the workspace, for inspection of intermediate results. Offsets are in
  * bytes from the workspace start.

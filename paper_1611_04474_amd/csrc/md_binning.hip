@@ -11,8 +11,11 @@
 //                precision), checks it, computes the cell and takes a slot with an atomic;
 //   k_scan       one workgroup: exclusive prefix sum of the counts -> cell_start;
 //   k_scatter    writes each atom's index at cell_start + slot (arbitrary order in a cell);
-//   k_cell_sort  one workgroup per cell: orders the cell's atoms by original index (so
-//                every later sum runs in a reproducible order) and writes the sorted arrays.
+//   k_cell_sort  one workgroup per cell: orders the cell's atoms by (wrapped x, original
+//                index) -- a total order, so every later sum runs in a reproducible order,
+//                and a row of cells along x is sorted in x, which lets the pair kernel
+//                bound each home atom's candidates by an x-window -- and writes the sorted
+//                arrays.
 #include "md_common.hpp"
 
 namespace md {
@@ -68,6 +71,7 @@ __global__ void k_setup(SysArgs<Real> a, TypeTable tt) {
     a.hdr->diag[0] = 0;
     a.hdr->diag[1] = 0;
     a.hdr->diag[2] = 0;
+    a.hdr->diag[3] = 0;
   }
 }
 
@@ -135,35 +139,47 @@ __global__ void k_scatter(SysArgs<Real> a) {
   a.unsorted[a.start[a.cell[i]] + a.rank[i]] = (int32_t)i;
 }
 
-// One workgroup per cell. Each member's position in the cell is the number of
-// members with a smaller original index, counted over LDS chunks of the member list,
-// so any cell occupancy is handled.
+// One workgroup per cell. Each member's position in the cell is the number of members
+// that precede it in (wrapped x, original index) order, counted over LDS chunks of the
+// member list, so any cell occupancy is handled.
 template <typename Real>
 __global__ __launch_bounds__(256) void k_cell_sort(SysArgs<Real> a) {
   constexpr int kChunk = 1024;
+  constexpr int kPer = kChunk / 256;
   __shared__ int32_t s_idx[kChunk];
+  __shared__ Real s_x[kChunk];
   int64_t c = blockIdx.x;
   int32_t s0 = a.start[c];
   int32_t m = a.start[c + 1] - s0;
   for (int32_t a0 = 0; a0 < m; a0 += kChunk) {
-    int32_t my_idx[kChunk / 256];
-    int32_t my_rank[kChunk / 256];
-    for (int k = 0; k < kChunk / 256; ++k) {
+    int32_t my_idx[kPer];
+    Real my_x[kPer];
+    int32_t my_rank[kPer];
+    for (int k = 0; k < kPer; ++k) {
       int32_t e = a0 + (int32_t)threadIdx.x + 256 * k;
       my_idx[k] = e < m ? a.unsorted[s0 + e] : -1;
+      uint32_t st = 0;
+      my_x[k] = my_idx[k] >= 0 ? wrap_coord(a.pos_in[3 * (int64_t)my_idx[k]], a.L[0], st) : Real(0);
       my_rank[k] = 0;
     }
     for (int32_t b0 = 0; b0 < m; b0 += kChunk) {
       int32_t mb = min(kChunk, m - b0);
       __syncthreads();
-      for (int32_t e = threadIdx.x; e < mb; e += 256) s_idx[e] = a.unsorted[s0 + b0 + e];
+      for (int32_t e = threadIdx.x; e < mb; e += 256) {
+        const int32_t i = a.unsorted[s0 + b0 + e];
+        uint32_t st = 0;
+        s_idx[e] = i;
+        s_x[e] = wrap_coord(a.pos_in[3 * (int64_t)i], a.L[0], st);
+      }
       __syncthreads();
       for (int32_t e = 0; e < mb; ++e) {
-        int32_t v = s_idx[e];
-        for (int k = 0; k < kChunk / 256; ++k) my_rank[k] += (v < my_idx[k]) ? 1 : 0;
+        const int32_t v = s_idx[e];
+        const Real xv = s_x[e];
+        for (int k = 0; k < kPer; ++k)
+          my_rank[k] += (xv < my_x[k] || (xv == my_x[k] && v < my_idx[k])) ? 1 : 0;
       }
     }
-    for (int k = 0; k < kChunk / 256; ++k) {
+    for (int k = 0; k < kPer; ++k) {
       int32_t i = my_idx[k];
       if (i < 0) continue;
       uint32_t st = 0;

@@ -22,8 +22,8 @@ constexpr int64_t kMaxAtoms = (int64_t)1 << 30;
 struct WsHeader {
   uint32_t status;
   uint32_t pad0;
-  unsigned long long diag[3];   // candidates, filter passes, cutoff passes
-  uint32_t pad1[56];
+  unsigned long long diag[4];   // candidates, filter passes, cutoff passes, filtered slots
+  uint32_t pad1[54];
 };
 static_assert(sizeof(WsHeader) == 256, "header size");
 

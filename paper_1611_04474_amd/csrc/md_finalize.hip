@@ -62,7 +62,7 @@ __global__ void k_finalize(SysArgs<Real> a) {
 
 __global__ __launch_bounds__(256) void k_energy(const double* epart, int64_t n_tasks,
                                                 double* out, WsHeader* hdr, int halve_diag) {
-  if (halve_diag && threadIdx.x < 3) hdr->diag[threadIdx.x] /= 2;
+  if (halve_diag && threadIdx.x < 4) hdr->diag[threadIdx.x] /= 2;
   __shared__ double s[256];
   double acc = 0.0;
   for (int64_t t = threadIdx.x; t < n_tasks; t += 256) acc += epart[t];

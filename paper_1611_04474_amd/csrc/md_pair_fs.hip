@@ -2,24 +2,28 @@
 // -- foreach home cell, foreach of its 27 neighbour cells, foreach home atom,
 // foreach neighbour atom, test the cutoff and accumulate the force on the home atom --
 // with the dynamic data flow of the enhanced design (Section 4.2, Fig. 4, Algorithm 3):
-// many cutoff filters feed one force stage through FIFOs, and the force stage only
+// several cutoff filters feed one force stage through FIFOs, and the force stage only
 // ever works on pairs that passed.
 //
-// One workgroup (8 waves) takes half of the atoms of one home cell. It stages the
-// atoms of the 27 neighbour cell images in LDS (periodic images shifted exactly:
-// the side lying in the last cell of an axis subtracts L, Sterbenz-exact), then each
-// wave takes groups of 8 home atoms:
-//   filter  -- for every 64 neighbour atoms (one per lane) and each of the 8 home
-//              atoms: the squared distance, the strict test u < rc^2, a wave ballot,
-//              and a prefix count (mbcnt) that appends the passing neighbour indices
-//              to that home atom's FIFO in LDS (8 "distance PEs" per wave);
-//   force   -- whenever a FIFO holds 64 entries, one dense pass over them with every
-//              lane busy (the "force PE"), summing the force on the home atom in
-//              registers.
+// One workgroup (16 waves) takes one home cell. It stages the atoms of the 27
+// neighbour-cell images in LDS, periodic images shifted exactly (the side lying in the
+// last cell of an axis subtracts L, which is Sterbenz-exact). Cells are sorted by x, so
+// the images of one (dy, dz) row, laid out in x order, form one x-sorted "segment".
+// Each wave takes groups of kQ home atoms (consecutive in x) and, per segment, only the
+// slice whose x lies within r_cut of the group, found by a binary search (one lane
+// per segment):
+//   filter  -- for every 64 neighbour atoms (one per lane) and each of the kQ home
+//              atoms: a conservative expanded-form distance test (three FMAs against a
+//              precomputed |r_j - o|^2), a wave ballot, and a prefix count (mbcnt) that
+//              appends the passing neighbour index to that home atom's FIFO in LDS
+//              (kQ "distance PEs" per wave);
+//   force   -- whenever a FIFO holds kDrain x 64 entries, dense passes over them with
+//              every lane busy (the "force PE"): the exact distance, the strict test
+//              u < rc^2, and the force summed on the home atom in registers.
 // Each home atom is owned by one wave, so no atomics are needed and every sum runs in
-// a fixed order. At the end the 64 lane partials are added per 16-lane row in a
-// fixed DPP order and the four row sums in 64-bit fixed point (2^-32 kcal/mol/A),
-// exactly. Every pair is evaluated from both of its atoms, as in Algorithm 1.
+// a fixed order. At the end the 64 lane partials are added per 16-lane row in a fixed
+// DPP order and the four row sums in 64-bit fixed point (2^-32 kcal/mol/A), exactly.
+// Every pair is evaluated from both of its atoms, as in Algorithm 1.
 #include "md_common.hpp"
 
 namespace md {
@@ -29,14 +33,15 @@ constexpr int kNW = 16;             // waves per workgroup
 constexpr int kThreads = 64 * kNW;
 constexpr int kQ = 4;               // home atoms filtered together by one wave, one FIFO each
 constexpr int kDrain = 2;           // force batches of 64 drained together from a full FIFO
-constexpr int kFifo = 64 * (kDrain + 1);  // FIFO entries: (neighbour type << 16) | index
-constexpr int kSplit = kFsSplit;    // workgroups per home cell
+constexpr int kFifo = 64 * (kDrain + 1);   // FIFO entries (uint16 neighbour index) per atom
+constexpr int kWaveFifo = kQ * kFifo + 64; // + one dump slot per lane (written, never read)
+constexpr int kMaxSeg = 18;         // 9 (dy, dz) rows, each split at most once by an x wrap
 constexpr int kLdsBytes = 160 * 1024;
 constexpr float kMargin = 0.05f;    // A^2 added to rc^2 by the expanded-form prefilter
-constexpr float kFar = 1.0e18f;     // |coordinate| that fails every cutoff test; absent home
-                                    // atoms use +kFar, absent neighbours -kFar
+constexpr float kWin = 1.0e-3f;     // A added to r_cut for the x-window
+constexpr float kBigU = 1.0e30f;    // squared distance given to lanes that must add nothing
 
-// The 27 neighbour images, the home cell first.
+// The 27 neighbour images.
 __constant__ int8_t c_img[27][3] = {
     {0, 0, 0},    {-1, -1, -1}, {0, -1, -1}, {1, -1, -1}, {-1, 0, -1}, {0, 0, -1}, {1, 0, -1},
     {-1, 1, -1},  {0, 1, -1},   {1, 1, -1},  {-1, -1, 0}, {0, -1, 0},  {1, -1, 0}, {-1, 0, 0},
@@ -51,13 +56,39 @@ struct Img {
   int jsh;     // bit d: image lies at -L along d (the neighbour side subtracts L)
 };
 
-struct StaticLds {
-  uint32_t fifo[kNW][kQ * kFifo + 64];  // per home atom: passing neighbours; last 64: lanes
-                                        // that did not pass write here (never read)
-  Img img[27];
-  int grp_begin[9];                 // neighbour-list position where group g starts
-  int next;                         // next group of home atoms to hand out
+struct Seg {
+  int begin, end;   // neighbour-list positions
+  int grp;
 };
+
+// Workgroup header in LDS.
+struct Hdr {
+  Img img[27];
+  Seg seg[kMaxSeg];
+  int n_seg;
+  int total;        // neighbour-list length
+  int iters;        // binary-search steps that cover the longest segment
+  int next;         // next group of home atoms to hand out
+};
+
+// LDS layout in bytes: type u8 [cap] | header | FIFOs | LJ (c12, c6) [nt^2] |
+// (x, y, z, |r - o_g|^2) [cap] | q [cap]
+struct Lds {
+  int hdr, fifo, lj, f4, q, total;
+};
+
+__host__ __device__ constexpr int align_up(int v, int a) { return (v + a - 1) / a * a; }
+
+__host__ __device__ inline Lds lds_layout(int cap, int n_types) {
+  Lds L;
+  L.hdr = align_up(cap, 16);
+  L.fifo = align_up(L.hdr + (int)sizeof(Hdr), 16);
+  L.lj = align_up(L.fifo + 2 * kNW * kWaveFifo, 16);
+  L.f4 = align_up(L.lj + 8 * n_types * n_types, 16);
+  L.q = L.f4 + 16 * cap;
+  L.total = L.q + 4 * cap;
+  return L;
+}
 
 __device__ inline float rowsum16(float v) {
   // fixed butterfly: xor 1, xor 2, mirror within 8, mirror within 16
@@ -89,30 +120,32 @@ __device__ inline long long readlane64(long long v, int lane) {
   return (long long)(((unsigned long long)hi << 32) | lo);
 }
 
-// Scalar pair force and energy; identical arithmetic to the half-shell kernels.
+// Pair force factor f (F_i = f r_ij) and pair energy e at squared distance u.
+// c12 = 4 eps s^12, c6 = 4 eps s^6 (Eq. 1: A = 12 c12, B = 6 c6); qq = k q_i q_j (Eq. 2).
+// The switch t = clamp((u - rs^2)/(rc^2 - rs^2), 0, 1), S = (1-t)^2 (1+2t), and
+// g = 12 t (1-t) / (rc^2 - rs^2) = -2 dS/du. With kSwitchCoulomb the whole energy is
+// switched, so at t = 1 both f and e are exactly zero.
 template <bool kSwitchCoulomb>
 __device__ inline float pair_f(float u, float c12, float c6, float qq, float rs2, float inv_sw,
                                float sw12, float& e) {
-  float rinv = __builtin_amdgcn_rsqf(u);
-  float r2 = rinv * rinv;
-  float r6 = r2 * r2 * r2;
-  float A = c12 * r6 * r6;
-  float B = c6 * r6;
-  float elj = A - B;
-  float flj = 12.f * A - 6.f * B;
-  float ec = qq * rinv;
-  float xs = fmaxf(u - rs2, 0.f);
-  float t = xs * inv_sw;
-  float d = 1.f - t;
-  float S = d * d * (1.f + 2.f * t);
-  float g = t * d * sw12;
+  const float rinv = __builtin_amdgcn_rsqf(u);
+  const float r2 = rinv * rinv;
+  const float r6 = r2 * r2 * r2;
+  const float c6r6 = c6 * r6;
+  const float elj = fmaf(c12 * r6, r6, -c6r6);      // c12/r^12 - c6/r^6
+  const float x6 = fmaf(2.f, elj, c6r6);            // (12 c12/r^12 - 6 c6/r^6) / 6
+  const float ec = qq * rinv;
+  const float t = __builtin_amdgcn_fmed3f((u - rs2) * inv_sw, 0.f, 1.f);
+  const float d = 1.f - t;
+  const float S = d * d * fmaf(2.f, t, 1.f);
+  const float g = t * d * sw12;
   if (kSwitchCoulomb) {
-    float et = elj + ec;
+    const float et = elj + ec;
     e = S * et;
-    return S * (flj + ec) * r2 + g * et;
+    return fmaf(g, et, S * fmaf(6.f, x6, ec) * r2);
   }
-  e = S * elj + ec;
-  return (S * flj + ec) * r2 + g * elj;
+  e = fmaf(S, elj, ec);
+  return fmaf(g, elj, fmaf(6.f * S, x6, ec) * r2);
 }
 
 // v = bit `lane` of mask ? a : b, as one v_cndmask on the mask (keeps the compiler from
@@ -123,91 +156,156 @@ __device__ inline int select_by_mask(unsigned long long mask, int a, int b) {
   return r;
 }
 
+// 16-bit LDS store to a byte address relative to the start of LDS (the dynamic block
+// starts there: the kernel has no static LDS). Written out so the address needs no
+// further add; LDS operations of one wave complete in order, so the compiler's own
+// waits on later LDS reads stay valid.
+__device__ inline void lds_store_u16(uint32_t addr, uint32_t v) {
+  __asm__ volatile("ds_write_b16 %0, %1" : : "v"(addr), "v"(v) : "memory");
+}
+
 __device__ inline int64_t xcd_unit(int64_t b, int64_t n_units) {
   int64_t per = (n_units + 7) / 8;
   return (b % 8) * per + b / 8;
 }
 
-template <bool kSwitchCoulomb>
+// kClamp: the whole energy is switched and the switch is on, so lanes that must add
+// nothing (a partial batch, the home atom itself) get u = kBigU instead of masks on f
+// and e, and pairs beyond the cutoff need no test (t clamps to 1).
+// kDiag: count filter passes, cutoff passes and filtered slots (MD_DIAG_COUNTERS).
+template <bool kSwitchCoulomb, bool kClamp, bool kDiag>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
 void k_pair_fs(SysArgs<float> a, int cap) {
-  // dynamic LDS: neighbour (x,y,z,q) [cap] | neighbour type [cap] | LJ table [2 nt^2]
   extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
-  float4* sJ = reinterpret_cast<float4*>(s_dyn);
-  uint8_t* sT = s_dyn + 16 * (size_t)cap;
-  float* sLJ = reinterpret_cast<float*>(s_dyn + 17 * (size_t)cap);
-  __shared__ StaticLds S;
+  const Lds LL = lds_layout(cap, a.n_types);
+  uint8_t* sT = s_dyn;
+  Hdr& H = *reinterpret_cast<Hdr*>(s_dyn + LL.hdr);
+  uint16_t* sFifo = reinterpret_cast<uint16_t*>(s_dyn + LL.fifo);
+  float2* sLJ = reinterpret_cast<float2*>(s_dyn + LL.lj);
+  float4* sF = reinterpret_cast<float4*>(s_dyn + LL.f4);
+  float* sQ = reinterpret_cast<float*>(s_dyn + LL.q);
 
-  const int64_t n_units = a.n_cells * kSplit;
+  const int64_t n_units = a.n_cells;
   const int64_t unit = xcd_unit(blockIdx.x, n_units);
   if (unit >= n_units) return;
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int64_t cellA = unit / kSplit;
-  const int half = (int)(unit % kSplit);
+  const int64_t cellA = unit;
   const int nt = a.n_types;
-  const bool diag = (a.flags & MD_DIAG_COUNTERS) != 0;
+  constexpr bool diag = kDiag;
   const bool f32 = (a.flags & MD_ACCUM_F32_ATOMIC) != 0;
   const float rc2 = a.rc2, rs2 = a.rs2, inv_sw = a.inv_sw, sw12 = 12.f * a.inv_sw;
   const float kc = a.coulomb_k;
   const float L0 = a.L[0], L1 = a.L[1], L2 = a.L[2];
+  const int ac0 = (int)(cellA % a.nx), ac1 = (int)((cellA / a.nx) % a.ny),
+            ac2 = (int)(cellA / ((int64_t)a.nx * a.ny));
+  // origin o of the prefilter: the home cell's centre (any nearby point would do)
+  const float O0 = ((float)ac0 + 0.5f) * (L0 / (float)a.nx);
+  const float O1 = ((float)ac1 + 0.5f) * (L1 / (float)a.ny);
+  const float O2 = ((float)ac2 + 0.5f) * (L2 / (float)a.nz);
 
-  for (int e = tid; e < 2 * nt * nt; e += kThreads) sLJ[e] = a.lj[e];
+  for (int e = tid; e < nt * nt; e += kThreads) sLJ[e] = make_float2(a.lj[2 * e], a.lj[2 * e + 1]);
+  // FIFO entries past a FIFO's fill level are read by partial force passes (and then
+  // ignored): start them as valid indices
+  for (int e = tid; e < kNW * kWaveFifo / 2; e += kThreads)
+    reinterpret_cast<uint32_t*>(sFifo)[e] = 0u;
   const int sA = a.start[cellA];
   const int nA = a.start[cellA + 1] - sA;
-  const int ib0 = (int)(((int64_t)half * nA) / kSplit);
-  const int ib1 = (int)(((int64_t)(half + 1) * nA) / kSplit);
 
-  // image table: one lane per image (independent loads), then the group order
-  if (tid < 27) {
+  // image table and segments (wave 0; lane m = image m). Images are ordered by
+  // (group, dz, dy, dx): the images of one (dy, dz) row with one group form a segment,
+  // sorted in x because each cell is and the cells follow each other in x.
+  if (tid < 64) {
+    const int m = lane;
+    const bool act = m < 27;
     const int nd[3] = {a.nx, a.ny, a.nz};
-    const int ac[3] = {(int)(cellA % a.nx), (int)((cellA / a.nx) % a.ny),
-                       (int)(cellA / ((int64_t)a.nx * a.ny))};
-    int b[3], grp = 0, jsh = 0;
-    for (int d = 0; d < 3; ++d) {
-      b[d] = ac[d] + c_img[tid][d];
-      if (b[d] >= nd[d]) {
-        b[d] -= nd[d];
-        grp |= 1 << d;
-      } else if (b[d] < 0) {
-        b[d] += nd[d];
-        jsh |= 1 << d;
+    const int ac[3] = {ac0, ac1, ac2};
+    int grp = 0, jsh = 0, st0 = 0, cnt = 0, key = 1 << 20, ox = 0;
+    if (act) {
+      int b[3];
+      for (int d = 0; d < 3; ++d) {
+        b[d] = ac[d] + c_img[m][d];
+        if (b[d] >= nd[d]) {
+          b[d] -= nd[d];
+          grp |= 1 << d;
+        } else if (b[d] < 0) {
+          b[d] += nd[d];
+          jsh |= 1 << d;
+        }
+      }
+      const int64_t cb = ((int64_t)b[2] * a.ny + b[1]) * a.nx + b[0];
+      st0 = a.start[cb];
+      cnt = a.start[cb + 1] - st0;
+      key = grp * 9 + (c_img[m][1] + 1) + 3 * (c_img[m][2] + 1);
+      ox = c_img[m][0];
+    }
+    int off = 0, seg_len = 0, tot = 0;
+    bool head = act;
+    for (int mm = 0; mm < 27; ++mm) {
+      const int km = __builtin_amdgcn_readlane(key, mm);
+      const int cm = __builtin_amdgcn_readlane(cnt, mm);
+      const int xm = __builtin_amdgcn_readlane(ox, mm);
+      const bool same = km == key;
+      off += (km < key || (same && xm < ox)) ? cm : 0;
+      seg_len += same ? cm : 0;
+      if (same && xm < ox) head = false;
+      tot += cm;
+    }
+    // a head (the first image of its segment) is numbered by the heads with smaller keys
+    const unsigned long long heads = __builtin_amdgcn_ballot_w64(head);
+    int seg_idx = 0;
+    for (int mm = 0; mm < 27; ++mm) {
+      const int km = __builtin_amdgcn_readlane(key, mm);
+      seg_idx += (((heads >> mm) & 1ull) && km < key) ? 1 : 0;
+    }
+    if (act) {
+      H.img[m].start = st0;
+      H.img[m].count = cnt;
+      H.img[m].off = off;
+      H.img[m].grp = grp;
+      H.img[m].jsh = jsh;
+      if (head) {
+        H.seg[seg_idx].begin = off;
+        H.seg[seg_idx].end = off + seg_len;
+        H.seg[seg_idx].grp = grp;
       }
     }
-    const int64_t cb = ((int64_t)b[2] * a.ny + b[1]) * a.nx + b[0];
-    const int st0 = a.start[cb], st1 = a.start[cb + 1];
-    S.img[tid].start = st0;
-    S.img[tid].count = st1 - st0;
-    S.img[tid].grp = grp;
-    S.img[tid].jsh = jsh;
-    // position in the neighbour list: images ordered by group, then by image index
-    // (the home image, group 0, first)
-    int off = 0, gb = 0;
-    for (int mm = 0; mm < 27; ++mm) {
-      const int gm = __builtin_amdgcn_readlane(grp, mm);
-      const int cm = __builtin_amdgcn_readlane(st1 - st0, mm);
-      off += (gm < grp || (gm == grp && mm < tid)) ? cm : 0;
-      gb += (tid < 9 && gm < tid) ? cm : 0;      // lane g < 9: start of group g
+    int ml = head ? seg_len : 0;
+    for (int s = 32; s > 0; s >>= 1) ml = max(ml, __shfl_xor(ml, s));
+    if (lane == 0) {
+      H.n_seg = __builtin_popcountll(heads);
+      H.total = tot;
+      int it = 0;
+      while ((1 << it) <= ml) ++it;   // steps of a lower_bound over ml elements
+      H.iters = it;
     }
-    S.img[tid].off = off;
-    if (tid < 9) S.grp_begin[tid] = gb;
   }
   __syncthreads();
 
-  const int total = S.grp_begin[8];
-  const int n_grp_q = (ib1 - ib0 + kQ - 1) / kQ;
+  const int total = H.total;
+  const int n_seg = H.n_seg;
+  const int iters = H.iters;
+  const int n_grp_q = (nA + kQ - 1) / kQ;
+  const float R = __builtin_sqrtf(rc2) + kWin;
   double e_wave = 0.0;
-  unsigned long long pass_count = 0;
+  unsigned long long pass_count = 0, filt_count = 0, slot_count = 0;
   uint32_t st = 0;
-  uint32_t* fifo = &S.fifo[w][0];
+  uint16_t* fifo = sFifo + w * kWaveFifo;
+  // LDS byte addresses: FIFO k of this wave starts at fk0 + 2 k kFifo; dump slot of the lane
+  const uint32_t fk0 = (uint32_t)(LL.fifo + 2 * w * kWaveFifo);
+  const uint32_t dump = fk0 + 2u * (uint32_t)(kQ * kFifo + lane);
 
   for (int P0 = 0; P0 < total; P0 += cap) {
     const int P1 = min(total, P0 + cap);
     // stage the neighbour-list slice [P0, P1): wave w copies images w and w + 16, issuing
     // all loads of an image (up to 4 x 64 atoms per round) before its LDS stores
     for (int m = w; m < 27; m += kNW) {
-      const Img im = S.img[m];
+      const Img im = H.img[m];
       const int lo = max(im.off, P0), hi = min(im.off + im.count, P1);
+      // o_g = o - h: the origin in this image's frame
+      const float og0 = O0 - ((im.grp & 1) ? L0 : 0.f);
+      const float og1 = O1 - ((im.grp & 2) ? L1 : 0.f);
+      const float og2 = O2 - ((im.grp & 4) ? L2 : 0.f);
       for (int e0 = lo; e0 < hi; e0 += 4 * 64) {
         P4<float> v[4];
         int tv[4];
@@ -225,163 +323,229 @@ void k_pair_fs(SysArgs<float> a, int cap) {
             const float x = (im.jsh & 1) ? v[r].x - L0 : v[r].x;
             const float y = (im.jsh & 2) ? v[r].y - L1 : v[r].y;
             const float z = (im.jsh & 4) ? v[r].z - L2 : v[r].z;
-            sJ[e - P0] = make_float4(x, y, z, v[r].w);
+            const float rx = x - og0, ry = y - og1, rz = z - og2;
+            sF[e - P0] = make_float4(x, y, z, fmaf(rz, rz, fmaf(ry, ry, rx * rx)));
+            sQ[e - P0] = v[r].w;
             sT[e - P0] = (uint8_t)tv[r];
           }
         }
       }
     }
-    if (tid == 0) S.next = 0;
+    if (tid == 0) H.next = 0;
     __syncthreads();
+
+    // segment table in registers: lane s holds segment s, clipped to this slice
+    int sb = 0, se = 0, sg = 0;
+    if (lane < n_seg) {
+      sb = max(H.seg[lane].begin, P0) - P0;
+      se = max(min(H.seg[lane].end, P1) - P0, sb);
+      sg = H.seg[lane].grp;
+    }
 
     while (true) {
       int o = 0;
-      if (lane == 0) o = atomicAdd(&S.next, 1);
+      if (lane == 0) o = atomicAdd(&H.next, 1);
       o = __builtin_amdgcn_readfirstlane(__shfl(o, 0));
       if (o >= n_grp_q) break;
-      const int ib = ib0 + kQ * o;
+      const int ib = kQ * o;
+      const int nv = min(kQ, nA - ib);   // home atoms present in this group
 
       float xi[kQ], yi[kQ], zi[kQ], kq[kQ], fx[kQ], fy[kQ], fz[kQ];
-      int ti[kQ], tl[kQ];
+      float ax[kQ], ay[kQ], az[kQ], thb[kQ];
+      int row[kQ], tl[kQ];
+      uint32_t fb[kQ];   // byte address of the next free slot of FIFO k
       unsigned cnt[kQ];
+      float xmin = 0.f, xmax = 0.f;
 #pragma unroll
       for (int k = 0; k < kQ; ++k) {
-        const bool v = ib + k < ib1;
-        const int s = sA + (v ? ib + k : ib0);
+        const bool v = k < nv;
+        const int s = sA + ib + (v ? k : 0);
         const P4<float> p = a.pos[s];
-        xi[k] = v ? p.x : kFar;   // an absent home atom fails every test
+        xi[k] = p.x;
         yi[k] = p.y;
         zi[k] = p.z;
         kq[k] = kc * p.w;
-        ti[k] = a.type[s] * nt;
+        row[k] = a.type[s] * nt;
+        xmin = k == 0 ? p.x : fminf(xmin, p.x);
+        xmax = k == 0 ? p.x : fmaxf(xmax, p.x);
+        // prefilter in the frame of group g, with a = r_i - o (the same in every frame):
+        // |r_j - r_i|^2 = c_j - 2 a.(r_j - o_g) + |a|^2, c_j = |r_j - o_g|^2, so the test
+        // c_j + ax.r_j < rc^2 + margin - |a|^2 + ax.o_g with ax = -2a
+        const float rx = p.x - O0, ry = p.y - O1, rz = p.z - O2;
+        ax[k] = v ? -2.f * rx : 0.f;
+        ay[k] = v ? -2.f * ry : 0.f;
+        az[k] = v ? -2.f * rz : 0.f;
+        // an absent atom gets -1, which c_j >= 0 never passes
+        thb[k] = v ? (rc2 + kMargin) - fmaf(rz, rz, fmaf(ry, ry, rx * rx)) +
+                         (ax[k] * O0 + ay[k] * O1 + az[k] * O2)
+                   : -1.f;
         fx[k] = fy[k] = fz[k] = 0.f;
         tl[k] = 0;
+        fb[k] = fk0 + 2u * (uint32_t)(k * kFifo);
         cnt[k] = 0;
       }
       float e_lane = 0.f;
 
-      for (int g = 0; g < 8; ++g) {
-        const int G0 = max(S.grp_begin[g], P0), G1 = min(S.grp_begin[g + 1], P1);
-        if (G0 >= G1) continue;
-        const int r0 = G0 - P0, r1 = G1 - P0;
-        // home coordinates in this group's frame: subtract L where the images lie at +L
-        float xs[kQ], ys[kQ], zs[kQ];
-        // prefilter terms relative to the origin o (the home cell's first atom, this frame):
-        // |x_i - x_j|^2 = c_i + c_j - 2 r_i . r_j with r = x - o, c = |r|^2
-        float ax[kQ], ay[kQ], az[kQ], thr[kQ];
-        const float ox = xi[0] - ((g & 1) ? L0 : 0.f), oy = yi[0] - ((g & 2) ? L1 : 0.f),
-                    oz = zi[0] - ((g & 4) ? L2 : 0.f);
-#pragma unroll
-        for (int k = 0; k < kQ; ++k) {
-          xs[k] = (g & 1) ? xi[k] - L0 : xi[k];
-          ys[k] = (g & 2) ? yi[k] - L1 : yi[k];
-          zs[k] = (g & 4) ? zi[k] - L2 : zi[k];
-          const float rx = xs[k] - ox, ry = ys[k] - oy, rz = zs[k] - oz;
-          ax[k] = -2.f * rx;
-          ay[k] = -2.f * ry;
-          az[k] = -2.f * rz;
-          thr[k] = (rc2 + kMargin) - fmaf(rz, rz, fmaf(ry, ry, rx * rx));
-        }
-
-        // dense force passes over the first c entries of FIFO k (c <= 64 * kDrain): the exact
-        // cutoff test (u < rc^2; u > 0 drops the home atom itself) and the force. All LDS
-        // reads of the kDrain batches are issued before any arithmetic.
-        auto force = [&](int k, int c) __attribute__((always_inline)) {
-          uint32_t ent[kDrain];
-          float4 pj[kDrain];
-          float c12[kDrain], c6[kDrain];
-#pragma unroll
-          for (int b = 0; b < kDrain; ++b) ent[b] = fifo[k * kFifo + 64 * b + lane];
-#pragma unroll
-          for (int b = 0; b < kDrain; ++b) {
-            const bool in = 64 * b + lane < c;
-            const int jj = in ? (int)(ent[b] & 0xffffu) : r0;
-            const int tj = in ? (int)(ent[b] >> 16) : 0;
-            pj[b] = sJ[jj];
-            const int e2 = 2 * (ti[k] + tj);
-            c12[b] = sLJ[e2];
-            c6[b] = sLJ[e2 + 1];
+      // x-window of every segment: lane s finds [lo, hi) of segment s with
+      // x in [min x_i - R, max x_i + R) in the segment's frame (two lower_bound searches)
+      int wlo, whi;
+      {
+        const float hx = (sg & 1) ? L0 : 0.f;
+        const float xlo = (xmin - hx) - R;
+        const float xhi = (xmax - hx) + R;
+        int f0 = sb, c0 = se - sb, f1 = sb, c1 = se - sb;
+        for (int it = 0; it < iters; ++it) {
+          const int h0 = c0 >> 1, h1 = c1 >> 1;
+          const float x0 = sF[f0 + h0].x;   // f + h <= se <= cap: inside the LDS block
+          const float x1 = sF[f1 + h1].x;
+          if (c0 > 0) {
+            if (x0 < xlo) {
+              f0 += h0 + 1;
+              c0 -= h0 + 1;
+            } else {
+              c0 = h0;
+            }
           }
+          if (c1 > 0) {
+            if (x1 < xhi) {
+              f1 += h1 + 1;
+              c1 -= h1 + 1;
+            } else {
+              c1 = h1;
+            }
+          }
+        }
+        wlo = f0;
+        whi = max(f1, f0);
+      }
+
+      float xs[kQ], ys[kQ], zs[kQ], thr[kQ];
+      // dense force passes over the first c entries of FIFO k (c <= 64 * kDrain): the exact
+      // distance in the current frame, the strict cutoff (u > 0 drops the home atom
+      // itself) and the force. All LDS reads of the kDrain batches precede the arithmetic.
+      auto force = [&](int k, int c) __attribute__((always_inline)) {
+        int jj[kDrain], tj[kDrain];
+        float4 pj[kDrain];
+        float qj[kDrain];
+        float2 lj[kDrain];
 #pragma unroll
-          for (int b = 0; b < kDrain; ++b) {
-            const bool in = 64 * b + lane < c;
-            const float dx = xs[k] - pj[b].x, dy = ys[k] - pj[b].y, dz = zs[k] - pj[b].z;
-            const float u = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        for (int b = 0; b < kDrain; ++b) jj[b] = fifo[k * kFifo + 64 * b + lane];
+#pragma unroll
+        for (int b = 0; b < kDrain; ++b) {
+          pj[b] = sF[jj[b]];
+          qj[b] = sQ[jj[b]];
+          tj[b] = sT[jj[b]];
+        }
+#pragma unroll
+        for (int b = 0; b < kDrain; ++b) lj[b] = sLJ[row[k] + tj[b]];
+#pragma unroll
+        for (int b = 0; b < kDrain; ++b) {
+          const float dx = xs[k] - pj[b].x, dy = ys[k] - pj[b].y, dz = zs[k] - pj[b].z;
+          float u = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+          const bool in = 64 * b + lane < c;
+          float e, f;
+          if (kClamp) {
+            u = (in && u > 0.f) ? u : kBigU;
+            f = pair_f<kSwitchCoulomb>(u, lj[b].x, lj[b].y, kq[k] * qj[b], rs2, inv_sw, sw12, e);
+            if (diag) cnt[k] += __builtin_popcountll(__builtin_amdgcn_ballot_w64(u < rc2));
+          } else {
             const bool lv = in && u < rc2 && u > 0.f;
-            float e;
-            float f = pair_f<kSwitchCoulomb>(u, c12[b], c6[b], kq[k] * pj[b].w, rs2, inv_sw, sw12, e);
+            f = pair_f<kSwitchCoulomb>(u, lj[b].x, lj[b].y, kq[k] * qj[b], rs2, inv_sw, sw12, e);
             f = lv ? f : 0.f;
             e = lv ? e : 0.f;
-            fx[k] = fmaf(f, dx, fx[k]);
-            fy[k] = fmaf(f, dy, fy[k]);
-            fz[k] = fmaf(f, dz, fz[k]);
-            e_lane += e;
-            cnt[k] += __builtin_popcountll(__builtin_amdgcn_ballot_w64(lv));
+            if (diag) cnt[k] += __builtin_popcountll(__builtin_amdgcn_ballot_w64(lv));
           }
-          // drop the first c entries; the remainder (fewer than 64) moves to the front
-          const int rem = tl[k] - c;
-          if (rem > 0) {
-            uint32_t v = 0;
-            if (lane < rem) v = fifo[k * kFifo + c + lane];
-            if (lane < rem) fifo[k * kFifo + lane] = v;
-          }
-          tl[k] = rem;
-        };
+          fx[k] = fmaf(f, dx, fx[k]);
+          fy[k] = fmaf(f, dy, fy[k]);
+          fz[k] = fmaf(f, dz, fz[k]);
+          e_lane += e;
+        }
+        // drop the first c entries; the remainder (fewer than 64) moves to the front
+        const int rem = tl[k] - c;
+        if (rem > 0) {
+          uint16_t v = 0;
+          if (lane < rem) v = fifo[k * kFifo + c + lane];
+          if (lane < rem) fifo[k * kFifo + lane] = v;
+        }
+        tl[k] = rem;
+        fb[k] = fk0 + 2u * (uint32_t)(k * kFifo + rem);
+      };
+      auto flush = [&]() __attribute__((always_inline)) {
+#pragma unroll
+        for (int k = 0; k < kQ; ++k) {
+          while (tl[k] > 0) force(k, tl[k] < 64 * kDrain ? tl[k] : 64 * kDrain);
+        }
+      };
 
-        // software pipeline: the next batch's neighbour is loaded one batch ahead
-        int jr = min(r0 + lane, r1 - 1);
-        float4 pn = sJ[jr];
-        uint32_t cn = ((uint32_t)sT[jr] << 16) | (uint32_t)jr;
-        for (int jb = r0; jb < r1; jb += 64) {
-          const int jv = jb + lane;
-          const bool last = jb + 64 >= r1;
-          float4 pj = pn;
-          const uint32_t code = cn;
-          if (!last) {
-            const int jn = min(jv + 64, r1 - 1);
-            pn = sJ[jn];
-            cn = ((uint32_t)sT[jn] << 16) | (uint32_t)jn;
+      int cur_g = -1;
+      for (int s = 0; s < n_seg; ++s) {
+        const int lo = __builtin_amdgcn_readlane(wlo, s);
+        const int hi = __builtin_amdgcn_readlane(whi, s);
+        if (lo >= hi) continue;
+        const int g = __builtin_amdgcn_readlane(sg, s);
+        if (g != cur_g) {
+          if (cur_g >= 0) flush();   // the home side changes frame
+          cur_g = g;
+          const float hx = (g & 1) ? L0 : 0.f, hy = (g & 2) ? L1 : 0.f, hz = (g & 4) ? L2 : 0.f;
+#pragma unroll
+          for (int k = 0; k < kQ; ++k) {
+            xs[k] = xi[k] - hx;   // exact: such home atoms lie in the last cell of the axis
+            ys[k] = yi[k] - hy;
+            zs[k] = zi[k] - hz;
+            // ax.o_g = ax.o - ax.h
+            thr[k] = thb[k] - (ax[k] * hx + ay[k] * hy + az[k] * hz);
           }
-          if (last) pj.x = jv < r1 ? pj.x : -kFar;   // opposite sign to the absent-home sentinel
-          const float rx = pj.x - ox, ry = pj.y - oy, rz = pj.z - oz;
-          const float cj = fmaf(rz, rz, fmaf(ry, ry, rx * rx));
+        }
+        if (diag) slot_count += (unsigned long long)(hi - lo) * (unsigned long long)nv;
+        for (int jb = lo; jb < hi; jb += 64) {
+          // lanes past hi read in-bounds LDS (the q block follows) and are masked off
+          const int j = jb + lane;
+          const int nb = hi - jb;
+          const unsigned long long vm = nb >= 64 ? ~0ull : ((1ull << nb) - 1ull);
+          const float4 pj = sF[j];
           float t[kQ];
 #pragma unroll
-          for (int k = 0; k < kQ; ++k) t[k] = fmaf(ax[k], rx, cj);
+          for (int k = 0; k < kQ; ++k) t[k] = fmaf(ax[k], pj.x, pj.w);
 #pragma unroll
-          for (int k = 0; k < kQ; ++k) t[k] = fmaf(ay[k], ry, t[k]);
+          for (int k = 0; k < kQ; ++k) t[k] = fmaf(ay[k], pj.y, t[k]);
 #pragma unroll
-          for (int k = 0; k < kQ; ++k) t[k] = fmaf(az[k], rz, t[k]);
+          for (int k = 0; k < kQ; ++k) t[k] = fmaf(az[k], pj.z, t[k]);
           unsigned long long m[kQ];
 #pragma unroll
-          for (int k = 0; k < kQ; ++k) m[k] = __builtin_amdgcn_ballot_w64(t[k] < thr[k]);
+          for (int k = 0; k < kQ; ++k) m[k] = __builtin_amdgcn_ballot_w64(t[k] < thr[k]) & vm;
           // every lane writes: passing lanes to their FIFO slot, the others to their own
           // dump slot, so no exec-mask changes are needed
-          int idx[kQ];
+          int adr[kQ];
 #pragma unroll
           for (int k = 0; k < kQ; ++k) {
-            const int rank = (int)__builtin_amdgcn_mbcnt_hi(
+            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
                 (unsigned)(m[k] >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m[k], 0u));
-            idx[k] = select_by_mask(m[k], k * kFifo + tl[k] + rank, kQ * kFifo + lane);
+            adr[k] = select_by_mask(m[k], (int)(fb[k] + 2u * rank), (int)dump);
           }
 #pragma unroll
-          for (int k = 0; k < kQ; ++k) fifo[idx[k]] = code;
-#pragma unroll
-          for (int k = 0; k < kQ; ++k) tl[k] += __builtin_popcountll(m[k]);
-          // drain full FIFOs (kDrain batches at a time); on the group's last batch drain
-          // everything (the home side changes frame in the next group)
-          const int thr_n = last ? 1 : 64 * kDrain;
+          for (int k = 0; k < kQ; ++k) lds_store_u16((uint32_t)adr[k], (uint32_t)j);
 #pragma unroll
           for (int k = 0; k < kQ; ++k) {
-            while (tl[k] >= thr_n) force(k, tl[k] < 64 * kDrain ? tl[k] : 64 * kDrain);
+            const int np = __builtin_popcountll(m[k]);
+            tl[k] += np;
+            fb[k] += 2u * (uint32_t)np;
+          }
+          if (diag) {
+#pragma unroll
+            for (int k = 0; k < kQ; ++k) filt_count += __builtin_popcountll(m[k]);
+          }
+#pragma unroll
+          for (int k = 0; k < kQ; ++k) {
+            if (tl[k] >= 64 * kDrain) force(k, 64 * kDrain);
           }
         }
       }
+      if (cur_g >= 0) flush();
 
       // per home atom: fixed-order row sums, then the four rows in 64-bit fixed point
 #pragma unroll
       for (int k = 0; k < kQ; ++k) {
-        if (ib + k >= ib1) continue;
+        if (k >= nv) continue;
         const int64_t s = sA + ib + k;
         const float comp[3] = {fx[k], fy[k], fz[k]};
 #pragma unroll
@@ -419,7 +583,7 @@ void k_pair_fs(SysArgs<float> a, int cap) {
   }
 
   // workgroup energy: each pair was seen from both atoms
-  double* sE = reinterpret_cast<double*>(s_dyn);
+  double* sE = reinterpret_cast<double*>(s_dyn + LL.f4);
   sE[tid] = e_wave;
   __syncthreads();
   for (int off = kThreads / 2; off > 0; off >>= 1) {
@@ -429,43 +593,56 @@ void k_pair_fs(SysArgs<float> a, int cap) {
   if (tid == 0) a.epart[unit] = 0.5 * sE[0];
   if (st) atomicOr(&a.hdr->status, st);
   if (diag && lane == 0) {
-    // candidates: every (home atom, other neighbour-list atom), counted from both atoms
+    // candidates of Algorithm 1: every (home atom, other neighbour-list atom), counted
+    // from both atoms; the neighbour slots this kernel actually filtered come separately
     if (w == 0) {
-      const unsigned long long cand =
-          (unsigned long long)(ib1 - ib0) * (unsigned long long)(total - 1);
+      const unsigned long long cand = (unsigned long long)nA * (unsigned long long)(total - 1);
       atomicAdd(&a.hdr->diag[0], cand);
     }
-    atomicAdd(&a.hdr->diag[1], pass_count);
+    atomicAdd(&a.hdr->diag[1], filt_count);
     atomicAdd(&a.hdr->diag[2], pass_count);
+    atomicAdd(&a.hdr->diag[3], slot_count);
   }
+}
+
+// Neighbour atoms staged in LDS per pass for n_types types (a multiple of 64).
+int fs_cap(int n_types) {
+  int cap = (kLdsBytes - lds_layout(0, n_types).total) / 21;
+  cap -= cap % 64;
+  while (cap > 0 && lds_layout(cap, n_types).total > kLdsBytes) cap -= 64;
+  return cap;
 }
 
 }  // namespace
 
-// Neighbour atoms staged in LDS per pass for n_types types (a multiple of 64).
-static int fs_cap(int n_types) {
-  const int avail = kLdsBytes - (int)sizeof(StaticLds) - (int)sizeof(float) * 2 * n_types * n_types;
-  int cap = avail / 17;
-  cap -= cap % 64;
-  return cap;
-}
-
 size_t pair_fs_lds_bytes(int n_types) {
-  return (size_t)17 * fs_cap(n_types) + sizeof(float) * 2 * n_types * n_types;
+  return (size_t)lds_layout(fs_cap(n_types), n_types).total;
 }
 
 hipError_t launch_pair_fs(const SysArgs<float>& a, hipStream_t stream) {
   if (a.n == 0) return hipSuccess;
-  const int64_t units = a.n_cells * kSplit;
+  const int64_t units = a.n_cells;
   const int64_t blocks = 8 * ((units + 7) / 8);
   const int cap = fs_cap(a.n_types);
   const size_t shmem = pair_fs_lds_bytes(a.n_types);
-  if (!(a.flags & MD_COULOMB_TRUNCATED))
-    hipLaunchKernelGGL(k_pair_fs<true>, dim3((unsigned)blocks), dim3(kThreads), shmem, stream, a,
-                       cap);
-  else
-    hipLaunchKernelGGL(k_pair_fs<false>, dim3((unsigned)blocks), dim3(kThreads), shmem, stream, a,
-                       cap);
+  const bool trunc = (a.flags & MD_COULOMB_TRUNCATED) != 0;
+  const bool clamp = !trunc && a.inv_sw > 0.f;
+  const dim3 grid((unsigned)blocks), block(kThreads);
+  if (a.flags & MD_DIAG_COUNTERS) {
+    if (clamp)
+      hipLaunchKernelGGL((k_pair_fs<true, true, true>), grid, block, shmem, stream, a, cap);
+    else if (!trunc)
+      hipLaunchKernelGGL((k_pair_fs<true, false, true>), grid, block, shmem, stream, a, cap);
+    else
+      hipLaunchKernelGGL((k_pair_fs<false, false, true>), grid, block, shmem, stream, a, cap);
+  } else {
+    if (clamp)
+      hipLaunchKernelGGL((k_pair_fs<true, true, false>), grid, block, shmem, stream, a, cap);
+    else if (!trunc)
+      hipLaunchKernelGGL((k_pair_fs<true, false, false>), grid, block, shmem, stream, a, cap);
+    else
+      hipLaunchKernelGGL((k_pair_fs<false, false, false>), grid, block, shmem, stream, a, cap);
+  }
   return hipGetLastError();
 }
 

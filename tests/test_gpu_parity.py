@@ -113,12 +113,14 @@ def test_binning_matches_oracle(gpu):
     perm = ws[lay["perm"]: lay["perm"] + 4 * s.n].view(torch.int32).cpu().numpy()
     assert start[0] == 0 and start[-1] == s.n and np.all(np.diff(start) >= 0)
     assert np.array_equal(np.sort(perm), np.arange(s.n))
+    pos64, _ = oracle.canonicalize(s.pos, s.box)   # wrapped in float32, as the kernels do
     gcell = np.empty(s.n, np.int64)
     for c in range(nc):
         seg = perm[start[c]:start[c + 1]]
-        assert np.all(np.diff(seg) > 0)           # ordered by original index in a cell
+        # a cell is ordered by (wrapped x, original index)
+        x = pos64[seg, 0]
+        assert np.all((np.diff(x) > 0) | ((np.diff(x) == 0) & (np.diff(seg) > 0)))
         gcell[seg] = c
-    pos64, _ = oracle.canonicalize(s.pos, s.box)
     ocell, dims = oracle.bin_atoms(p, pos64)
     diff = np.nonzero(gcell != ocell)[0]
     # an atom may only change cell when it sits within 1e-4 A of a cell face
