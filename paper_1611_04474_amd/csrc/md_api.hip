@@ -68,6 +68,18 @@ md_status make_plan(const md_params* p, int64_t n, int real_bytes, Plan* pl) {
   pl->off_epart = o;     o = align_up(o + sizeof(double) * pl->n_tasks);
   pl->off_lj = o;        o = align_up(o + (size_t)real_bytes * 2 * kMaxTypes * kMaxTypes);
   pl->off_paircount = o; o = align_up(o + sizeof(int32_t) * 2 * nn);
+  // binning with per-block LDS histograms when the grid fits in LDS
+  pl->bin_blocks = 0;
+  pl->bin_chunk = 0;
+  if (n > 0 && cells <= kBinLdsCells) {
+    int64_t chunk = (n + kBinMaxBlocks - 1) / kBinMaxBlocks;
+    chunk = (chunk + 1023) / 1024 * 1024;
+    if (chunk < kBinMinChunk) chunk = kBinMinChunk;
+    pl->bin_chunk = chunk;
+    pl->bin_blocks = (int)((n + chunk - 1) / chunk);
+  }
+  pl->off_bhist = o;     o = align_up(o + sizeof(int32_t) * (size_t)pl->bin_blocks * cells);
+  pl->off_bstat = o;     o = align_up(o + sizeof(uint32_t) * (size_t)(pl->bin_blocks + 1));
   pl->total = o;
   return MD_OK;
 }
@@ -98,7 +110,10 @@ SysArgs<Real> make_args(const md_params* p, const Plan& pl, int64_t n, const Rea
   a.lj = (Real*)(b + pl.off_lj);
   a.paircount = (int32_t*)(b + pl.off_paircount);
   a.acc64 = (long long*)(b + pl.off_part);   // the full-shell path reuses the partial buffer
-  a.work = nullptr;
+  a.bhist = (int32_t*)(b + pl.off_bhist);
+  a.bstat = (uint32_t*)(b + pl.off_bstat);
+  a.bin_blocks = pl.bin_blocks;
+  a.bin_chunk = pl.bin_chunk;
   a.n = n;
   a.n_cells = pl.n_cells;
   a.n_tasks = pl.n_tasks;

@@ -4,13 +4,19 @@
 // arrays (first transformation of Section 2.2): float4/double4 (x, y, z, q), the
 // type and the permutation back to the caller's order.
 //
-// Kernels, in launch order:
-//   k_setup      clears the cell counters and status word, builds the mixed
-//                Lennard-Jones table (Lorentz-Berthelot) in the workspace;
-//   k_bin_count  wraps each coordinate into [0, L] (one add/subtract of L in the input
-//                precision), checks it, computes the cell and takes a slot with an atomic;
-//   k_scan       one workgroup: exclusive prefix sum of the counts -> cell_start;
-//   k_scatter    writes each atom's index at cell_start + slot (arbitrary order in a cell);
+// Kernels, in launch order. When the grid fits in LDS (the usual case):
+//   k_bin_hist   each block takes a contiguous range of atoms, wraps each coordinate
+//                into [0, L] (one add/subtract of L in the input precision), checks it,
+//                computes the cell and counts it in an LDS histogram (the LDS atomic's
+//                return value is the atom's slot among the block's atoms of that cell);
+//                the histogram and the block's status bits go to the workspace, so no
+//                global atomics are needed;
+//   k_bin_scan   one workgroup: per cell, exclusive offsets of the blocks and the total;
+//                exclusive scan of the totals -> cell_start; the mixed Lennard-Jones
+//                table (Lorentz-Berthelot); the status word;
+// otherwise k_setup (clears the counters) and k_bin_count (one global atomic per atom)
+// take the place of k_bin_hist, and k_bin_scan only scans. Then:
+//   k_scatter    writes each atom's index into its cell's range (arbitrary order);
 //   k_cell_sort  one workgroup per cell: orders the cell's atoms by (wrapped x, original
 //                index) -- a total order, so every later sum runs in a reproducible order,
 //                and a row of cells along x is sorted in x, which lets the pair kernel
@@ -38,7 +44,7 @@ __device__ inline Real wrap_coord(Real x, Real L, uint32_t& st) {
   }
   if (x < Real(0)) return x + L;   // one rounding in the input precision
   if (x >= L) return x - L;        // exact
-  return x;
+  return x + Real(0);              // -0 becomes +0
 }
 
 template <typename Real>
@@ -49,29 +55,61 @@ __device__ inline int cell_coord(Real x, Real inv_w, int n) {
 }
 
 template <typename Real>
-__global__ void k_setup(SysArgs<Real> a, TypeTable tt) {
+__device__ inline int cell_of(const SysArgs<Real>& a, int64_t i, uint32_t& st) {
+  const Real x = wrap_coord(a.pos_in[3 * i + 0], a.L[0], st);
+  const Real y = wrap_coord(a.pos_in[3 * i + 1], a.L[1], st);
+  const Real z = wrap_coord(a.pos_in[3 * i + 2], a.L[2], st);
+  const int t = a.type_in[i];
+  if (t < 0 || t >= a.n_types) st |= MD_STATUS_BAD_TYPE;
+  const int cx = cell_coord(x, a.inv_w[0], a.nx);
+  const int cy = cell_coord(y, a.inv_w[1], a.ny);
+  const int cz = cell_coord(z, a.inv_w[2], a.nz);
+  return (cz * a.ny + cy) * a.nx + cx;
+}
+
+// Clears the per-atom accumulators that the pair kernels add into.
+template <typename Real>
+__device__ inline void clear_atom(const SysArgs<Real>& a, int64_t i) {
+  if (a.flags & MD_ACCUM_F32_ATOMIC) {
+    a.facc[i] = 0.f;
+    a.facc[a.n + i] = 0.f;
+    a.facc[2 * a.n + i] = 0.f;
+  }
+  if (a.flags & MD_DIAG_COUNTERS) a.paircount[a.n + i] = 0;
+}
+
+template <typename Real>
+__global__ __launch_bounds__(1024) void k_bin_hist(SysArgs<Real> a) {
+  extern __shared__ int32_t s_h[];   // [n_cells] counts, then the status bits
+  const int nc = (int)a.n_cells;
+  const int tid = threadIdx.x;
+  for (int c = tid; c <= nc; c += 1024) s_h[c] = 0;
+  __syncthreads();
+  const int64_t i0 = (int64_t)blockIdx.x * a.bin_chunk;
+  const int64_t i1 = i0 + a.bin_chunk < a.n ? i0 + a.bin_chunk : a.n;
+  uint32_t st = 0;
+  for (int64_t i = i0 + tid; i < i1; i += 1024) {
+    const int c = cell_of(a, i, st);
+    a.cell[i] = c;
+    a.rank[i] = atomicAdd(&s_h[c], 1);
+    clear_atom(a, i);
+  }
+  if (st) atomicOr(reinterpret_cast<uint32_t*>(&s_h[nc]), st);
+  __syncthreads();
+  int32_t* hb = a.bhist + (int64_t)blockIdx.x * nc;
+  for (int c = tid; c < nc; c += 1024) hb[c] = s_h[c];
+  if (tid == 0) a.bstat[blockIdx.x] = (uint32_t)s_h[nc];
+}
+
+template <typename Real>
+__global__ void k_setup(SysArgs<Real> a) {
   int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t c = tid; c < a.n_cells; c += stride) a.count[c] = 0;
-  if (a.flags & MD_ACCUM_F32_ATOMIC)
-    for (int64_t i = tid; i < 3 * a.n; i += stride) a.facc[i] = 0.f;
-  if (a.flags & MD_DIAG_COUNTERS)
-    for (int64_t i = tid; i < a.n; i += stride) a.paircount[a.n + i] = 0;
-  int nt = a.n_types;
-  for (int64_t e = tid; e < nt * nt; e += stride) {
-    int ti = (int)(e / nt), tj = (int)(e % nt);
-    double s = 0.5 * (tt.sigma[ti] + tt.sigma[tj]);
-    double ep = sqrt(tt.eps[ti] * tt.eps[tj]);
-    double s2 = s * s, s6 = s2 * s2 * s2;
-    a.lj[2 * e + 0] = (Real)(4.0 * ep * s6 * s6);
-    a.lj[2 * e + 1] = (Real)(4.0 * ep * s6);
-  }
+  for (int64_t i = tid; i < a.n; i += stride) clear_atom(a, i);
   if (tid == 0) {
     a.hdr->status = 0;
-    a.hdr->diag[0] = 0;
-    a.hdr->diag[1] = 0;
-    a.hdr->diag[2] = 0;
-    a.hdr->diag[3] = 0;
+    for (int k = 0; k < 4; ++k) a.hdr->diag[k] = 0;
   }
 }
 
@@ -80,115 +118,147 @@ __global__ void k_bin_count(SysArgs<Real> a) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   uint32_t st = 0;
-  Real x = wrap_coord(a.pos_in[3 * i + 0], a.L[0], st);
-  Real y = wrap_coord(a.pos_in[3 * i + 1], a.L[1], st);
-  Real z = wrap_coord(a.pos_in[3 * i + 2], a.L[2], st);
-  int t = a.type_in[i];
-  if (t < 0 || t >= a.n_types) st |= MD_STATUS_BAD_TYPE;
-  int cx = cell_coord(x, a.inv_w[0], a.nx);
-  int cy = cell_coord(y, a.inv_w[1], a.ny);
-  int cz = cell_coord(z, a.inv_w[2], a.nz);
-  int c = (cz * a.ny + cy) * a.nx + cx;
+  const int c = cell_of(a, i, st);
   a.cell[i] = c;
   a.rank[i] = atomicAdd(&a.count[c], 1);
   if (st) atomicOr(&a.hdr->status, st);
 }
 
-// Exclusive scan of count[0..n_cells) into start[], start[n_cells] = n. One
-// workgroup of 1024 threads walks the array in chunks of 4096 with a running carry.
-__global__ __launch_bounds__(1024) void k_scan(const int32_t* count, int32_t* start,
-                                               int64_t n_cells) {
+// One workgroup of 1024 threads. With per-block histograms: per cell, the blocks'
+// counts become exclusive offsets (in place) and their total the cell count. Then the
+// exclusive scan of the counts into start[] (start[n_cells] = n), in chunks of 4096
+// with a running carry, the mixed LJ table, and (own_header) the status word.
+template <typename Real>
+__global__ __launch_bounds__(1024) void k_bin_scan(SysArgs<Real> a, TypeTable tt,
+                                                   int own_header) {
   __shared__ int32_t s[1024];
   __shared__ int32_t carry;
-  int t = threadIdx.x;
+  const int t = threadIdx.x;
+  const int64_t nc = a.n_cells;
+  const int B = a.bin_blocks;
+  if (B > 0) {
+    for (int64_t c = t; c < nc; c += 1024) {
+      int32_t acc = 0;
+      for (int b = 0; b < B; ++b) {
+        const int32_t v = a.bhist[(int64_t)b * nc + c];
+        a.bhist[(int64_t)b * nc + c] = acc;
+        acc += v;
+      }
+      a.count[c] = acc;
+    }
+  }
   if (t == 0) carry = 0;
   __syncthreads();
-  for (int64_t base = 0; base < n_cells; base += 4096) {
+  for (int64_t base = 0; base < nc; base += 4096) {
     int32_t v[4];
     int32_t sum = 0;
     for (int k = 0; k < 4; ++k) {
-      int64_t idx = base + 4 * t + k;
-      v[k] = idx < n_cells ? count[idx] : 0;
+      const int64_t idx = base + 4 * t + k;
+      v[k] = idx < nc ? a.count[idx] : 0;
       sum += v[k];
     }
     s[t] = sum;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {   // inclusive Hillis-Steele scan
-      int32_t add = t >= off ? s[t - off] : 0;
+      const int32_t add = t >= off ? s[t - off] : 0;
       __syncthreads();
       s[t] += add;
       __syncthreads();
     }
     int32_t run = carry + s[t] - sum;             // exclusive prefix of this thread
     for (int k = 0; k < 4; ++k) {
-      int64_t idx = base + 4 * t + k;
-      if (idx < n_cells) start[idx] = run;
+      const int64_t idx = base + 4 * t + k;
+      if (idx < nc) a.start[idx] = run;
       run += v[k];
     }
     __syncthreads();
     if (t == 1023) carry += s[1023];
     __syncthreads();
   }
-  if (t == 0) start[n_cells] = carry;
+  if (t == 0) a.start[nc] = carry;
+  const int nt = a.n_types;
+  for (int e = t; e < nt * nt; e += 1024) {
+    const int ti = e / nt, tj = e % nt;
+    const double sg = 0.5 * (tt.sigma[ti] + tt.sigma[tj]);
+    const double ep = sqrt(tt.eps[ti] * tt.eps[tj]);
+    const double s2 = sg * sg, s6 = s2 * s2 * s2;
+    a.lj[2 * e + 0] = (Real)(4.0 * ep * s6 * s6);
+    a.lj[2 * e + 1] = (Real)(4.0 * ep * s6);
+  }
+  if (own_header && t == 0) {
+    uint32_t st = 0;
+    for (int b = 0; b < B; ++b) st |= a.bstat[b];
+    a.hdr->status = st;
+    for (int k = 0; k < 4; ++k) a.hdr->diag[k] = 0;
+  }
 }
 
 template <typename Real>
 __global__ void k_scatter(SysArgs<Real> a) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
-  a.unsorted[a.start[a.cell[i]] + a.rank[i]] = (int32_t)i;
+  const int c = a.cell[i];
+  int32_t slot = a.start[c] + a.rank[i];
+  if (a.bin_blocks > 0) slot += a.bhist[(i / a.bin_chunk) * a.n_cells + c];
+  a.unsorted[slot] = (int32_t)i;
+}
+
+// Sort key of an atom: (wrapped x as float32 bits, original index). Wrapped x is >= +0,
+// where the bits of a float order as its value.
+template <typename Real>
+__device__ inline unsigned long long sort_key(const SysArgs<Real>& a, int32_t i) {
+  uint32_t st = 0;
+  const float x = (float)wrap_coord(a.pos_in[3 * (int64_t)i], a.L[0], st) + 0.f;
+  return ((unsigned long long)__builtin_bit_cast(uint32_t, x) << 32) | (uint32_t)i;
 }
 
 // One workgroup per cell. Each member's position in the cell is the number of members
-// that precede it in (wrapped x, original index) order, counted over LDS chunks of the
-// member list, so any cell occupancy is handled.
+// with a smaller key, counted over LDS chunks of the member list, so any cell
+// occupancy is handled.
 template <typename Real>
 __global__ __launch_bounds__(256) void k_cell_sort(SysArgs<Real> a) {
   constexpr int kChunk = 1024;
   constexpr int kPer = kChunk / 256;
-  __shared__ int32_t s_idx[kChunk];
-  __shared__ Real s_x[kChunk];
-  int64_t c = blockIdx.x;
-  int32_t s0 = a.start[c];
-  int32_t m = a.start[c + 1] - s0;
+  __shared__ unsigned long long s_key[kChunk];
+  const int64_t c = blockIdx.x;
+  const int32_t s0 = a.start[c];
+  const int32_t m = a.start[c + 1] - s0;
   for (int32_t a0 = 0; a0 < m; a0 += kChunk) {
+    const int kk = min(kPer, (m - a0 + 255) / 256);   // member slots in use (uniform)
     int32_t my_idx[kPer];
-    Real my_x[kPer];
+    unsigned long long my_key[kPer];
     int32_t my_rank[kPer];
     for (int k = 0; k < kPer; ++k) {
-      int32_t e = a0 + (int32_t)threadIdx.x + 256 * k;
-      my_idx[k] = e < m ? a.unsorted[s0 + e] : -1;
-      uint32_t st = 0;
-      my_x[k] = my_idx[k] >= 0 ? wrap_coord(a.pos_in[3 * (int64_t)my_idx[k]], a.L[0], st) : Real(0);
+      const int32_t e = a0 + (int32_t)threadIdx.x + 256 * k;
+      my_idx[k] = (k < kk && e < m) ? a.unsorted[s0 + e] : -1;
+      my_key[k] = my_idx[k] >= 0 ? sort_key(a, my_idx[k]) : ~0ull;
       my_rank[k] = 0;
     }
     for (int32_t b0 = 0; b0 < m; b0 += kChunk) {
-      int32_t mb = min(kChunk, m - b0);
+      const int32_t mb = min(kChunk, m - b0);
       __syncthreads();
-      for (int32_t e = threadIdx.x; e < mb; e += 256) {
-        const int32_t i = a.unsorted[s0 + b0 + e];
-        uint32_t st = 0;
-        s_idx[e] = i;
-        s_x[e] = wrap_coord(a.pos_in[3 * (int64_t)i], a.L[0], st);
-      }
+      for (int32_t e = threadIdx.x; e < mb; e += 256) s_key[e] = sort_key(a, a.unsorted[s0 + b0 + e]);
+      for (int32_t e = mb + (int32_t)threadIdx.x; e < ((mb + 3) & ~3); e += 256) s_key[e] = ~0ull;
       __syncthreads();
-      for (int32_t e = 0; e < mb; ++e) {
-        const int32_t v = s_idx[e];
-        const Real xv = s_x[e];
-        for (int k = 0; k < kPer; ++k)
-          my_rank[k] += (xv < my_x[k] || (xv == my_x[k] && v < my_idx[k])) ? 1 : 0;
+      for (int32_t e = 0; e < mb; e += 4) {
+        const unsigned long long k0 = s_key[e], k1 = s_key[e + 1], k2 = s_key[e + 2],
+                                 k3 = s_key[e + 3];
+        for (int k = 0; k < kPer; ++k) {
+          if (k < kk)
+            my_rank[k] += (k0 < my_key[k]) + (k1 < my_key[k]) + (k2 < my_key[k]) + (k3 < my_key[k]);
+        }
       }
     }
     for (int k = 0; k < kPer; ++k) {
-      int32_t i = my_idx[k];
+      const int32_t i = my_idx[k];
       if (i < 0) continue;
       uint32_t st = 0;
-      Real x = wrap_coord(a.pos_in[3 * (int64_t)i + 0], a.L[0], st);
-      Real y = wrap_coord(a.pos_in[3 * (int64_t)i + 1], a.L[1], st);
-      Real z = wrap_coord(a.pos_in[3 * (int64_t)i + 2], a.L[2], st);
+      const Real x = wrap_coord(a.pos_in[3 * (int64_t)i + 0], a.L[0], st);
+      const Real y = wrap_coord(a.pos_in[3 * (int64_t)i + 1], a.L[1], st);
+      const Real z = wrap_coord(a.pos_in[3 * (int64_t)i + 2], a.L[2], st);
       int t = a.type_in[i];
       if (t < 0 || t >= a.n_types) t = 0;
-      int32_t d = s0 + my_rank[k];
+      const int32_t d = s0 + my_rank[k];
       P4<Real> p;
       p.x = x;
       p.y = y;
@@ -211,18 +281,31 @@ hipError_t launch_binning(const SysArgs<Real>& a, const double* sigma, const dou
     tt.sigma[t] = t < a.n_types ? sigma[t] : 0.0;
     tt.eps[t] = t < a.n_types ? eps[t] : 0.0;
   }
-  int64_t work = a.n_cells;
-  if (a.n_types * a.n_types > work) work = a.n_types * a.n_types;
-  if (3 * a.n > work) work = 3 * a.n;
-  int64_t blocks = (work + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_setup<Real>, dim3((unsigned)blocks), dim3(256), 0, stream, a, tt);
+  int own_header = 1;
+  if (a.n > 0 && a.bin_blocks > 0) {
+    const size_t shmem = sizeof(int32_t) * (size_t)(a.n_cells + 1);
+    hipLaunchKernelGGL(k_bin_hist<Real>, dim3((unsigned)a.bin_blocks), dim3(1024), shmem, stream,
+                       a);
+  } else if (a.n > 0) {
+    int64_t work = a.n_cells > a.n ? a.n_cells : a.n;
+    int64_t blocks = (work + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_setup<Real>, dim3((unsigned)blocks), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(k_bin_count<Real>, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0,
+                       stream, a);
+    own_header = 0;
+  }
+  SysArgs<Real> as = a;
+  if (a.n == 0) {
+    // nothing binned: every cell is empty
+    as.bin_blocks = 0;
+    hipLaunchKernelGGL(k_setup<Real>, dim3((unsigned)((a.n_cells + 255) / 256 > 4096 ? 4096 : (a.n_cells + 255) / 256)),
+                       dim3(256), 0, stream, as);
+  }
+  hipLaunchKernelGGL(k_bin_scan<Real>, dim3(1), dim3(1024), 0, stream, as, tt, own_header);
   if (a.n == 0) return hipGetLastError();
-  unsigned nb = (unsigned)((a.n + 255) / 256);
-  hipLaunchKernelGGL(k_bin_count<Real>, dim3(nb), dim3(256), 0, stream, a);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, stream, (const int32_t*)a.count, a.start,
-                     a.n_cells);
-  hipLaunchKernelGGL(k_scatter<Real>, dim3(nb), dim3(256), 0, stream, a);
+  hipLaunchKernelGGL(k_scatter<Real>, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, stream,
+                     a);
   hipLaunchKernelGGL(k_cell_sort<Real>, dim3((unsigned)a.n_cells), dim3(256), 0, stream, a);
   return hipGetLastError();
 }

@@ -17,6 +17,9 @@ constexpr int kPairThreads = 256;    // threads of one half-shell pair workgroup
 constexpr int kFsSplit = 1;          // full-shell workgroups per home cell
 constexpr int64_t kMaxCells = 1 << 24;
 constexpr int64_t kMaxAtoms = (int64_t)1 << 30;
+constexpr int kBinLdsCells = 32768;  // largest grid binned with a per-block LDS histogram
+constexpr int kBinMaxBlocks = 64;    // blocks of that pass
+constexpr int kBinMinChunk = 4096;   // atoms per block at least
 
 // Workspace header (first 256 bytes).
 struct WsHeader {
@@ -41,7 +44,9 @@ struct Plan {
   int real_bytes;               // 4 or 8
   // byte offsets
   size_t off_count, off_start, off_cell, off_rank, off_unsorted, off_pos, off_type, off_perm,
-      off_part, off_facc, off_epart, off_lj, off_paircount, total;
+      off_part, off_facc, off_epart, off_lj, off_paircount, off_bhist, off_bstat, total;
+  int bin_blocks;               // blocks of the LDS-histogram binning pass (0: global atomics)
+  int64_t bin_chunk;            // atoms per such block
 };
 
 // Computes the grid and workspace layout; returns MD_OK or an error code.
@@ -72,9 +77,12 @@ struct SysArgs {
   Real* lj;                    // [n_types^2][2] (c12, c6)
   int32_t* paircount;          // [2][n]: caller order (after finalize), sorted order (pass)
   long long* acc64;            // [3][n] per-atom fixed-point sums (full-shell path)
-  unsigned int* work;          // [8] per-XCD work counters of the full-shell kernel
+  int32_t* bhist;              // [bin_blocks][n_cells] per-block cell counts, then offsets
+  uint32_t* bstat;             // [bin_blocks] per-block status bits
   // scalars
   int64_t n, n_cells, n_tasks;
+  int bin_blocks;
+  int64_t bin_chunk;
   int nx, ny, nz, n_types;
   Real L[3];                   // box (rounded once to Real)
   Real inv_w[3];               // n_d / L_d

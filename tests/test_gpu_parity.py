@@ -221,6 +221,56 @@ def test_clustered_cell_beyond_one_tile(gpu):
         assert err32["max_norm"] <= 1e-5 and err32["rms"] <= 1e-5, (flags, err32)
 
 
+def _lattice_blob(rng, origin, n_side, spacing, jitter):
+    g = np.arange(n_side) * spacing
+    pts = np.array([[x, y, z] for x in g for y in g for z in g], dtype=np.float64)
+    return origin + pts + rng.uniform(-jitter, jitter, pts.shape)
+
+
+def test_fullshell_multi_pass(gpu):
+    """8,000 atoms in a 3x3x3 grid: every home cell sees all of them, more than one LDS
+    load of neighbours, so the float32 kernel stages and filters in several passes."""
+    _say("case: 8,000 atoms, 37 A box, neighbour list beyond LDS")
+    rng = np.random.default_rng(11)
+    L = 37.0
+    pos = np.mod(_lattice_blob(rng, np.zeros(3), 20, 1.85, 0.3), L)
+    pos = pos.astype(np.float32).astype(np.float64)
+    n = len(pos)
+    t = rng.integers(0, 2, n).astype(np.int32)
+    q = rng.normal(0, 0.3, n)
+    p = dict(box=(L, L, L), r_cut=12.0, r_switch=10.0, coulomb_k=W.COULOMB_K,
+             sigma=np.array([1.0, 1.2]), epsilon=np.array([0.05, 0.1]), flags=0)
+    f, e, ws, cnt = run(p, pos, t, q, gpu, flags=api.DIAG_COUNTERS)
+    _check_fp32(p, pos, t, q, f, e, cnt)
+
+
+def test_global_atomic_binning_path(gpu):
+    """A 400 A box has 33^3 cells, more than the per-block LDS histogram holds, so the
+    binning takes the global-atomic path; atoms sit in dense blobs, one across the
+    periodic corner."""
+    _say("case: 400 A box, 35,937 cells, 3 blobs of 1,728 atoms")
+    rng = np.random.default_rng(12)
+    L = 400.0
+    blobs = [_lattice_blob(rng, o, 12, 1.9, 0.3) for o in
+             (np.array([30.0, 40.0, 50.0]), np.array([200.0, 210.0, 190.0]),
+              np.array([390.0, 392.0, 389.0]))]
+    pos = np.mod(np.vstack(blobs), L).astype(np.float32).astype(np.float64)
+    n = len(pos)
+    t = rng.integers(0, 3, n).astype(np.int32)
+    q = rng.normal(0, 0.5, n)
+    p = dict(box=(L, L, L), r_cut=12.0, r_switch=10.0, coulomb_k=W.COULOMB_K,
+             sigma=np.array([2.5, 3.0, 3.5]), epsilon=np.array([0.05, 0.1, 0.15]), flags=0)
+    lay = api.workspace_layout(p, n)
+    assert lay["n_cells"] == 33 ** 3
+    f, e, ws, cnt = run(p, pos, t, q, gpu, flags=api.DIAG_COUNTERS)
+    _check_fp32(p, pos, t, q, f, e, cnt)
+    f64, e64, _, cnt64 = run(p, pos, t, q, gpu, double=True, flags=api.DIAG_COUNTERS)
+    r = _ref(p, pos, t, q)
+    err = force_errors(f64, r.force, r.abs_sum)
+    assert err["max_norm"] <= 1e-12 and e64 == pytest.approx(r.energy, rel=1e-12)
+    assert np.array_equal(cnt64, r.count)
+
+
 def test_empty_and_single_atom(gpu):
     _say("case: n = 0 and n = 1")
     import torch
