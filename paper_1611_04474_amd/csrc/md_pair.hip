@@ -16,16 +16,12 @@
 // in a fixed order; the finalize kernel adds the 27 partials of an atom in 64-bit
 // fixed point.
 //
-// Two data-flow variants of the same stage:
-//   predicated -- one home atom per lane; the lane walks the neighbour tile and
-//                 evaluates the force under the cutoff predicate, so lanes whose
-//                 candidate fails idle through the force arithmetic (the conditional
-//                 data flow that leaves the force unit underused, Section 4.1);
-//   compacted  -- the cutoff filter runs over 64 candidates per wave instruction and
-//                 appends the passing pairs to a per-wave LDS queue with a wave ballot
-//                 and prefix count; the force stage then consumes the queue 64 pairs at
-//                 a time with every lane busy (the multi-producer single-consumer
-//                 stream of Section 4.2 and Algorithm 3).
+// This is the predicated data flow: one home atom per lane; the lane walks the
+// neighbour tile and evaluates the force under the cutoff predicate, so lanes whose
+// candidate fails idle through the force arithmetic -- the conditional data flow that
+// leaves the force unit of the HLS design underused (Section 5.1). It serves the
+// float64 path (bit-for-bit the oracle's predicate) and, in float32, the
+// MD_PAIR_PREDICATED comparison with the compacted full-shell kernel.
 #include "md_common.hpp"
 
 namespace md {

@@ -1,7 +1,7 @@
 // Compacted pair kernel, full shell: the loop order of Algorithm 1 (Section 2.1)
 // -- foreach home cell, foreach of its 27 neighbour cells, foreach home atom,
 // foreach neighbour atom, test the cutoff and accumulate the force on the home atom --
-// with the dynamic data flow of the enhanced design (Section 4.2, Fig. 4, Algorithm 3):
+// with the dynamic data flow of the enhanced design (Section 5.2, Fig. 4; Algorithm 3):
 // several cutoff filters feed one force stage through FIFOs, and the force stage only
 // ever works on pairs that passed.
 //
