@@ -141,14 +141,12 @@ template SysArgs<double> make_args<double>(const md_params*, const Plan&, int64_
                                            const double*, const int32_t*, const double*,
                                            double*, double*, void*);
 
+// Synchronous argument checks of one force call; fills the plan.
 template <typename Real>
-static md_status forces_impl(const md_params* p, int64_t n, const Real* pos,
-                             const int32_t* type, const Real* q, Real* force, double* energy,
-                             void* ws, size_t ws_bytes, void* stream,
-                             uint32_t stages = MD_STAGE_ALL) {
-  if (stages & ~(uint32_t)MD_STAGE_ALL) return MD_ERR_INVALID_ARG;
-  Plan pl;
-  md_status s = make_plan(p, n, (int)sizeof(Real), &pl);
+static md_status check_call(const md_params* p, int64_t n, const Real* pos, const int32_t* type,
+                            const Real* q, const Real* force, const double* energy,
+                            const void* ws, size_t ws_bytes, Plan* pl) {
+  md_status s = make_plan(p, n, (int)sizeof(Real), pl);
   if (s != MD_OK) return s;
   if (!energy || ((uintptr_t)energy & 7)) return MD_ERR_INVALID_ARG;
   if (n > 0) {
@@ -157,10 +155,40 @@ static md_status forces_impl(const md_params* p, int64_t n, const Real* pos,
       return MD_ERR_INVALID_ARG;
     if ((uintptr_t)type & 3) return MD_ERR_INVALID_ARG;
   }
-  if (!ws || ((uintptr_t)ws & 255) || ws_bytes < pl.total) return MD_ERR_WORKSPACE;
+  if (!ws || ((uintptr_t)ws & 255) || ws_bytes < pl->total) return MD_ERR_WORKSPACE;
+  return MD_OK;
+}
+
+// Systems that may share one batched launch: same flags and the same type table.
+static bool same_kind(const md_params* x, const md_params* y) {
+  if (x->flags != y->flags || x->n_types != y->n_types || x->r_cut != y->r_cut ||
+      x->r_switch != y->r_switch || x->coulomb_k != y->coulomb_k)
+    return false;
+  for (int t = 0; t < x->n_types; ++t)
+    if (x->sigma[t] != y->sigma[t] || x->epsilon[t] != y->epsilon[t]) return false;
+  return true;
+}
+
+static md_status launch_batch(const Batch<float>& b, const md_params* p, hipStream_t st) {
+  if (b.n == 0) return MD_OK;
+  if (launch_binning_batch(b, make_type_table(p), st) != hipSuccess) return MD_ERR_HIP;
+  if (launch_pair_fs_batch(b, st) != hipSuccess) return MD_ERR_HIP;
+  if (launch_finalize_batch(b, st) != hipSuccess) return MD_ERR_HIP;
+  return MD_OK;
+}
+
+template <typename Real>
+static md_status forces_impl(const md_params* p, int64_t n, const Real* pos,
+                             const int32_t* type, const Real* q, Real* force, double* energy,
+                             void* ws, size_t ws_bytes, void* stream,
+                             uint32_t stages = MD_STAGE_ALL) {
+  if (stages & ~(uint32_t)MD_STAGE_ALL) return MD_ERR_INVALID_ARG;
+  Plan pl;
+  md_status s = check_call<Real>(p, n, pos, type, q, force, energy, ws, ws_bytes, &pl);
+  if (s != MD_OK) return s;
   SysArgs<Real> a = make_args<Real>(p, pl, n, pos, type, q, force, energy, ws);
   hipStream_t st = (hipStream_t)stream;
-  if ((stages & MD_STAGE_BIN) && launch_binning<Real>(a, p->sigma, p->epsilon, st) != hipSuccess)
+  if ((stages & MD_STAGE_BIN) && launch_binning<Real>(a, make_type_table(p), st) != hipSuccess)
     return MD_ERR_HIP;
   if ((stages & MD_STAGE_PAIR) && launch_pair<Real>(a, st) != hipSuccess) return MD_ERR_HIP;
   if ((stages & MD_STAGE_FINALIZE) && launch_finalize<Real>(a, st) != hipSuccess)
@@ -223,22 +251,41 @@ md_status md_forces_batched(const md_system* sys, int32_t n_sys, void* stream) {
   if (n_sys < 0 || (n_sys > 0 && !sys)) return MD_ERR_INVALID_ARG;
   for (int32_t k = 0; k < n_sys; ++k) {
     md::Plan pl;
-    md_status s = md::make_plan(&sys[k].p, sys[k].n_atoms, 4, &pl);
+    md_status s = md::check_call<float>(&sys[k].p, sys[k].n_atoms, sys[k].d_pos, sys[k].d_type,
+                                        sys[k].d_charge, sys[k].d_force, sys[k].d_energy,
+                                        sys[k].d_ws, sys[k].ws_bytes, &pl);
     if (s != MD_OK) return s;
-    if (!sys[k].d_ws || ((uintptr_t)sys[k].d_ws & 255) || sys[k].ws_bytes < pl.total)
-      return MD_ERR_WORKSPACE;
-    if (!sys[k].d_energy) return MD_ERR_INVALID_ARG;
-    if (sys[k].n_atoms > 0 &&
-        (!sys[k].d_pos || !sys[k].d_type || !sys[k].d_charge || !sys[k].d_force))
-      return MD_ERR_INVALID_ARG;
   }
+  // Systems binned through LDS histograms and forced by the compacted kernel go in
+  // batches of up to kBatchMax systems of one kind, in input order; any other system is
+  // evaluated on its own.
+  hipStream_t st = (hipStream_t)stream;
+  md::Batch<float> b;
+  b.n = 0;
+  const md_params* kind = nullptr;
   for (int32_t k = 0; k < n_sys; ++k) {
-    md_status s = md_forces_f32(&sys[k].p, sys[k].n_atoms, sys[k].d_pos, sys[k].d_type,
-                                sys[k].d_charge, sys[k].d_force, sys[k].d_energy, sys[k].d_ws,
-                                sys[k].ws_bytes, stream);
-    if (s != MD_OK) return s;
+    md::Plan pl;
+    md::make_plan(&sys[k].p, sys[k].n_atoms, 4, &pl);
+    const bool batchable = sys[k].n_atoms > 0 && pl.bin_blocks > 0 &&
+                           !(sys[k].p.flags & MD_PAIR_PREDICATED);
+    if (!batchable) {
+      md_status s = md_forces_f32(&sys[k].p, sys[k].n_atoms, sys[k].d_pos, sys[k].d_type,
+                                  sys[k].d_charge, sys[k].d_force, sys[k].d_energy, sys[k].d_ws,
+                                  sys[k].ws_bytes, stream);
+      if (s != MD_OK) return s;
+      continue;
+    }
+    if (b.n == md::kBatchMax || (b.n > 0 && !md::same_kind(kind, &sys[k].p))) {
+      md_status s = md::launch_batch(b, kind, st);
+      if (s != MD_OK) return s;
+      b.n = 0;
+    }
+    if (b.n == 0) kind = &sys[k].p;
+    b.sys[b.n++] = md::make_args<float>(&sys[k].p, pl, sys[k].n_atoms, sys[k].d_pos,
+                                        sys[k].d_type, sys[k].d_charge, sys[k].d_force,
+                                        sys[k].d_energy, sys[k].d_ws);
   }
-  return MD_OK;
+  return md::launch_batch(b, kind, st);
 }
 
 md_status md_read_device_status(const void* d_ws, void* stream, uint32_t* bits) {

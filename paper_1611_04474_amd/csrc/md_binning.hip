@@ -27,11 +27,6 @@
 namespace md {
 namespace {
 
-struct TypeTable {
-  double sigma[kMaxTypes];
-  double eps[kMaxTypes];
-};
-
 template <typename Real>
 __device__ inline Real wrap_coord(Real x, Real L, uint32_t& st) {
   if (x != x) {
@@ -79,13 +74,13 @@ __device__ inline void clear_atom(const SysArgs<Real>& a, int64_t i) {
 }
 
 template <typename Real>
-__global__ __launch_bounds__(1024) void k_bin_hist(SysArgs<Real> a) {
+__device__ inline void bin_hist(const SysArgs<Real>& a, int64_t blk) {
   extern __shared__ int32_t s_h[];   // [n_cells] counts, then the status bits
   const int nc = (int)a.n_cells;
   const int tid = threadIdx.x;
   for (int c = tid; c <= nc; c += 1024) s_h[c] = 0;
   __syncthreads();
-  const int64_t i0 = (int64_t)blockIdx.x * a.bin_chunk;
+  const int64_t i0 = blk * a.bin_chunk;
   const int64_t i1 = i0 + a.bin_chunk < a.n ? i0 + a.bin_chunk : a.n;
   uint32_t st = 0;
   for (int64_t i = i0 + tid; i < i1; i += 1024) {
@@ -96,9 +91,18 @@ __global__ __launch_bounds__(1024) void k_bin_hist(SysArgs<Real> a) {
   }
   if (st) atomicOr(reinterpret_cast<uint32_t*>(&s_h[nc]), st);
   __syncthreads();
-  int32_t* hb = a.bhist + (int64_t)blockIdx.x * nc;
+  int32_t* hb = a.bhist + blk * nc;
   for (int c = tid; c < nc; c += 1024) hb[c] = s_h[c];
-  if (tid == 0) a.bstat[blockIdx.x] = (uint32_t)s_h[nc];
+  if (tid == 0) a.bstat[blk] = (uint32_t)s_h[nc];
+}
+
+template <typename Real>
+__global__ __launch_bounds__(1024) void k_bin_hist(SysArgs<Real> a) { bin_hist(a, blockIdx.x); }
+
+__global__ __launch_bounds__(1024) void k_bin_hist_batch(Batch<float> b) {
+  int64_t blk;
+  const int s = b.pick(blockIdx.x, blk);
+  bin_hist(b.sys[s], blk);
 }
 
 template <typename Real>
@@ -129,8 +133,7 @@ __global__ void k_bin_count(SysArgs<Real> a) {
 // exclusive scan of the counts into start[] (start[n_cells] = n), in chunks of 4096
 // with a running carry, the mixed LJ table, and (own_header) the status word.
 template <typename Real>
-__global__ __launch_bounds__(1024) void k_bin_scan(SysArgs<Real> a, TypeTable tt,
-                                                   int own_header) {
+__device__ inline void bin_scan(const SysArgs<Real>& a, const TypeTable& tt, int own_header) {
   __shared__ int32_t s[1024];
   __shared__ int32_t carry;
   const int t = threadIdx.x;
@@ -194,13 +197,34 @@ __global__ __launch_bounds__(1024) void k_bin_scan(SysArgs<Real> a, TypeTable tt
 }
 
 template <typename Real>
-__global__ void k_scatter(SysArgs<Real> a) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(1024) void k_bin_scan(SysArgs<Real> a, TypeTable tt,
+                                                   int own_header) {
+  bin_scan(a, tt, own_header);
+}
+
+__global__ __launch_bounds__(1024) void k_bin_scan_batch(Batch<float> b, TypeTable tt) {
+  int64_t blk;
+  const int s = b.pick(blockIdx.x, blk);
+  bin_scan(b.sys[s], tt, 1);
+}
+
+template <typename Real>
+__device__ inline void scatter(const SysArgs<Real>& a, int64_t blk) {
+  const int64_t i = blk * 256 + threadIdx.x;
   if (i >= a.n) return;
   const int c = a.cell[i];
   int32_t slot = a.start[c] + a.rank[i];
   if (a.bin_blocks > 0) slot += a.bhist[(i / a.bin_chunk) * a.n_cells + c];
   a.unsorted[slot] = (int32_t)i;
+}
+
+template <typename Real>
+__global__ __launch_bounds__(256) void k_scatter(SysArgs<Real> a) { scatter(a, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void k_scatter_batch(Batch<float> b) {
+  int64_t blk;
+  const int s = b.pick(blockIdx.x, blk);
+  scatter(b.sys[s], blk);
 }
 
 // Sort key of an atom: (wrapped x as float32 bits, original index). Wrapped x is >= +0,
@@ -216,11 +240,10 @@ __device__ inline unsigned long long sort_key(const SysArgs<Real>& a, int32_t i)
 // with a smaller key, counted over LDS chunks of the member list, so any cell
 // occupancy is handled.
 template <typename Real>
-__global__ __launch_bounds__(256) void k_cell_sort(SysArgs<Real> a) {
+__device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
   constexpr int kChunk = 1024;
   constexpr int kPer = kChunk / 256;
   __shared__ unsigned long long s_key[kChunk];
-  const int64_t c = blockIdx.x;
   const int32_t s0 = a.start[c];
   const int32_t m = a.start[c + 1] - s0;
   for (int32_t a0 = 0; a0 < m; a0 += kChunk) {
@@ -271,16 +294,28 @@ __global__ __launch_bounds__(256) void k_cell_sort(SysArgs<Real> a) {
   }
 }
 
+template <typename Real>
+__global__ __launch_bounds__(256) void k_cell_sort(SysArgs<Real> a) { cell_sort(a, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void k_cell_sort_batch(Batch<float> b) {
+  int64_t blk;
+  const int s = b.pick(blockIdx.x, blk);
+  cell_sort(b.sys[s], blk);
+}
+
 }  // namespace
 
-template <typename Real>
-hipError_t launch_binning(const SysArgs<Real>& a, const double* sigma, const double* eps,
-                          hipStream_t stream) {
+TypeTable make_type_table(const md_params* p) {
   TypeTable tt;
   for (int t = 0; t < kMaxTypes; ++t) {
-    tt.sigma[t] = t < a.n_types ? sigma[t] : 0.0;
-    tt.eps[t] = t < a.n_types ? eps[t] : 0.0;
+    tt.sigma[t] = t < p->n_types ? p->sigma[t] : 0.0;
+    tt.eps[t] = t < p->n_types ? p->epsilon[t] : 0.0;
   }
+  return tt;
+}
+
+template <typename Real>
+hipError_t launch_binning(const SysArgs<Real>& a, const TypeTable& tt, hipStream_t stream) {
   int own_header = 1;
   if (a.n > 0 && a.bin_blocks > 0) {
     const size_t shmem = sizeof(int32_t) * (size_t)(a.n_cells + 1);
@@ -299,8 +334,9 @@ hipError_t launch_binning(const SysArgs<Real>& a, const double* sigma, const dou
   if (a.n == 0) {
     // nothing binned: every cell is empty
     as.bin_blocks = 0;
-    hipLaunchKernelGGL(k_setup<Real>, dim3((unsigned)((a.n_cells + 255) / 256 > 4096 ? 4096 : (a.n_cells + 255) / 256)),
-                       dim3(256), 0, stream, as);
+    int64_t blocks = (a.n_cells + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_setup<Real>, dim3((unsigned)blocks), dim3(256), 0, stream, as);
   }
   hipLaunchKernelGGL(k_bin_scan<Real>, dim3(1), dim3(1024), 0, stream, as, tt, own_header);
   if (a.n == 0) return hipGetLastError();
@@ -310,9 +346,33 @@ hipError_t launch_binning(const SysArgs<Real>& a, const double* sigma, const dou
   return hipGetLastError();
 }
 
-template hipError_t launch_binning<float>(const SysArgs<float>&, const double*, const double*,
-                                          hipStream_t);
-template hipError_t launch_binning<double>(const SysArgs<double>&, const double*,
-                                           const double*, hipStream_t);
+// Sets cum[] of a batch from per-system block counts.
+template <typename F>
+static int64_t batch_blocks(Batch<float>& b, F per_sys) {
+  b.cum[0] = 0;
+  for (int s = 0; s < b.n; ++s) b.cum[s + 1] = b.cum[s] + per_sys(b.sys[s]);
+  return b.cum[b.n];
+}
+
+hipError_t launch_binning_batch(const Batch<float>& b0, const TypeTable& tt, hipStream_t stream) {
+  Batch<float> b = b0;
+  size_t shmem = 0;
+  for (int s = 0; s < b.n; ++s) {
+    const size_t need = sizeof(int32_t) * (size_t)(b.sys[s].n_cells + 1);
+    shmem = need > shmem ? need : shmem;
+  }
+  int64_t nb = batch_blocks(b, [](const SysArgs<float>& a) { return (int64_t)a.bin_blocks; });
+  hipLaunchKernelGGL(k_bin_hist_batch, dim3((unsigned)nb), dim3(1024), shmem, stream, b);
+  nb = batch_blocks(b, [](const SysArgs<float>&) { return (int64_t)1; });
+  hipLaunchKernelGGL(k_bin_scan_batch, dim3((unsigned)nb), dim3(1024), 0, stream, b, tt);
+  nb = batch_blocks(b, [](const SysArgs<float>& a) { return (a.n + 255) / 256; });
+  hipLaunchKernelGGL(k_scatter_batch, dim3((unsigned)nb), dim3(256), 0, stream, b);
+  nb = batch_blocks(b, [](const SysArgs<float>& a) { return a.n_cells; });
+  hipLaunchKernelGGL(k_cell_sort_batch, dim3((unsigned)nb), dim3(256), 0, stream, b);
+  return hipGetLastError();
+}
+
+template hipError_t launch_binning<float>(const SysArgs<float>&, const TypeTable&, hipStream_t);
+template hipError_t launch_binning<double>(const SysArgs<double>&, const TypeTable&, hipStream_t);
 
 }  // namespace md

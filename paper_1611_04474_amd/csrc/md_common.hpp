@@ -92,20 +92,52 @@ struct SysArgs {
   int full_shell;              // 1: per-atom sums come from the full-shell pair kernel
 };
 
+// Up to kBatchMax systems evaluated by one launch of each kernel of the path. The
+// systems' arguments travel in the kernel argument block; block b of a batched launch
+// belongs to system s with cum[s] <= b < cum[s+1], as its local block b - cum[s].
+constexpr int kBatchMax = 10;   // keeps every batched kernel's arguments under 4 KB
+
+template <typename Real>
+struct Batch {
+  int n;
+  int64_t cum[kBatchMax + 1];
+  SysArgs<Real> sys[kBatchMax];
+
+  __device__ inline int pick(int64_t b, int64_t& local) const {
+    int s = 0;
+    while (s + 1 < n && cum[s + 1] <= b) ++s;
+    local = b - cum[s];
+    return s;
+  }
+};
+
+// Per-type sigma and epsilon, mixed into the LJ table by the binning stage.
+struct TypeTable {
+  double sigma[kMaxTypes];
+  double eps[kMaxTypes];
+};
+
 template <typename Real>
 SysArgs<Real> make_args(const md_params* p, const Plan& pl, int64_t n, const Real* pos,
                         const int32_t* type, const Real* q, Real* force, double* energy,
                         void* ws);
 
 // Launchers (each enqueues on `stream`, returns hipSuccess or an error).
+TypeTable make_type_table(const md_params* p);
 template <typename Real>
-hipError_t launch_binning(const SysArgs<Real>& a, const double* sigma, const double* eps,
-                          hipStream_t stream);
+hipError_t launch_binning(const SysArgs<Real>& a, const TypeTable& tt, hipStream_t stream);
 template <typename Real>
 hipError_t launch_pair(const SysArgs<Real>& a, hipStream_t stream);
 template <typename Real>
 hipError_t launch_finalize(const SysArgs<Real>& a, hipStream_t stream);
 hipError_t launch_pair_fs(const SysArgs<float>& a, hipStream_t stream);
 size_t pair_fs_lds_bytes(int n_types);
+
+// Batched float32 launchers. Every system of the batch has n > 0, uses the LDS-histogram
+// binning (bin_blocks > 0), the compacted full-shell kernel, and the same flags and
+// type table.
+hipError_t launch_binning_batch(const Batch<float>& b, const TypeTable& tt, hipStream_t stream);
+hipError_t launch_pair_fs_batch(const Batch<float>& b, hipStream_t stream);
+hipError_t launch_finalize_batch(const Batch<float>& b, hipStream_t stream);
 
 }  // namespace md

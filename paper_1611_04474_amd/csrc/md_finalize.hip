@@ -36,8 +36,8 @@ __device__ inline float fixed_sum(const float* part, int64_t n, int c, int64_t s
 }
 
 template <typename Real>
-__global__ void k_finalize(SysArgs<Real> a) {
-  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ inline void finalize(const SysArgs<Real>& a, int64_t blk) {
+  int64_t s = blk * 256 + threadIdx.x;
   if (s >= a.n) return;
   const int64_t i = a.perm[s];
   uint32_t st = 0;
@@ -60,8 +60,17 @@ __global__ void k_finalize(SysArgs<Real> a) {
   if (st) atomicOr(&a.hdr->status, st);
 }
 
-__global__ __launch_bounds__(256) void k_energy(const double* epart, int64_t n_tasks,
-                                                double* out, WsHeader* hdr, int halve_diag) {
+template <typename Real>
+__global__ __launch_bounds__(256) void k_finalize(SysArgs<Real> a) { finalize(a, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void k_finalize_batch(Batch<float> b) {
+  int64_t blk;
+  const int s = b.pick(blockIdx.x, blk);
+  finalize(b.sys[s], blk);
+}
+
+__device__ inline void energy(const double* epart, int64_t n_tasks, double* out, WsHeader* hdr,
+                              int halve_diag) {
   if (halve_diag && threadIdx.x < 4) hdr->diag[threadIdx.x] /= 2;
   __shared__ double s[256];
   double acc = 0.0;
@@ -75,6 +84,27 @@ __global__ __launch_bounds__(256) void k_energy(const double* epart, int64_t n_t
   if (threadIdx.x == 0) *out = s[0];
 }
 
+__global__ __launch_bounds__(256) void k_energy(const double* epart, int64_t n_tasks,
+                                                double* out, WsHeader* hdr, int halve_diag) {
+  energy(epart, n_tasks, out, hdr, halve_diag);
+}
+
+template <typename Real>
+__host__ __device__ inline int64_t energy_parts(const SysArgs<Real>& a) {
+  return a.n > 0 ? (a.full_shell ? a.n_cells * kFsSplit : a.n_tasks) : 0;
+}
+
+template <typename Real>
+__host__ __device__ inline int halve_diag(const SysArgs<Real>& a) {
+  return (a.full_shell && (a.flags & MD_DIAG_COUNTERS) && a.n > 0) ? 1 : 0;
+}
+
+__global__ __launch_bounds__(256) void k_energy_batch(Batch<float> b) {
+  int64_t blk;
+  const SysArgs<float>& a = b.sys[b.pick(blockIdx.x, blk)];
+  energy(a.epart, energy_parts(a), a.energy_out, a.hdr, halve_diag(a));
+}
+
 }  // namespace
 
 template <typename Real>
@@ -83,10 +113,18 @@ hipError_t launch_finalize(const SysArgs<Real>& a, hipStream_t stream) {
     unsigned nb = (unsigned)((a.n + 255) / 256);
     hipLaunchKernelGGL(k_finalize<Real>, dim3(nb), dim3(256), 0, stream, a);
   }
-  const int64_t n_part = a.full_shell ? a.n_cells * kFsSplit : a.n_tasks;
-  const int halve = (a.full_shell && (a.flags & MD_DIAG_COUNTERS) && a.n > 0) ? 1 : 0;
   hipLaunchKernelGGL(k_energy, dim3(1), dim3(256), 0, stream, (const double*)a.epart,
-                     a.n > 0 ? n_part : (int64_t)0, a.energy_out, a.hdr, halve);
+                     energy_parts(a), a.energy_out, a.hdr, halve_diag(a));
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_batch(const Batch<float>& b0, hipStream_t stream) {
+  Batch<float> b = b0;
+  b.cum[0] = 0;
+  for (int s = 0; s < b.n; ++s) b.cum[s + 1] = b.cum[s] + (b.sys[s].n + 255) / 256;
+  hipLaunchKernelGGL(k_finalize_batch, dim3((unsigned)b.cum[b.n]), dim3(256), 0, stream, b);
+  for (int s = 0; s < b.n; ++s) b.cum[s + 1] = s + 1;
+  hipLaunchKernelGGL(k_energy_batch, dim3((unsigned)b.n), dim3(256), 0, stream, b);
   return hipGetLastError();
 }
 

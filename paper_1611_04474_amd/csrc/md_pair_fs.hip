@@ -22,7 +22,9 @@
 //              u < rc^2, and the force summed on the home atom in registers.
 // Each home atom is owned by one wave, so no atomics are needed and every sum runs in
 // a fixed order. At the end the 64 lane partials are added per 16-lane row in a fixed
-// DPP order and the four row sums in 64-bit fixed point (2^-32 kcal/mol/A), exactly.
+// DPP order and the four row sums in 64-bit fixed point (2^-32 kcal/mol/A), exactly;
+// lane energies are summed in 64-bit fixed point (2^-24 kcal/mol), so the energy does
+// not depend on how groups of home atoms were spread over the waves either.
 // Every pair is evaluated from both of its atoms, as in Algorithm 1.
 #include "md_common.hpp"
 
@@ -174,8 +176,8 @@ __device__ inline int64_t xcd_unit(int64_t b, int64_t n_units) {
 // and e, and pairs beyond the cutoff need no test (t clamps to 1).
 // kDiag: count filter passes, cutoff passes and filtered slots (MD_DIAG_COUNTERS).
 template <bool kSwitchCoulomb, bool kClamp, bool kDiag>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
-void k_pair_fs(SysArgs<float> a, int cap) {
+__device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<float>& a, int cap,
+                                                              int64_t unit) {
   extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
   const Lds LL = lds_layout(cap, a.n_types);
   uint8_t* sT = s_dyn;
@@ -185,9 +187,6 @@ void k_pair_fs(SysArgs<float> a, int cap) {
   float4* sF = reinterpret_cast<float4*>(s_dyn + LL.f4);
   float* sQ = reinterpret_cast<float*>(s_dyn + LL.q);
 
-  const int64_t n_units = a.n_cells;
-  const int64_t unit = xcd_unit(blockIdx.x, n_units);
-  if (unit >= n_units) return;
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t cellA = unit;
@@ -287,7 +286,7 @@ void k_pair_fs(SysArgs<float> a, int cap) {
   const int iters = H.iters;
   const int n_grp_q = (nA + kQ - 1) / kQ;
   const float R = __builtin_sqrtf(rc2) + kWin;
-  double e_wave = 0.0;
+  long long e_fix = 0;   // energy in units of 2^-24 kcal/mol: exact, order-independent sums
   unsigned long long pass_count = 0, filt_count = 0, slot_count = 0;
   uint32_t st = 0;
   uint16_t* fifo = sFifo + w * kWaveFifo;
@@ -577,20 +576,26 @@ void k_pair_fs(SysArgs<float> a, int cap) {
         }
         pass_count += cnt[k];
       }
-      e_wave += (double)e_lane;
+      {
+        // the group's lane energy in 64-bit fixed point (exact scaling by 2^24, then one
+        // rounding), so the workgroup total does not depend on which wave took which group
+        const float v = e_lane * 16777216.0f;
+        if (!(fabsf(v) < 4.6116860184273879e18f)) st |= MD_STATUS_FIXED_OVERFLOW;
+        else e_fix += __float2ll_rn(v);
+      }
     }
     __syncthreads();
   }
 
   // workgroup energy: each pair was seen from both atoms
-  double* sE = reinterpret_cast<double*>(s_dyn + LL.f4);
-  sE[tid] = e_wave;
+  long long* sE = reinterpret_cast<long long*>(s_dyn + LL.f4);
+  sE[tid] = e_fix;
   __syncthreads();
   for (int off = kThreads / 2; off > 0; off >>= 1) {
     if (tid < off) sE[tid] += sE[tid + off];
     __syncthreads();
   }
-  if (tid == 0) a.epart[unit] = 0.5 * sE[0];
+  if (tid == 0) a.epart[unit] = 0.5 * ((double)sE[0] * 5.9604644775390625e-08);   // 2^-24
   if (st) atomicOr(&a.hdr->status, st);
   if (diag && lane == 0) {
     // candidates of Algorithm 1: every (home atom, other neighbour-list atom), counted
@@ -603,6 +608,26 @@ void k_pair_fs(SysArgs<float> a, int cap) {
     atomicAdd(&a.hdr->diag[2], pass_count);
     atomicAdd(&a.hdr->diag[3], slot_count);
   }
+}
+
+template <bool kSwitchCoulomb, bool kClamp, bool kDiag>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
+void k_pair_fs(SysArgs<float> a, int cap) {
+  const int64_t unit = xcd_unit(blockIdx.x, a.n_cells);
+  if (unit >= a.n_cells) return;
+  pair_fs<kSwitchCoulomb, kClamp, kDiag>(a, cap, unit);
+}
+
+// One launch for a batch: the XCD-aware numbering runs over the cells of all systems.
+template <bool kSwitchCoulomb, bool kClamp, bool kDiag>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
+void k_pair_fs_batch(Batch<float> b, int cap) {
+  const int64_t total = b.cum[b.n];
+  const int64_t g = xcd_unit(blockIdx.x, total);
+  if (g >= total) return;
+  int64_t unit;
+  const int s = b.pick(g, unit);
+  pair_fs<kSwitchCoulomb, kClamp, kDiag>(b.sys[s], cap, unit);
 }
 
 // Neighbour atoms staged in LDS per pass for n_types types (a multiple of 64).
@@ -642,6 +667,39 @@ hipError_t launch_pair_fs(const SysArgs<float>& a, hipStream_t stream) {
       hipLaunchKernelGGL((k_pair_fs<true, false, false>), grid, block, shmem, stream, a, cap);
     else
       hipLaunchKernelGGL((k_pair_fs<false, false, false>), grid, block, shmem, stream, a, cap);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_fs_batch(const Batch<float>& b0, hipStream_t stream) {
+  Batch<float> b = b0;
+  int nt = 1;
+  b.cum[0] = 0;
+  for (int s = 0; s < b.n; ++s) {
+    b.cum[s + 1] = b.cum[s] + b.sys[s].n_cells;
+    nt = b.sys[s].n_types > nt ? b.sys[s].n_types : nt;
+  }
+  const int64_t blocks = 8 * ((b.cum[b.n] + 7) / 8);
+  const int cap = fs_cap(nt);
+  const size_t shmem = pair_fs_lds_bytes(nt);
+  const SysArgs<float>& a = b.sys[0];
+  const bool trunc = (a.flags & MD_COULOMB_TRUNCATED) != 0;
+  const bool clamp = !trunc && a.inv_sw > 0.f;
+  const dim3 grid((unsigned)blocks), block(kThreads);
+  if (a.flags & MD_DIAG_COUNTERS) {
+    if (clamp)
+      hipLaunchKernelGGL((k_pair_fs_batch<true, true, true>), grid, block, shmem, stream, b, cap);
+    else if (!trunc)
+      hipLaunchKernelGGL((k_pair_fs_batch<true, false, true>), grid, block, shmem, stream, b, cap);
+    else
+      hipLaunchKernelGGL((k_pair_fs_batch<false, false, true>), grid, block, shmem, stream, b, cap);
+  } else {
+    if (clamp)
+      hipLaunchKernelGGL((k_pair_fs_batch<true, true, false>), grid, block, shmem, stream, b, cap);
+    else if (!trunc)
+      hipLaunchKernelGGL((k_pair_fs_batch<true, false, false>), grid, block, shmem, stream, b, cap);
+    else
+      hipLaunchKernelGGL((k_pair_fs_batch<false, false, false>), grid, block, shmem, stream, b, cap);
   }
   return hipGetLastError();
 }

@@ -342,3 +342,39 @@ def test_stmv_sampled(gpu):
         _say("step", step, err)
         assert err["max_norm"] <= 1e-5 and err["rms"] <= 1e-5
         assert np.linalg.norm(fh.sum(axis=0)) <= 1e-6 * np.abs(fh).sum()
+
+
+def test_batched_matches_alone(gpu):
+    """Serving form: systems of different sizes in one batched call give bitwise the
+    results of evaluating each alone. 13 systems exceed one launch batch, and one
+    predicated system is evaluated on its own inside the call."""
+    _say("case: 13 serving requests, batched vs alone")
+    import torch
+    from _gpu import to_dev
+    reqs, table = W.serving_trace(n_req=64)
+    picks = [0, 1, 2, 3, 5, 8, 13, 21, 34, 40, 50, 55, 63]
+    systems, alone = [], []
+    for k, r in enumerate(picks):
+        s = W.request_system(reqs[r], table)
+        flags = api.PAIR_PREDICATED if k == 6 else 0
+        p = api.Params.from_dict(s.params(), flags)
+        d = to_dev((s.pos, s.types, s.charges), gpu)
+        f, e = api.forces(p, *d)
+        alone.append((f.clone(), e.clone()))
+        ws = api.alloc_workspace(p, s.n, gpu)
+        ws.fill_(0xAB)   # the batched call must not depend on workspace contents
+        systems.append(dict(params=p, pos=d[0], types=d[1], charges=d[2],
+                            force=torch.full_like(f, float("nan")),
+                            energy=torch.full_like(e, float("nan")), workspace=ws))
+        _say("  request", r, "atoms", s.n, "box", s.box[0])
+    api.forces_batched(systems)
+    torch.cuda.synchronize()
+    for k, (sysd, (f, e)) in enumerate(zip(systems, alone)):
+        assert torch.equal(sysd["force"], f), k
+        assert torch.equal(sysd["energy"], e), k
+        assert api.read_status(sysd["workspace"]) == 0
+    # one of them against the oracle
+    s = W.request_system(reqs[picks[0]], table)
+    r = _ref(s.params(), s.pos, s.types, s.charges)
+    err = force_errors(systems[0]["force"].double().cpu().numpy(), r.force, r.abs_sum)
+    assert err["max_norm"] <= 1e-5 and err["rms"] <= 1e-5, err
