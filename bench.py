@@ -9,7 +9,13 @@ and energy) on inputs already resident in HBM.
 
 Prints ONE JSON line: within-cutoff pair interactions per second, the roofline of the
 pair kernel (algorithmic float32 FLOPs per launch / launch time measured with HIP
-events on the launch stream), and the FP64 oracle timed on the host cores.
+events on the launch stream), the FP64 oracle timed on the host cores, and two more
+forms of the same path:
+  serving  -- 512 requests of 2k-200k atoms (cubes at 0.1 atoms/A^3, Poisson arrivals
+              at 200 req/s), continuous batching against the plain one-at-a-time path,
+              plus a lowered HBM cap and saturating arrival rates;
+  scaling  -- 1,066,628 atoms in a 216.83 A cube, 20 evaluations with positions
+              perturbed by N(0, 0.01 A) between calls.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -24,7 +30,7 @@ import numpy as np
 
 PEAK_FP32_TFLOPS = 157.3       # MI355X published float32 vector peak
 FLOP_PER_CANDIDATE = 8         # filter: 3 sub, 1 mul, 2 fma (fma = 2)
-FLOP_PER_PAIR = 40             # force, switch, accumulation (see DESIGN.md)
+FLOP_PER_PAIR = 40             # force, switch, accumulation
 METRIC = "within-cutoff pair-interactions/s @92k atoms; p50/p99 latency mixed batch"
 
 
@@ -39,14 +45,22 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="wall time budget of the oracle baseline (0 disables it)")
     ap.add_argument("--latency-reps", type=int, default=50)
+    ap.add_argument("--serving-requests", type=int, default=512,
+                    help="requests of the serving form (0 disables it)")
+    ap.add_argument("--scaling-evals", type=int, default=20,
+                    help="evaluations of the 1,066,628-atom scaling shape (0 disables it)")
     return ap.parse_args()
+
+
+def pct(v, q):
+    return float(np.percentile(np.asarray(v), q))
 
 
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(see DESIGN.md for how the path would shard)", file=sys.stderr)
+              "(the multi-GPU decomposition is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -98,6 +112,7 @@ def main():
     bin_ms = [e[0].elapsed_time(e[1]) for e in events]
     pair_ms = [e[1].elapsed_time(e[2]) for e in events]
     fin_ms = [e[2].elapsed_time(e[3]) for e in events]
+    eval_ms = [e[0].elapsed_time(e[3]) for e in events]
     ms_per_step = 1e3 * wall / args.steps
     pair_avg_s = statistics.mean(pair_ms) * 1e-3
     achieved = flop_per_launch / pair_avg_s / 1e12
@@ -110,7 +125,6 @@ def main():
         step()
         torch.cuda.synchronize()
         lat.append(1e3 * (time.perf_counter() - t))
-    lat = np.array(lat)
 
     out = {
         "metric": METRIC,
@@ -133,14 +147,16 @@ def main():
             "r_cut_A": 12.0, "r_switch_A": 10.0, "n_types": 8,
             "pair_mode": args.mode, "accumulation": args.accum,
             "candidates_per_step": n_cand, "filter_passes_per_step": n_filter,
-            "pairs_per_step": n_pairs,
+            "candidates_examined_per_step": n_slots, "pairs_per_step": n_pairs,
         },
         "stage_ms": {"bin": statistics.mean(bin_ms), "pair": statistics.mean(pair_ms),
                      "finalize": statistics.mean(fin_ms)},
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "kind": "plain path, one system per call"},
+        "eval_ms": {"p10": pct(eval_ms, 10), "median": pct(eval_ms, 50), "p90": pct(eval_ms, 90)},
+        "latency_ms": None,
+        "latency_ms_plain_92k": {"p50": pct(lat, 50), "p99": pct(lat, 99),
+                                 "kind": "plain path, one 92,224-atom system per call"},
         "roofline": {
-            "kernel": "pair (filter + force)",
+            "kernel": "k_pair_fs (filter + force)",
             "bound": "alu",
             "achieved": achieved,
             "peak": PEAK_FP32_TFLOPS,
@@ -150,11 +166,100 @@ def main():
             "traffic": None,
         },
     }
+    del ws, force, energy, pos, typ, q
 
+    if args.serving_requests > 0:
+        out["serving"] = serving(args.serving_requests, dev)
+        tr = out["serving"]["scenarios"]["trace_200hz"]["batched"]
+        out["latency_ms"] = {"p50": tr["p50_ms"], "p99": tr["p99_ms"],
+                             "kind": f"serving trace: {args.serving_requests} requests of "
+                                     "2k-200k atoms at 200 req/s, continuous batching"}
+    if args.scaling_evals > 0:
+        out["scaling_1m"] = scaling(args.scaling_evals, dev)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds)
         out["config"]["pairs_oracle_fp64"] = out["cpu_baseline"].pop("n_pairs")
     print(json.dumps(out), flush=True)
+
+
+def serving(n_req, dev):
+    """The trace and saturating variants, continuous batching vs the plain path."""
+    import torch
+    from paper_1611_04474_amd import workloads as W
+    from paper_1611_04474_amd import serving as S
+    reqs, table = W.serving_trace(n_req=n_req)
+    systems = [W.request_system(r, table) for r in reqs]
+    items = S.prepare(systems, dev)
+    pairs = np.array(S.count_pairs(items, dev), dtype=np.int64)
+    arrivals = np.array([r.arrival_s for r in reqs])
+    backend = S.GpuBackend(dev)
+    # warm both paths on a few requests
+    S.run_policy(items[:8], np.zeros(8), backend, 64 << 30)
+    S.replay_plain(items[:8], np.zeros(8), dev)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(6)
+    gaps = rng.exponential(1.0, n_req)
+    out = {"requests": n_req, "mean_atoms": float(np.mean([x.n for x in items])),
+           "pairs_total": int(pairs.sum()), "scenarios": {}}
+
+    def both(name, arr, budget, plain=True):
+        res = {"batched": S.run_policy(items, arr, backend, budget).summary(pairs)}
+        if plain:
+            res["plain"] = S.replay_plain(items, arr, dev).summary(pairs)
+        res["budget_MB"] = budget / 2 ** 20
+        out["scenarios"][name] = res
+
+    both("trace_200hz", arrivals, 64 << 30)
+    both("trace_200hz_cap_64MB", arrivals, 64 << 20, plain=False)
+    both("all_at_t0", np.zeros(n_req), 64 << 30)
+    for rate in (2000.0, 20000.0):
+        arr = np.cumsum(gaps / rate)
+        both(f"poisson_{int(rate)}hz", arr - arr[0], 64 << 30)
+    return out
+
+
+def scaling(n_eval, dev):
+    """20 evaluations of the 1,066,628-atom cube, positions perturbed between calls."""
+    import torch
+    from paper_1611_04474_amd import api
+    from paper_1611_04474_amd import workloads as W
+    s = W.stmv_system()
+    P = api.Params.from_dict(s.params())
+    pos = torch.as_tensor(s.pos).to(dev)
+    typ = torch.as_tensor(s.types).to(dev)
+    q = torch.as_tensor(s.charges).to(dev)
+    force = torch.empty((s.n, 3), dtype=torch.float32, device=dev)
+    energy = torch.empty(1, dtype=torch.float64, device=dev)
+    ws = api.alloc_workspace(P, s.n, dev)
+    api.forces(P.with_flags(api.DIAG_COUNTERS), pos, typ, q, force=force, energy=energy,
+               workspace=ws)
+    n_cand, _, n_pairs, _ = api.read_diag(ws)
+    stream = torch.cuda.current_stream()
+    # positions of each evaluation: x += N(0, 0.01 A) per call, wrapped by the call
+    xs, x = [], s.pos
+    for d in W.perturbation_stream(s.n, n_eval):
+        x = W.perturb(x, d)
+        xs.append(torch.as_tensor(x))
+    for _ in range(2):
+        api.forces(P, pos, typ, q, force=force, energy=energy, workspace=ws)
+    ms = []
+    for k in range(n_eval):
+        pos.copy_(xs[k])
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        api.forces(P, pos, typ, q, force=force, energy=energy, workspace=ws)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b))
+    if api.read_status(ws) != 0:
+        raise SystemExit(f"device status {api.read_status(ws):#x} (1M-atom system)")
+    med = pct(ms, 50)
+    flop = FLOP_PER_CANDIDATE * n_cand + FLOP_PER_PAIR * n_pairs
+    return {"n_atoms": s.n, "evaluations": n_eval, "eval_ms_median": med,
+            "eval_ms_p10": pct(ms, 10), "eval_ms_p90": pct(ms, 90),
+            "pairs_first_eval": n_pairs, "candidates_first_eval": n_cand,
+            "pairs_per_s": n_pairs / (med * 1e-3),
+            "whole_eval_algorithmic_TFLOPs": flop / (med * 1e-3) / 1e12}
 
 
 def cpu_baseline(s, budget_s):

@@ -378,3 +378,37 @@ def test_batched_matches_alone(gpu):
     r = _ref(s.params(), s.pos, s.types, s.charges)
     err = force_errors(systems[0]["force"].double().cpu().numpy(), r.force, r.abs_sum)
     assert err["max_norm"] <= 1e-5 and err["rms"] <= 1e-5, err
+
+
+def test_precision_form_report(gpu):
+    """Precision form on the 92,224-atom system: float32 pair arithmetic with 64-bit
+    fixed-point per-atom sums against float32-atomic sums, each against the FP64 oracle
+    (metrics (i)-(iii) and energy), and bit-reproducibility over 10 runs of each."""
+    _say("case: precision form, 92,224 atoms, fixed64 vs f32 atomic vs FP64 oracle")
+    import json
+    import torch
+    from _gpu import to_dev
+    s = W.apoa1_system()
+    r = _ref(s.params(), s.pos, s.types, s.charges)
+    d = to_dev((s.pos, s.types, s.charges), gpu)
+    report = {}
+    for name, flags in (("fixed64", 0), ("f32_atomic", api.ACCUM_F32_ATOMIC)):
+        p = api.Params.from_dict(s.params(), flags)
+        ws = api.alloc_workspace(p, s.n, gpu)
+        runs = []
+        for k in range(10):
+            f, e = api.forces(p, *d, workspace=ws)
+            runs.append((f.clone(), e.clone()))
+        torch.cuda.synchronize()
+        same = sum(torch.equal(runs[k][0], runs[0][0]) and torch.equal(runs[k][1], runs[0][1])
+                   for k in range(10))
+        err = force_errors(runs[0][0].double().cpu().numpy(), r.force, r.abs_sum)
+        e0 = float(runs[0][1].item())
+        err["energy_rel"] = abs(e0 - r.energy) / abs(r.energy)
+        err["bitwise_identical_runs_of_10"] = int(same)
+        report[name] = err
+    _say("PRECISION_REPORT " + json.dumps(report))
+    assert report["fixed64"]["bitwise_identical_runs_of_10"] == 10
+    for name in report:
+        assert report[name]["max_norm"] <= 1e-5 and report[name]["rms"] <= 1e-5, report
+        assert report[name]["energy_rel"] <= 1e-6, report
