@@ -57,7 +57,10 @@ typedef enum {
 /* md_params.flags */
 enum {
   MD_ACCUM_FIXED64 = 0,         /* default: per-atom sums in 64-bit fixed point (2^-32 kcal/mol/A) */
-  MD_ACCUM_F32_ATOMIC = 1 << 0, /* per-atom sums with float32 atomics (order-dependent) */
+  MD_ACCUM_F32_ATOMIC = 1 << 0, /* per-atom sums in float32: with float32 atomics (order-
+                                   dependent) in the half-shell kernels; in the compacted
+                                   float32 kernel, which owns each atom in one wave, as a
+                                   fixed-order float32 sum */
   MD_COULOMB_TRUNCATED = 1 << 1,/* switch only the LJ energy; Coulomb is Eq. 2 up to r_cut */
   MD_DIAG_COUNTERS = 1 << 2,    /* count candidates, filter passes and per-atom partners */
   MD_PAIR_PREDICATED = 1 << 3   /* evaluate the force under the cutoff predicate, without
@@ -88,7 +91,8 @@ typedef struct {
 } md_params;
 
 /* Bytes of device workspace needed by md_forces_f32 (double_precision = 0) or
- * md_forces_f64 (double_precision = 1) for n_atoms atoms. Returns 0 when the
+ * md_forces_f64 (double_precision = 1) for n_atoms atoms with p->flags (the flags
+ * choose the pair kernel, whose per-atom buffers differ in size). Returns 0 when the
  * parameters are invalid. The workspace must be 256-byte aligned; its contents
  * need no initialisation and are scratch between calls. */
 size_t md_workspace_bytes(const md_params* p, int64_t n_atoms, int double_precision);

@@ -63,7 +63,11 @@ md_status make_plan(const md_params* p, int64_t n, int real_bytes, Plan* pl) {
   pl->off_pos = o;       o = align_up(o + (size_t)4 * real_bytes * nn);
   pl->off_type = o;      o = align_up(o + sizeof(int32_t) * nn);
   pl->off_perm = o;      o = align_up(o + sizeof(int32_t) * nn);
-  pl->off_part = o;      o = align_up(o + (size_t)real_bytes * kSlots * 3 * nn);
+  // per-atom partials: 27 slots x 3 components for the half-shell kernel, or three
+  // 64-bit fixed-point sums for the float32 compacted full-shell kernel
+  const bool full_shell = real_bytes == 4 && !(p->flags & MD_PAIR_PREDICATED);
+  pl->off_part = o;
+  o = align_up(o + (full_shell ? sizeof(long long) * 3 * nn : (size_t)real_bytes * kSlots * 3 * nn));
   pl->off_facc = o;      o = align_up(o + sizeof(float) * 3 * nn);
   pl->off_epart = o;     o = align_up(o + sizeof(double) * pl->n_tasks);
   pl->off_lj = o;        o = align_up(o + (size_t)real_bytes * 2 * kMaxTypes * kMaxTypes);

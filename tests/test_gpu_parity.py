@@ -392,7 +392,10 @@ def test_precision_form_report(gpu):
     r = _ref(s.params(), s.pos, s.types, s.charges)
     d = to_dev((s.pos, s.types, s.charges), gpu)
     report = {}
-    for name, flags in (("fixed64", 0), ("f32_atomic", api.ACCUM_F32_ATOMIC)):
+    # float32 sums: the compacted kernel owns each atom in one wave, so its float32 sums
+    # run in a fixed order too; the half-shell kernel adds them with float32 atomics
+    for name, flags in (("fixed64", 0), ("f32_sums_full_shell", api.ACCUM_F32_ATOMIC),
+                        ("f32_atomic_half_shell", api.ACCUM_F32_ATOMIC | api.PAIR_PREDICATED)):
         p = api.Params.from_dict(s.params(), flags)
         ws = api.alloc_workspace(p, s.n, gpu)
         runs = []
