@@ -84,6 +84,7 @@ md_status make_plan(const md_params* p, int64_t n, int real_bytes, Plan* pl) {
   }
   pl->off_bhist = o;     o = align_up(o + sizeof(int32_t) * (size_t)pl->bin_blocks * cells);
   pl->off_bstat = o;     o = align_up(o + sizeof(uint32_t) * (size_t)(pl->bin_blocks + 1));
+  pl->off_order = o;     o = align_up(o + sizeof(int32_t) * cells);
   pl->total = o;
   return MD_OK;
 }
@@ -116,6 +117,7 @@ SysArgs<Real> make_args(const md_params* p, const Plan& pl, int64_t n, const Rea
   a.acc64 = (long long*)(b + pl.off_part);   // the full-shell path reuses the partial buffer
   a.bhist = (int32_t*)(b + pl.off_bhist);
   a.bstat = (uint32_t*)(b + pl.off_bstat);
+  a.order = (int32_t*)(b + pl.off_order);
   a.bin_blocks = pl.bin_blocks;
   a.bin_chunk = pl.bin_chunk;
   a.n = n;

@@ -12,8 +12,10 @@
 //                the histogram and the block's status bits go to the workspace, so no
 //                global atomics are needed;
 //   k_bin_scan   one workgroup: per cell, exclusive offsets of the blocks and the total;
-//                exclusive scan of the totals -> cell_start; the mixed Lennard-Jones
-//                table (Lorentz-Berthelot); the status word;
+//                exclusive scan of the totals -> cell_start; the cells ordered by
+//                decreasing atom count (the pair kernel starts the largest home cells
+//                first, so the last workgroups to run are short ones); the mixed
+//                Lennard-Jones table (Lorentz-Berthelot); the status word;
 // otherwise k_setup (clears the counters) and k_bin_count (one global atomic per atom)
 // take the place of k_bin_hist, and k_bin_scan only scans. Then:
 //   k_scatter    writes each atom's index into its cell's range (arbitrary order);
@@ -179,6 +181,36 @@ __device__ inline void bin_scan(const SysArgs<Real>& a, const TypeTable& tt, int
     __syncthreads();
   }
   if (t == 0) a.start[nc] = carry;
+  // launch order of the pair kernel: counting sort of the cells by decreasing count
+  // (counts clamped to kOrderBins - 1); the order within a bin is arbitrary, which only
+  // changes which compute unit takes a cell, never a result
+  constexpr int kOrderBins = 1024;
+  __shared__ int32_t s_bin[kOrderBins];
+  s_bin[t] = 0;
+  __syncthreads();
+  for (int64_t c = t; c < nc; c += 1024) {
+    const int32_t v = a.count[c];
+    atomicAdd(&s_bin[kOrderBins - 1 - (v < kOrderBins - 1 ? v : kOrderBins - 1)], 1);
+  }
+  __syncthreads();
+  {
+    const int32_t own = s_bin[t];
+    for (int off = 1; off < 1024; off <<= 1) {
+      const int32_t add = t >= off ? s_bin[t - off] : 0;
+      __syncthreads();
+      s_bin[t] += add;
+      __syncthreads();
+    }
+    const int32_t excl = s_bin[t] - own;
+    __syncthreads();
+    s_bin[t] = excl;
+    __syncthreads();
+  }
+  for (int64_t c = t; c < nc; c += 1024) {
+    const int32_t v = a.count[c];
+    const int32_t pos = atomicAdd(&s_bin[kOrderBins - 1 - (v < kOrderBins - 1 ? v : kOrderBins - 1)], 1);
+    a.order[pos] = (int32_t)c;
+  }
   const int nt = a.n_types;
   for (int e = t; e < nt * nt; e += 1024) {
     const int ti = e / nt, tj = e % nt;

@@ -44,7 +44,8 @@ struct Plan {
   int real_bytes;               // 4 or 8
   // byte offsets
   size_t off_count, off_start, off_cell, off_rank, off_unsorted, off_pos, off_type, off_perm,
-      off_part, off_facc, off_epart, off_lj, off_paircount, off_bhist, off_bstat, total;
+      off_part, off_facc, off_epart, off_lj, off_paircount, off_bhist, off_bstat, off_order,
+      total;
   int bin_blocks;               // blocks of the LDS-histogram binning pass (0: global atomics)
   int64_t bin_chunk;            // atoms per such block
 };
@@ -79,6 +80,7 @@ struct SysArgs {
   long long* acc64;            // [3][n] per-atom fixed-point sums (full-shell path)
   int32_t* bhist;              // [bin_blocks][n_cells] per-block cell counts, then offsets
   uint32_t* bstat;             // [bin_blocks] per-block status bits
+  int32_t* order;              // [n_cells] cells by decreasing atom count (launch order)
   // scalars
   int64_t n, n_cells, n_tasks;
   int bin_blocks;

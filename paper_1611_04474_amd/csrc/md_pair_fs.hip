@@ -36,7 +36,7 @@ constexpr int kThreads = 64 * kNW;
 constexpr int kQ = 4;               // home atoms filtered together by one wave, one FIFO each
 constexpr int kDrain = 2;           // force batches of 64 drained together from a full FIFO
 constexpr int kFifo = 64 * (kDrain + 1);   // FIFO entries (uint16 neighbour index) per atom
-constexpr int kWaveFifo = kQ * kFifo + 64; // + one dump slot per lane (written, never read)
+constexpr int kWaveFifo = kQ * kFifo;
 constexpr int kMaxSeg = 18;         // 9 (dy, dz) rows, each split at most once by an x wrap
 constexpr int kLdsBytes = 160 * 1024;
 constexpr float kMargin = 0.05f;    // A^2 added to rc^2 by the expanded-form prefilter
@@ -138,9 +138,9 @@ __device__ inline float pair_f(float u, float c12, float c6, float qq, float rs2
   const float x6 = fmaf(2.f, elj, c6r6);            // (12 c12/r^12 - 6 c6/r^6) / 6
   const float ec = qq * rinv;
   const float t = __builtin_amdgcn_fmed3f((u - rs2) * inv_sw, 0.f, 1.f);
-  const float d = 1.f - t;
-  const float S = d * d * fmaf(2.f, t, 1.f);
-  const float g = t * d * sw12;
+  const float t2 = t * t;
+  const float S = fmaf(t2, fmaf(2.f, t, -3.f), 1.f);   // (1-t)^2 (1+2t)
+  const float g = (t - t2) * sw12;
   if (kSwitchCoulomb) {
     const float et = elj + ec;
     e = S * et;
@@ -150,25 +150,20 @@ __device__ inline float pair_f(float u, float c12, float c6, float qq, float rs2
   return fmaf(g, elj, fmaf(6.f * S, x6, ec) * r2);
 }
 
-// v = bit `lane` of mask ? a : b, as one v_cndmask on the mask (keeps the compiler from
-// turning the select into exec-masked branches)
-__device__ inline int select_by_mask(unsigned long long mask, int a, int b) {
-  int r;
-  __asm__ volatile("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(b), "v"(a), "s"(mask));
-  return r;
-}
-
-// 16-bit LDS store to a byte address relative to the start of LDS (the dynamic block
-// starts there: the kernel has no static LDS). Written out so the address needs no
-// further add; LDS operations of one wave complete in order, so the compiler's own
-// waits on later LDS reads stay valid.
-__device__ inline void lds_store_u16(uint32_t addr, uint32_t v) {
-  __asm__ volatile("ds_write_b16 %0, %1" : : "v"(addr), "v"(v) : "memory");
-}
-
-__device__ inline int64_t xcd_unit(int64_t b, int64_t n_units) {
-  int64_t per = (n_units + 7) / 8;
-  return (b % 8) * per + b / 8;
+// 16-bit LDS store, by the lanes set in `mask` only, to a byte address relative to the
+// start of LDS (the dynamic block starts there: the kernel has no static LDS). The exec
+// mask is narrowed for the one store and restored, so no per-lane select is needed and
+// the address needs no further add. LDS operations of one wave complete in order, so the
+// compiler's own waits on later LDS reads stay valid.
+__device__ inline void lds_store_u16_lanes(uint32_t addr, uint32_t v, unsigned long long mask) {
+  unsigned long long saved;
+  __asm__ volatile(
+      "s_and_saveexec_b64 %0, %3\n\t"
+      "ds_write_b16 %1, %2\n\t"
+      "s_mov_b64 exec, %0"
+      : "=&s"(saved)
+      : "v"(addr), "v"(v), "s"(mask)
+      : "memory", "scc");
 }
 
 // kClamp: the whole energy is switched and the switch is on, so lanes that must add
@@ -177,7 +172,7 @@ __device__ inline int64_t xcd_unit(int64_t b, int64_t n_units) {
 // kDiag: count filter passes, cutoff passes and filtered slots (MD_DIAG_COUNTERS).
 template <bool kSwitchCoulomb, bool kClamp, bool kDiag>
 __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<float>& a, int cap,
-                                                              int64_t unit) {
+                                                              int64_t cellA) {
   extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
   const Lds LL = lds_layout(cap, a.n_types);
   uint8_t* sT = s_dyn;
@@ -189,7 +184,6 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int64_t cellA = unit;
   const int nt = a.n_types;
   constexpr bool diag = kDiag;
   const bool f32 = (a.flags & MD_ACCUM_F32_ATOMIC) != 0;
@@ -290,9 +284,8 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
   unsigned long long pass_count = 0, filt_count = 0, slot_count = 0;
   uint32_t st = 0;
   uint16_t* fifo = sFifo + w * kWaveFifo;
-  // LDS byte addresses: FIFO k of this wave starts at fk0 + 2 k kFifo; dump slot of the lane
+  // LDS byte address where FIFO k of this wave starts: fk0 + 2 k kFifo
   const uint32_t fk0 = (uint32_t)(LL.fifo + 2 * w * kWaveFifo);
-  const uint32_t dump = fk0 + 2u * (uint32_t)(kQ * kFifo + lane);
 
   for (int P0 = 0; P0 < total; P0 += cap) {
     const int P1 = min(total, P0 + cap);
@@ -441,7 +434,7 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
         for (int b = 0; b < kDrain; ++b) {
           const float dx = xs[k] - pj[b].x, dy = ys[k] - pj[b].y, dz = zs[k] - pj[b].z;
           float u = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-          const bool in = 64 * b + lane < c;
+          const bool in = c >= 64 * kDrain || 64 * b + lane < c;   // full passes: all lanes
           float e, f;
           if (kClamp) {
             u = (in && u > 0.f) ? u : kBigU;
@@ -512,17 +505,16 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
           unsigned long long m[kQ];
 #pragma unroll
           for (int k = 0; k < kQ; ++k) m[k] = __builtin_amdgcn_ballot_w64(t[k] < thr[k]) & vm;
-          // every lane writes: passing lanes to their FIFO slot, the others to their own
-          // dump slot, so no exec-mask changes are needed
-          int adr[kQ];
+          // passing lanes append at their prefix rank
+          uint32_t adr[kQ];
 #pragma unroll
           for (int k = 0; k < kQ; ++k) {
             const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
                 (unsigned)(m[k] >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m[k], 0u));
-            adr[k] = select_by_mask(m[k], (int)(fb[k] + 2u * rank), (int)dump);
+            adr[k] = fb[k] + 2u * rank;
           }
 #pragma unroll
-          for (int k = 0; k < kQ; ++k) lds_store_u16((uint32_t)adr[k], (uint32_t)j);
+          for (int k = 0; k < kQ; ++k) lds_store_u16_lanes(adr[k], (uint32_t)j, m[k]);
 #pragma unroll
           for (int k = 0; k < kQ; ++k) {
             const int np = __builtin_popcountll(m[k]);
@@ -595,7 +587,7 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
     if (tid < off) sE[tid] += sE[tid + off];
     __syncthreads();
   }
-  if (tid == 0) a.epart[unit] = 0.5 * ((double)sE[0] * 5.9604644775390625e-08);   // 2^-24
+  if (tid == 0) a.epart[cellA] = 0.5 * ((double)sE[0] * 5.9604644775390625e-08);   // 2^-24
   if (st) atomicOr(&a.hdr->status, st);
   if (diag && lane == 0) {
     // candidates of Algorithm 1: every (home atom, other neighbour-list atom), counted
@@ -613,21 +605,17 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
 template <bool kSwitchCoulomb, bool kClamp, bool kDiag>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
 void k_pair_fs(SysArgs<float> a, int cap) {
-  const int64_t unit = xcd_unit(blockIdx.x, a.n_cells);
-  if (unit >= a.n_cells) return;
-  pair_fs<kSwitchCoulomb, kClamp, kDiag>(a, cap, unit);
+  // home cells in decreasing order of atom count, spread over the XCDs in turn
+  pair_fs<kSwitchCoulomb, kClamp, kDiag>(a, cap, a.order[blockIdx.x]);
 }
 
-// One launch for a batch: the XCD-aware numbering runs over the cells of all systems.
+// One launch for a batch: block b is cell order[b - cum[s]] of system s.
 template <bool kSwitchCoulomb, bool kClamp, bool kDiag>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
 void k_pair_fs_batch(Batch<float> b, int cap) {
-  const int64_t total = b.cum[b.n];
-  const int64_t g = xcd_unit(blockIdx.x, total);
-  if (g >= total) return;
   int64_t unit;
-  const int s = b.pick(g, unit);
-  pair_fs<kSwitchCoulomb, kClamp, kDiag>(b.sys[s], cap, unit);
+  const int s = b.pick(blockIdx.x, unit);
+  pair_fs<kSwitchCoulomb, kClamp, kDiag>(b.sys[s], cap, b.sys[s].order[unit]);
 }
 
 // Neighbour atoms staged in LDS per pass for n_types types (a multiple of 64).
@@ -646,8 +634,7 @@ size_t pair_fs_lds_bytes(int n_types) {
 
 hipError_t launch_pair_fs(const SysArgs<float>& a, hipStream_t stream) {
   if (a.n == 0) return hipSuccess;
-  const int64_t units = a.n_cells;
-  const int64_t blocks = 8 * ((units + 7) / 8);
+  const int64_t blocks = a.n_cells;
   const int cap = fs_cap(a.n_types);
   const size_t shmem = pair_fs_lds_bytes(a.n_types);
   const bool trunc = (a.flags & MD_COULOMB_TRUNCATED) != 0;
@@ -679,7 +666,7 @@ hipError_t launch_pair_fs_batch(const Batch<float>& b0, hipStream_t stream) {
     b.cum[s + 1] = b.cum[s] + b.sys[s].n_cells;
     nt = b.sys[s].n_types > nt ? b.sys[s].n_types : nt;
   }
-  const int64_t blocks = 8 * ((b.cum[b.n] + 7) / 8);
+  const int64_t blocks = b.cum[b.n];
   const int cap = fs_cap(nt);
   const size_t shmem = pair_fs_lds_bytes(nt);
   const SysArgs<float>& a = b.sys[0];
