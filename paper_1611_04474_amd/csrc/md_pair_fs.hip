@@ -34,6 +34,7 @@ namespace {
 constexpr int kNW = 16;             // waves per workgroup
 constexpr int kThreads = 64 * kNW;
 constexpr int kQ = 4;               // home atoms filtered together by one wave, one FIFO each
+static_assert(kQ == 4, "the FIFO append writes four home atoms' FIFOs in one block");
 constexpr int kDrain = 2;           // force batches of 64 drained together from a full FIFO
 constexpr int kFifo = 64 * (kDrain + 1);   // FIFO entries (uint16 neighbour index) per atom
 constexpr int kWaveFifo = kQ * kFifo;
@@ -150,19 +151,36 @@ __device__ inline float pair_f(float u, float c12, float c6, float qq, float rs2
   return fmaf(g, elj, fmaf(6.f * S, x6, ec) * r2);
 }
 
-// 16-bit LDS store, by the lanes set in `mask` only, to a byte address relative to the
-// start of LDS (the dynamic block starts there: the kernel has no static LDS). The exec
-// mask is narrowed for the one store and restored, so no per-lane select is needed and
-// the address needs no further add. LDS operations of one wave complete in order, so the
+// Four 16-bit LDS stores of v, store i by the lanes set in m_i only, to byte addresses
+// relative to the start of LDS (the dynamic block starts there: the kernel has no static
+// LDS). The exec mask is narrowed for each store and restored, so no per-lane select is
+// needed and the addresses need no further add. LDS operations of one wave complete in order, so the
 // compiler's own waits on later LDS reads stay valid.
-__device__ inline void lds_store_u16_lanes(uint32_t addr, uint32_t v, unsigned long long mask) {
+// (n << 1) + b in one scalar instruction
+__device__ inline uint32_t lshl1_add(uint32_t n, uint32_t b) {
+  uint32_t r;
+  __asm__("s_lshl1_add_u32 %0, %1, %2" : "=s"(r) : "s"(n), "s"(b) : "scc");
+  return r;
+}
+
+__device__ inline void lds_store_u16_lanes4(uint32_t a0, uint32_t a1, uint32_t a2, uint32_t a3,
+                                            uint32_t v, unsigned long long m0,
+                                            unsigned long long m1, unsigned long long m2,
+                                            unsigned long long m3) {
   unsigned long long saved;
   __asm__ volatile(
-      "s_and_saveexec_b64 %0, %3\n\t"
-      "ds_write_b16 %1, %2\n\t"
+      "s_mov_b64 %0, exec\n\t"
+      "s_and_b64 exec, %0, %6\n\t"
+      "ds_write_b16 %1, %5\n\t"
+      "s_and_b64 exec, %0, %7\n\t"
+      "ds_write_b16 %2, %5\n\t"
+      "s_and_b64 exec, %0, %8\n\t"
+      "ds_write_b16 %3, %5\n\t"
+      "s_and_b64 exec, %0, %9\n\t"
+      "ds_write_b16 %4, %5\n\t"
       "s_mov_b64 exec, %0"
       : "=&s"(saved)
-      : "v"(addr), "v"(v), "s"(mask)
+      : "v"(a0), "v"(a1), "v"(a2), "v"(a3), "v"(v), "s"(m0), "s"(m1), "s"(m2), "s"(m3)
       : "memory", "scc");
 }
 
@@ -344,8 +362,9 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
 
       float xi[kQ], yi[kQ], zi[kQ], kq[kQ], fx[kQ], fy[kQ], fz[kQ];
       float ax[kQ], ay[kQ], az[kQ], thb[kQ];
-      int row[kQ], tl[kQ];
+      int row[kQ];
       uint32_t fb[kQ];   // byte address of the next free slot of FIFO k
+      uint32_t fl[kQ];   // fb[k] at which FIFO k holds a full drain
       unsigned cnt[kQ];
       float xmin = 0.f, xmax = 0.f;
 #pragma unroll
@@ -372,8 +391,8 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
                          (ax[k] * O0 + ay[k] * O1 + az[k] * O2)
                    : -1.f;
         fx[k] = fy[k] = fz[k] = 0.f;
-        tl[k] = 0;
         fb[k] = fk0 + 2u * (uint32_t)(k * kFifo);
+        fl[k] = fb[k] + 2u * (uint32_t)(64 * kDrain);
         cnt[k] = 0;
       }
       float e_lane = 0.f;
@@ -412,6 +431,10 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
       }
 
       float xs[kQ], ys[kQ], zs[kQ], thr[kQ];
+      // entries in FIFO k
+      auto fill = [&](int k) __attribute__((always_inline)) {
+        return (int)((fb[k] - fk0) >> 1) - k * kFifo;
+      };
       // dense force passes over the first c entries of FIFO k (c <= 64 * kDrain): the exact
       // distance in the current frame, the strict cutoff (u > 0 drops the home atom
       // itself) and the force. All LDS reads of the kDrain batches precede the arithmetic.
@@ -453,19 +476,18 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
           e_lane += e;
         }
         // drop the first c entries; the remainder (fewer than 64) moves to the front
-        const int rem = tl[k] - c;
+        const int rem = fill(k) - c;
         if (rem > 0) {
           uint16_t v = 0;
           if (lane < rem) v = fifo[k * kFifo + c + lane];
           if (lane < rem) fifo[k * kFifo + lane] = v;
         }
-        tl[k] = rem;
         fb[k] = fk0 + 2u * (uint32_t)(k * kFifo + rem);
       };
       auto flush = [&]() __attribute__((always_inline)) {
 #pragma unroll
         for (int k = 0; k < kQ; ++k) {
-          while (tl[k] > 0) force(k, tl[k] < 64 * kDrain ? tl[k] : 64 * kDrain);
+          while (fill(k) > 0) force(k, fill(k) < 64 * kDrain ? fill(k) : 64 * kDrain);
         }
       };
 
@@ -489,11 +511,13 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
           }
         }
         if (diag) slot_count += (unsigned long long)(hi - lo) * (unsigned long long)nv;
+        // se: end of this segment. Lanes in [hi, se) are neighbours of this segment (this
+        // frame) past the x-window, farther than r_cut from every home atom of the group:
+        // the exact test drops any that the prefilter's margin lets through. Lanes past se
+        // belong to another segment (or to the q block, still inside LDS) and are masked.
+        const int se_s = __builtin_amdgcn_readlane(se, s);
         for (int jb = lo; jb < hi; jb += 64) {
-          // lanes past hi read in-bounds LDS (the q block follows) and are masked off
           const int j = jb + lane;
-          const int nb = hi - jb;
-          const unsigned long long vm = nb >= 64 ? ~0ull : ((1ull << nb) - 1ull);
           const float4 pj = sF[j];
           float t[kQ];
 #pragma unroll
@@ -504,7 +528,12 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
           for (int k = 0; k < kQ; ++k) t[k] = fmaf(az[k], pj.z, t[k]);
           unsigned long long m[kQ];
 #pragma unroll
-          for (int k = 0; k < kQ; ++k) m[k] = __builtin_amdgcn_ballot_w64(t[k] < thr[k]) & vm;
+          for (int k = 0; k < kQ; ++k) m[k] = __builtin_amdgcn_ballot_w64(t[k] < thr[k]);
+          if (jb + 64 > se_s) {
+            const unsigned long long vm = (1ull << (se_s - jb)) - 1ull;   // se_s - jb < 64
+#pragma unroll
+            for (int k = 0; k < kQ; ++k) m[k] &= vm;
+          }
           // passing lanes append at their prefix rank
           uint32_t adr[kQ];
 #pragma unroll
@@ -513,21 +542,16 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
                 (unsigned)(m[k] >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m[k], 0u));
             adr[k] = fb[k] + 2u * rank;
           }
+          lds_store_u16_lanes4(adr[0], adr[1], adr[2], adr[3], (uint32_t)j, m[0], m[1], m[2], m[3]);
 #pragma unroll
-          for (int k = 0; k < kQ; ++k) lds_store_u16_lanes(adr[k], (uint32_t)j, m[k]);
-#pragma unroll
-          for (int k = 0; k < kQ; ++k) {
-            const int np = __builtin_popcountll(m[k]);
-            tl[k] += np;
-            fb[k] += 2u * (uint32_t)np;
-          }
+          for (int k = 0; k < kQ; ++k) fb[k] = lshl1_add((uint32_t)__builtin_popcountll(m[k]), fb[k]);
           if (diag) {
 #pragma unroll
             for (int k = 0; k < kQ; ++k) filt_count += __builtin_popcountll(m[k]);
           }
 #pragma unroll
           for (int k = 0; k < kQ; ++k) {
-            if (tl[k] >= 64 * kDrain) force(k, 64 * kDrain);
+            if (fb[k] >= fl[k]) force(k, 64 * kDrain);
           }
         }
       }
