@@ -177,7 +177,9 @@ md_status md_read_diag(const void* d_ws, void* stream, uint64_t counters[4]);
  *   perm:       int32 [n_atoms], original index of each sorted atom
  *   pair_count: int32 [n_atoms], partners inside the cutoff (MD_DIAG_COUNTERS),
  *               in the caller's atom order
- *   energy_partials: float64 [n_energy_partials], per-workgroup energy sums */
+ *   energy_partials: float64 [n_energy_partials], per-workgroup energy sums
+ *   z_split:    int32 [n_cells], atoms of each cell in its lower z half; a cell's sorted
+ *               atoms are ordered by (z half, x, original index) */
 typedef struct {
   int32_t dims[3];
   int64_t n_cells;
@@ -186,6 +188,7 @@ typedef struct {
   size_t pair_count;
   size_t energy_partials;
   int64_t n_energy_partials;
+  size_t z_split;
   size_t total_bytes;
 } md_layout;
 

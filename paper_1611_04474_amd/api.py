@@ -54,7 +54,8 @@ class _System(C.Structure):
 class _Layout(C.Structure):
     _fields_ = [("dims", C.c_int32 * 3), ("n_cells", C.c_int64), ("cell_start", C.c_size_t),
                 ("perm", C.c_size_t), ("pair_count", C.c_size_t), ("energy_partials", C.c_size_t),
-                ("n_energy_partials", C.c_int64), ("total_bytes", C.c_size_t)]
+                ("n_energy_partials", C.c_int64), ("z_split", C.c_size_t),
+                ("total_bytes", C.c_size_t)]
 
 
 _lib = None
@@ -145,7 +146,8 @@ def workspace_layout(params, n_atoms, double_precision=False):
     return dict(dims=tuple(out.dims), n_cells=int(out.n_cells), cell_start=int(out.cell_start),
                 perm=int(out.perm), pair_count=int(out.pair_count),
                 energy_partials=int(out.energy_partials),
-                n_energy_partials=int(out.n_energy_partials), total_bytes=int(out.total_bytes))
+                n_energy_partials=int(out.n_energy_partials), z_split=int(out.z_split),
+                total_bytes=int(out.total_bytes))
 
 
 def _stream_ptr(stream):

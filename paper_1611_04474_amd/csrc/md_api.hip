@@ -85,6 +85,7 @@ md_status make_plan(const md_params* p, int64_t n, int real_bytes, Plan* pl) {
   pl->off_bhist = o;     o = align_up(o + sizeof(int32_t) * (size_t)pl->bin_blocks * cells);
   pl->off_bstat = o;     o = align_up(o + sizeof(uint32_t) * (size_t)(pl->bin_blocks + 1));
   pl->off_order = o;     o = align_up(o + sizeof(int32_t) * cells);
+  pl->off_zsplit = o;    o = align_up(o + sizeof(int32_t) * cells);
   pl->total = o;
   return MD_OK;
 }
@@ -118,6 +119,7 @@ SysArgs<Real> make_args(const md_params* p, const Plan& pl, int64_t n, const Rea
   a.bhist = (int32_t*)(b + pl.off_bhist);
   a.bstat = (uint32_t*)(b + pl.off_bstat);
   a.order = (int32_t*)(b + pl.off_order);
+  a.zsplit = (int32_t*)(b + pl.off_zsplit);
   a.bin_blocks = pl.bin_blocks;
   a.bin_chunk = pl.bin_chunk;
   a.n = n;
@@ -227,6 +229,7 @@ md_status md_workspace_layout(const md_params* p, int64_t n_atoms, int double_pr
   out->n_energy_partials =
       (!double_precision && !(p->flags & MD_PAIR_PREDICATED)) ? pl.n_cells * md::kFsSplit
                                                              : pl.n_tasks;
+  out->z_split = pl.off_zsplit;
   out->total_bytes = pl.total;
   return MD_OK;
 }

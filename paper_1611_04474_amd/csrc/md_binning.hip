@@ -19,11 +19,12 @@
 // otherwise k_setup (clears the counters) and k_bin_count (one global atomic per atom)
 // take the place of k_bin_hist, and k_bin_scan only scans. Then:
 //   k_scatter    writes each atom's index into its cell's range (arbitrary order);
-//   k_cell_sort  one workgroup per cell: orders the cell's atoms by (wrapped x, original
-//                index) -- a total order, so every later sum runs in a reproducible order,
-//                and a row of cells along x is sorted in x, which lets the pair kernel
-//                bound each home atom's candidates by an x-window -- and writes the sorted
-//                arrays.
+//   k_cell_sort  one workgroup per cell: orders the cell's atoms by (z half of the cell,
+//                wrapped x, original index) -- a total order, so every later sum runs in
+//                a reproducible order, and each half of a row of cells along x is sorted in
+//                x, which lets the pair kernel bound the candidates of a group of home
+//                atoms by an x-window per half-row -- writes the sorted arrays and the
+//                number of atoms in the lower z half.
 #include "md_common.hpp"
 
 namespace md {
@@ -259,13 +260,22 @@ __global__ __launch_bounds__(256) void k_scatter_batch(Batch<float> b) {
   scatter(b.sys[s], blk);
 }
 
-// Sort key of an atom: (wrapped x as float32 bits, original index). Wrapped x is >= +0,
-// where the bits of a float order as its value.
+// z half of an atom in its cell: 1 if 2 z n_z / L_z reaches the cell's middle.
 template <typename Real>
-__device__ inline unsigned long long sort_key(const SysArgs<Real>& a, int32_t i) {
+__device__ inline int z_half(const SysArgs<Real>& a, Real z, int cz) {
+  return (int)(z * a.inv_w[2] * Real(2)) >= 2 * cz + 1 ? 1 : 0;
+}
+
+// Sort key of an atom of cell cz (z index): (z half, wrapped x as float32 bits, original
+// index) in bits 63, 62..31 and 30..0. Wrapped x is >= +0, where the bits of a float
+// order as its value (31 bits: the sign bit is 0).
+template <typename Real>
+__device__ inline unsigned long long sort_key(const SysArgs<Real>& a, int32_t i, int cz) {
   uint32_t st = 0;
   const float x = (float)wrap_coord(a.pos_in[3 * (int64_t)i], a.L[0], st) + 0.f;
-  return ((unsigned long long)__builtin_bit_cast(uint32_t, x) << 32) | (uint32_t)i;
+  const Real z = wrap_coord(a.pos_in[3 * (int64_t)i + 2], a.L[2], st);
+  return ((unsigned long long)z_half(a, z, cz) << 63) |
+         ((unsigned long long)__builtin_bit_cast(uint32_t, x) << 31) | (uint32_t)i;
 }
 
 // One workgroup per cell. Each member's position in the cell is the number of members
@@ -276,8 +286,11 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
   constexpr int kChunk = 1024;
   constexpr int kPer = kChunk / 256;
   __shared__ unsigned long long s_key[kChunk];
+  __shared__ int32_t s_low;
   const int32_t s0 = a.start[c];
   const int32_t m = a.start[c + 1] - s0;
+  const int cz = (int)(c / ((int64_t)a.nx * a.ny));
+  if (threadIdx.x == 0) s_low = 0;
   for (int32_t a0 = 0; a0 < m; a0 += kChunk) {
     const int kk = min(kPer, (m - a0 + 255) / 256);   // member slots in use (uniform)
     int32_t my_idx[kPer];
@@ -286,13 +299,13 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
     for (int k = 0; k < kPer; ++k) {
       const int32_t e = a0 + (int32_t)threadIdx.x + 256 * k;
       my_idx[k] = (k < kk && e < m) ? a.unsorted[s0 + e] : -1;
-      my_key[k] = my_idx[k] >= 0 ? sort_key(a, my_idx[k]) : ~0ull;
+      my_key[k] = my_idx[k] >= 0 ? sort_key(a, my_idx[k], cz) : ~0ull;
       my_rank[k] = 0;
     }
     for (int32_t b0 = 0; b0 < m; b0 += kChunk) {
       const int32_t mb = min(kChunk, m - b0);
       __syncthreads();
-      for (int32_t e = threadIdx.x; e < mb; e += 256) s_key[e] = sort_key(a, a.unsorted[s0 + b0 + e]);
+      for (int32_t e = threadIdx.x; e < mb; e += 256) s_key[e] = sort_key(a, a.unsorted[s0 + b0 + e], cz);
       for (int32_t e = mb + (int32_t)threadIdx.x; e < ((mb + 3) & ~3); e += 256) s_key[e] = ~0ull;
       __syncthreads();
       for (int32_t e = 0; e < mb; e += 4) {
@@ -314,6 +327,7 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
       int t = a.type_in[i];
       if (t < 0 || t >= a.n_types) t = 0;
       const int32_t d = s0 + my_rank[k];
+      if (!(my_key[k] >> 63)) atomicAdd(&s_low, 1);
       P4<Real> p;
       p.x = x;
       p.y = y;
@@ -324,6 +338,8 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
       a.perm[d] = i;
     }
   }
+  __syncthreads();
+  if (threadIdx.x == 0) a.zsplit[c] = s_low;
 }
 
 template <typename Real>

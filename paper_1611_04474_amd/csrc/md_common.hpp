@@ -45,7 +45,7 @@ struct Plan {
   // byte offsets
   size_t off_count, off_start, off_cell, off_rank, off_unsorted, off_pos, off_type, off_perm,
       off_part, off_facc, off_epart, off_lj, off_paircount, off_bhist, off_bstat, off_order,
-      total;
+      off_zsplit, total;
   int bin_blocks;               // blocks of the LDS-histogram binning pass (0: global atomics)
   int64_t bin_chunk;            // atoms per such block
 };
@@ -81,6 +81,7 @@ struct SysArgs {
   int32_t* bhist;              // [bin_blocks][n_cells] per-block cell counts, then offsets
   uint32_t* bstat;             // [bin_blocks] per-block status bits
   int32_t* order;              // [n_cells] cells by decreasing atom count (launch order)
+  int32_t* zsplit;             // [n_cells] atoms of each cell in its lower z half
   // scalars
   int64_t n, n_cells, n_tasks;
   int bin_blocks;

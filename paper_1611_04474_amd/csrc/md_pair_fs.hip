@@ -38,7 +38,8 @@ static_assert(kQ == 4, "the FIFO append writes four home atoms' FIFOs in one blo
 constexpr int kDrain = 2;           // force batches of 64 drained together from a full FIFO
 constexpr int kFifo = 64 * (kDrain + 1);   // FIFO entries (uint16 neighbour index) per atom
 constexpr int kWaveFifo = kQ * kFifo;
-constexpr int kMaxSeg = 18;         // 9 (dy, dz) rows, each split at most once by an x wrap
+constexpr int kMaxSeg = 36;         // 9 (dy, dz) rows x 2 z halves, each split at most once by
+                                    // an x wrap
 constexpr int kLdsBytes = 160 * 1024;
 constexpr float kMargin = 0.05f;    // A^2 added to rc^2 by the expanded-form prefilter
 constexpr float kWin = 1.0e-3f;     // A added to r_cut for the x-window
@@ -54,14 +55,18 @@ __constant__ int8_t c_img[27][3] = {
 struct Img {
   int start;   // first sorted index of the cell
   int count;
-  int off;     // position in the neighbour list
+  int n0;      // atoms in the cell's lower z half (they come first)
+  int off[2];  // neighbour-list position of the lower and upper halves
   int grp;     // bit d: image lies at +L along d (the home side subtracts L)
   int jsh;     // bit d: image lies at -L along d (the neighbour side subtracts L)
 };
 
+// A segment: one z half of the images of one (dy, dz) row with one shift class, in x
+// order. Its slab bounds y0..y1, z0..z1 are in the home cell's frame.
 struct Seg {
   int begin, end;   // neighbour-list positions
   int grp;
+  float y0, y1, z0, z1;
 };
 
 // Workgroup header in LDS.
@@ -115,12 +120,6 @@ __device__ inline long long to_fixed(float v, uint32_t& st) {
   unsigned long long m =
       ((unsigned long long)(unsigned)hi << 32) + (unsigned long long)(unsigned)lo;
   return v < 0.f ? -(long long)m : (long long)m;
-}
-
-__device__ inline long long readlane64(long long v, int lane) {
-  unsigned lo = __builtin_amdgcn_readlane((int)(unsigned)(v & 0xffffffffull), lane);
-  unsigned hi = __builtin_amdgcn_readlane((int)(unsigned)((unsigned long long)v >> 32), lane);
-  return (long long)(((unsigned long long)hi << 32) | lo);
 }
 
 // Pair force factor f (F_i = f r_ij) and pair energy e at squared distance u.
@@ -223,15 +222,16 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
   const int sA = a.start[cellA];
   const int nA = a.start[cellA + 1] - sA;
 
-  // image table and segments (wave 0; lane m = image m). Images are ordered by
-  // (group, dz, dy, dx): the images of one (dy, dz) row with one group form a segment,
-  // sorted in x because each cell is and the cells follow each other in x.
+  // image table and segments (wave 0; lane l < 54 = half l & 1 of image l >> 1). Pieces
+  // are ordered by (group, dz, dy, z half, dx): the pieces of one (dy, dz) row, one z half
+  // and one group form a segment, sorted in x because each half of a cell is and the
+  // cells follow each other in x.
   if (tid < 64) {
-    const int m = lane;
-    const bool act = m < 27;
+    const int m = lane >> 1, h = lane & 1;
+    const bool act = lane < 54;
     const int nd[3] = {a.nx, a.ny, a.nz};
     const int ac[3] = {ac0, ac1, ac2};
-    int grp = 0, jsh = 0, st0 = 0, cnt = 0, key = 1 << 20, ox = 0;
+    int grp = 0, jsh = 0, st0 = 0, cnt = 0, n0 = 0, key = 1 << 20, ox = 0;
     if (act) {
       int b[3];
       for (int d = 0; d < 3; ++d) {
@@ -247,42 +247,53 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
       const int64_t cb = ((int64_t)b[2] * a.ny + b[1]) * a.nx + b[0];
       st0 = a.start[cb];
       cnt = a.start[cb + 1] - st0;
-      key = grp * 9 + (c_img[m][1] + 1) + 3 * (c_img[m][2] + 1);
+      n0 = a.zsplit[cb];
+      key = (grp * 9 + (c_img[m][1] + 1) + 3 * (c_img[m][2] + 1)) * 2 + h;
       ox = c_img[m][0];
     }
+    const int pc = act ? (h ? cnt - n0 : n0) : 0;   // atoms of this piece
     int off = 0, seg_len = 0, tot = 0;
     bool head = act;
-    for (int mm = 0; mm < 27; ++mm) {
-      const int km = __builtin_amdgcn_readlane(key, mm);
-      const int cm = __builtin_amdgcn_readlane(cnt, mm);
-      const int xm = __builtin_amdgcn_readlane(ox, mm);
+    for (int l2 = 0; l2 < 54; ++l2) {
+      const int km = __builtin_amdgcn_readlane(key, l2);
+      const int cm = __builtin_amdgcn_readlane(pc, l2);
+      const int xm = __builtin_amdgcn_readlane(ox, l2);
       const bool same = km == key;
       off += (km < key || (same && xm < ox)) ? cm : 0;
       seg_len += same ? cm : 0;
       if (same && xm < ox) head = false;
       tot += cm;
     }
-    // a head (the first image of its segment) is numbered by the heads with smaller keys
+    // a head (the first piece of its segment) is numbered by the heads with smaller keys
     const unsigned long long heads = __builtin_amdgcn_ballot_w64(head);
     int seg_idx = 0;
-    for (int mm = 0; mm < 27; ++mm) {
-      const int km = __builtin_amdgcn_readlane(key, mm);
-      seg_idx += (((heads >> mm) & 1ull) && km < key) ? 1 : 0;
+    for (int l2 = 0; l2 < 54; ++l2) {
+      const int km = __builtin_amdgcn_readlane(key, l2);
+      seg_idx += (((heads >> l2) & 1ull) && km < key) ? 1 : 0;
     }
     if (act) {
-      H.img[m].start = st0;
-      H.img[m].count = cnt;
-      H.img[m].off = off;
-      H.img[m].grp = grp;
-      H.img[m].jsh = jsh;
+      H.img[m].off[h] = off;
+      if (h == 0) {
+        H.img[m].start = st0;
+        H.img[m].count = cnt;
+        H.img[m].n0 = n0;
+        H.img[m].grp = grp;
+        H.img[m].jsh = jsh;
+      }
       if (head) {
-        H.seg[seg_idx].begin = off;
-        H.seg[seg_idx].end = off + seg_len;
-        H.seg[seg_idx].grp = grp;
+        const float wy = L1 / (float)a.ny, wz = L2 / (float)a.nz;
+        Seg& sg_ = H.seg[seg_idx];
+        sg_.begin = off;
+        sg_.end = off + seg_len;
+        sg_.grp = grp;
+        sg_.y0 = (float)(ac1 + c_img[m][1]) * wy;
+        sg_.y1 = (float)(ac1 + c_img[m][1] + 1) * wy;
+        sg_.z0 = ((float)(ac2 + c_img[m][2]) + 0.5f * (float)h) * wz;
+        sg_.z1 = ((float)(ac2 + c_img[m][2]) + 0.5f * (float)(h + 1)) * wz;
       }
     }
     int ml = head ? seg_len : 0;
-    for (int s = 32; s > 0; s >>= 1) ml = max(ml, __shfl_xor(ml, s));
+    for (int s2 = 32; s2 > 0; s2 >>= 1) ml = max(ml, __shfl_xor(ml, s2));
     if (lane == 0) {
       H.n_seg = __builtin_popcountll(heads);
       H.total = tot;
@@ -307,36 +318,37 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
 
   for (int P0 = 0; P0 < total; P0 += cap) {
     const int P1 = min(total, P0 + cap);
-    // stage the neighbour-list slice [P0, P1): wave w copies images w and w + 16, issuing
-    // all loads of an image (up to 4 x 64 atoms per round) before its LDS stores
+    // stage the neighbour-list slice [P0, P1): wave w copies images w and w + 16 (both z
+    // halves, to their two segments), issuing all loads of up to 4 x 64 atoms before the
+    // LDS stores
     for (int m = w; m < 27; m += kNW) {
       const Img im = H.img[m];
-      const int lo = max(im.off, P0), hi = min(im.off + im.count, P1);
       // o_g = o - h: the origin in this image's frame
       const float og0 = O0 - ((im.grp & 1) ? L0 : 0.f);
       const float og1 = O1 - ((im.grp & 2) ? L1 : 0.f);
       const float og2 = O2 - ((im.grp & 4) ? L2 : 0.f);
-      for (int e0 = lo; e0 < hi; e0 += 4 * 64) {
+      for (int e0 = 0; e0 < im.count; e0 += 4 * 64) {
         P4<float> v[4];
         int tv[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int e = e0 + 64 * r + lane;
-          const int src = im.start + (min(e, hi - 1) - im.off);
+          const int src = im.start + min(e, im.count - 1);
           v[r] = a.pos[src];
           tv[r] = a.type[src];
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int e = e0 + 64 * r + lane;
-          if (e < hi) {
+          const int dst = e < im.n0 ? im.off[0] + e : im.off[1] + (e - im.n0);
+          if (e < im.count && dst >= P0 && dst < P1) {
             const float x = (im.jsh & 1) ? v[r].x - L0 : v[r].x;
             const float y = (im.jsh & 2) ? v[r].y - L1 : v[r].y;
             const float z = (im.jsh & 4) ? v[r].z - L2 : v[r].z;
             const float rx = x - og0, ry = y - og1, rz = z - og2;
-            sF[e - P0] = make_float4(x, y, z, fmaf(rz, rz, fmaf(ry, ry, rx * rx)));
-            sQ[e - P0] = v[r].w;
-            sT[e - P0] = (uint8_t)tv[r];
+            sF[dst - P0] = make_float4(x, y, z, fmaf(rz, rz, fmaf(ry, ry, rx * rx)));
+            sQ[dst - P0] = v[r].w;
+            sT[dst - P0] = (uint8_t)tv[r];
           }
         }
       }
@@ -346,10 +358,15 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
 
     // segment table in registers: lane s holds segment s, clipped to this slice
     int sb = 0, se = 0, sg = 0;
+    float sy0 = 0.f, sy1 = 0.f, sz0 = 0.f, sz1 = 0.f;
     if (lane < n_seg) {
       sb = max(H.seg[lane].begin, P0) - P0;
       se = max(min(H.seg[lane].end, P1) - P0, sb);
       sg = H.seg[lane].grp;
+      sy0 = H.seg[lane].y0;
+      sy1 = H.seg[lane].y1;
+      sz0 = H.seg[lane].z0;
+      sz1 = H.seg[lane].z1;
     }
 
     while (true) {
@@ -366,7 +383,7 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
       uint32_t fb[kQ];   // byte address of the next free slot of FIFO k
       uint32_t fl[kQ];   // fb[k] at which FIFO k holds a full drain
       unsigned cnt[kQ];
-      float xmin = 0.f, xmax = 0.f;
+      float xmin = 0.f, xmax = 0.f, ymin = 0.f, ymax = 0.f, zmin = 0.f, zmax = 0.f;
 #pragma unroll
       for (int k = 0; k < kQ; ++k) {
         const bool v = k < nv;
@@ -379,6 +396,10 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
         row[k] = a.type[s] * nt;
         xmin = k == 0 ? p.x : fminf(xmin, p.x);
         xmax = k == 0 ? p.x : fmaxf(xmax, p.x);
+        ymin = k == 0 ? p.y : fminf(ymin, p.y);
+        ymax = k == 0 ? p.y : fmaxf(ymax, p.y);
+        zmin = k == 0 ? p.z : fminf(zmin, p.z);
+        zmax = k == 0 ? p.z : fmaxf(zmax, p.z);
         // prefilter in the frame of group g, with a = r_i - o (the same in every frame):
         // |r_j - r_i|^2 = c_j - 2 a.(r_j - o_g) + |a|^2, c_j = |r_j - o_g|^2, so the test
         // c_j + ax.r_j < rc^2 + margin - |a|^2 + ax.o_g with ax = -2a
@@ -397,14 +418,20 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
       }
       float e_lane = 0.f;
 
-      // x-window of every segment: lane s finds [lo, hi) of segment s with
-      // x in [min x_i - R, max x_i + R) in the segment's frame (two lower_bound searches)
+      // x-window of every segment: lane s finds [lo, hi) of segment s with x in
+      // [min x_i - w, max x_i + w) in the segment's frame (two lower_bound searches), where
+      // w^2 = R^2 - gy^2 - gz^2 and gy, gz are the gaps between the group's bounding box
+      // and the segment's slab (less 1e-3 A for atoms binned at a face by rounding)
       int wlo, whi;
       {
+        const float gy = fmaxf(fmaxf(sy0 - ymax, ymin - sy1) - kWin, 0.f);
+        const float gz = fmaxf(fmaxf(sz0 - zmax, zmin - sz1) - kWin, 0.f);
+        const float w2 = fmaf(R, R, -fmaf(gz, gz, gy * gy));
+        const float hw = w2 > 0.f ? __builtin_sqrtf(w2) : -1.f;
         const float hx = (sg & 1) ? L0 : 0.f;
-        const float xlo = (xmin - hx) - R;
-        const float xhi = (xmax - hx) + R;
-        int f0 = sb, c0 = se - sb, f1 = sb, c1 = se - sb;
+        const float xlo = (xmin - hx) - hw;
+        const float xhi = (xmax - hx) + hw;
+        int f0 = sb, c0 = se - sb, f1 = sb, c1 = w2 > 0.f ? se - sb : 0;
         for (int it = 0; it < iters; ++it) {
           const int h0 = c0 >> 1, h1 = c1 >> 1;
           const float x0 = sF[f0 + h0].x;   // f + h <= se <= cap: inside the LDS block
@@ -557,32 +584,39 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
       }
       if (cur_g >= 0) flush();
 
-      // per home atom: fixed-order row sums, then the four rows in 64-bit fixed point
+      // per home atom and component: the 64 lane partials summed in one fixed order (a
+      // butterfly within each 16-lane row, then rows 0+1 and 2+3, then the two halves), the
+      // twelve sums side by side; every lane ends with the same total, which lane 0 adds
+      // to the atom's 64-bit fixed-point sum (exact conversion) or float32 sum
+      float r[3 * kQ];
+#pragma unroll
+      for (int k = 0; k < kQ; ++k) {
+        r[3 * k] = fx[k];
+        r[3 * k + 1] = fy[k];
+        r[3 * k + 2] = fz[k];
+      }
+#pragma unroll
+      for (int i = 0; i < 3 * kQ; ++i) r[i] = rowsum16(r[i]);
+#pragma unroll
+      for (int i = 0; i < 3 * kQ; ++i) r[i] += __shfl_xor(r[i], 16);
+#pragma unroll
+      for (int i = 0; i < 3 * kQ; ++i) r[i] += __shfl_xor(r[i], 32);
 #pragma unroll
       for (int k = 0; k < kQ; ++k) {
         if (k >= nv) continue;
         const int64_t s = sA + ib + k;
-        const float comp[3] = {fx[k], fy[k], fz[k]};
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const float r = rowsum16(comp[c]);
           if (f32) {
-            const float r0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, r), 0));
-            const float r1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, r), 16));
-            const float r2 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, r), 32));
-            const float r3 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, r), 48));
-            const float tot = (r0 + r1) + (r2 + r3);
             if (lane == 0) {
               float* dst = &a.facc[(int64_t)c * a.n + s];
-              *dst = P0 == 0 ? tot : *dst + tot;
+              *dst = P0 == 0 ? r[3 * k + c] : *dst + r[3 * k + c];
             }
           } else {
-            const long long q = to_fixed(r, st);
-            const long long tot = readlane64(q, 0) + readlane64(q, 16) + readlane64(q, 32) +
-                                  readlane64(q, 48);
+            const long long qv = to_fixed(r[3 * k + c], st);
             if (lane == 0) {
               long long* dst = &a.acc64[(int64_t)c * a.n + s];
-              *dst = P0 == 0 ? tot : *dst + tot;
+              *dst = P0 == 0 ? qv : *dst + qv;
             }
           }
         }

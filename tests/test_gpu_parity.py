@@ -114,12 +114,21 @@ def test_binning_matches_oracle(gpu):
     assert start[0] == 0 and start[-1] == s.n and np.all(np.diff(start) >= 0)
     assert np.array_equal(np.sort(perm), np.arange(s.n))
     pos64, _ = oracle.canonicalize(s.pos, s.box)   # wrapped in float32, as the kernels do
+    dims_g = lay["dims"]
+    inv_wz = np.float32(dims_g[2] / float(np.float32(s.box[2])))
+    zsplit = ws[lay["z_split"]: lay["z_split"] + 4 * nc].view(torch.int32).cpu().numpy()
     gcell = np.empty(s.n, np.int64)
     for c in range(nc):
         seg = perm[start[c]:start[c + 1]]
-        # a cell is ordered by (wrapped x, original index)
+        # a cell is ordered by (z half, wrapped x, original index); z half in float32 as
+        # the kernel computes it
+        cz = c // (dims_g[0] * dims_g[1])
+        zf = pos64[seg, 2].astype(np.float32)
+        half = ((zf * inv_wz * np.float32(2)).astype(np.int64) >= 2 * cz + 1).astype(np.int64)
+        assert zsplit[c] == int((half == 0).sum())
         x = pos64[seg, 0]
-        assert np.all((np.diff(x) > 0) | ((np.diff(x) == 0) & (np.diff(seg) > 0)))
+        dh, dx, di = np.diff(half), np.diff(x), np.diff(seg)
+        assert np.all((dh > 0) | ((dh == 0) & ((dx > 0) | ((dx == 0) & (di > 0)))))
         gcell[seg] = c
     ocell, dims = oracle.bin_atoms(p, pos64)
     diff = np.nonzero(gcell != ocell)[0]
