@@ -145,7 +145,18 @@ __device__ inline void bin_scan(const SysArgs<Real>& a, const TypeTable& tt, int
   if (B > 0) {
     for (int64_t c = t; c < nc; c += 1024) {
       int32_t acc = 0;
-      for (int b = 0; b < B; ++b) {
+      int b = 0;
+      for (; b + 8 <= B; b += 8) {   // eight independent loads in flight
+        int32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = a.bhist[(int64_t)(b + u) * nc + c];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          a.bhist[(int64_t)(b + u) * nc + c] = acc;
+          acc += v[u];
+        }
+      }
+      for (; b < B; ++b) {
         const int32_t v = a.bhist[(int64_t)b * nc + c];
         a.bhist[(int64_t)b * nc + c] = acc;
         acc += v;

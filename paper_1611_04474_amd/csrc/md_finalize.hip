@@ -7,7 +7,8 @@
 // depend on any summation order; an out-of-range value sets MD_STATUS_FIXED_OVERFLOW.
 // On the float64 path the partials are added in slot order.
 //
-// k_energy adds the per-task float64 energy partials in a fixed tree order.
+// The energy block adds the per-workgroup float64 energy partials in a fixed tree order;
+// it is one more block of the same launch.
 #include "md_common.hpp"
 
 namespace md {
@@ -60,15 +61,6 @@ __device__ inline void finalize(const SysArgs<Real>& a, int64_t blk) {
   if (st) atomicOr(&a.hdr->status, st);
 }
 
-template <typename Real>
-__global__ __launch_bounds__(256) void k_finalize(SysArgs<Real> a) { finalize(a, blockIdx.x); }
-
-__global__ __launch_bounds__(256) void k_finalize_batch(Batch<float> b) {
-  int64_t blk;
-  const int s = b.pick(blockIdx.x, blk);
-  finalize(b.sys[s], blk);
-}
-
 __device__ inline void energy(const double* epart, int64_t n_tasks, double* out, WsHeader* hdr,
                               int halve_diag) {
   if (halve_diag && threadIdx.x < 4) hdr->diag[threadIdx.x] /= 2;
@@ -84,11 +76,6 @@ __device__ inline void energy(const double* epart, int64_t n_tasks, double* out,
   if (threadIdx.x == 0) *out = s[0];
 }
 
-__global__ __launch_bounds__(256) void k_energy(const double* epart, int64_t n_tasks,
-                                                double* out, WsHeader* hdr, int halve_diag) {
-  energy(epart, n_tasks, out, hdr, halve_diag);
-}
-
 template <typename Real>
 __host__ __device__ inline int64_t energy_parts(const SysArgs<Real>& a) {
   return a.n > 0 ? (a.full_shell ? a.n_cells * kFsSplit : a.n_tasks) : 0;
@@ -99,32 +86,42 @@ __host__ __device__ inline int halve_diag(const SysArgs<Real>& a) {
   return (a.full_shell && (a.flags & MD_DIAG_COUNTERS) && a.n > 0) ? 1 : 0;
 }
 
-__global__ __launch_bounds__(256) void k_energy_batch(Batch<float> b) {
+// Blocks 0 .. ceil(n/256) - 1 finalize atoms; the block after them sums the energy
+// partials, which the pair kernel has completed, so one launch does both.
+template <typename Real>
+__device__ inline void finalize_or_energy(const SysArgs<Real>& a, int64_t blk) {
+  if (blk == (a.n + 255) / 256) {
+    energy(a.epart, energy_parts(a), a.energy_out, a.hdr, halve_diag(a));
+    return;
+  }
+  finalize(a, blk);
+}
+
+template <typename Real>
+__global__ __launch_bounds__(256) void k_finalize_energy(SysArgs<Real> a) {
+  finalize_or_energy(a, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_finalize_energy_batch(Batch<float> b) {
   int64_t blk;
-  const SysArgs<float>& a = b.sys[b.pick(blockIdx.x, blk)];
-  energy(a.epart, energy_parts(a), a.energy_out, a.hdr, halve_diag(a));
+  const int s = b.pick(blockIdx.x, blk);
+  finalize_or_energy(b.sys[s], blk);
 }
 
 }  // namespace
 
 template <typename Real>
 hipError_t launch_finalize(const SysArgs<Real>& a, hipStream_t stream) {
-  if (a.n > 0) {
-    unsigned nb = (unsigned)((a.n + 255) / 256);
-    hipLaunchKernelGGL(k_finalize<Real>, dim3(nb), dim3(256), 0, stream, a);
-  }
-  hipLaunchKernelGGL(k_energy, dim3(1), dim3(256), 0, stream, (const double*)a.epart,
-                     energy_parts(a), a.energy_out, a.hdr, halve_diag(a));
+  const unsigned nb = (unsigned)((a.n + 255) / 256) + 1;
+  hipLaunchKernelGGL(k_finalize_energy<Real>, dim3(nb), dim3(256), 0, stream, a);
   return hipGetLastError();
 }
 
 hipError_t launch_finalize_batch(const Batch<float>& b0, hipStream_t stream) {
   Batch<float> b = b0;
   b.cum[0] = 0;
-  for (int s = 0; s < b.n; ++s) b.cum[s + 1] = b.cum[s] + (b.sys[s].n + 255) / 256;
-  hipLaunchKernelGGL(k_finalize_batch, dim3((unsigned)b.cum[b.n]), dim3(256), 0, stream, b);
-  for (int s = 0; s < b.n; ++s) b.cum[s + 1] = s + 1;
-  hipLaunchKernelGGL(k_energy_batch, dim3((unsigned)b.n), dim3(256), 0, stream, b);
+  for (int s = 0; s < b.n; ++s) b.cum[s + 1] = b.cum[s] + (b.sys[s].n + 255) / 256 + 1;
+  hipLaunchKernelGGL(k_finalize_energy_batch, dim3((unsigned)b.cum[b.n]), dim3(256), 0, stream, b);
   return hipGetLastError();
 }
 
