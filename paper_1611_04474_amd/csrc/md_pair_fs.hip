@@ -34,7 +34,8 @@ namespace {
 constexpr int kNW = 16;             // waves per workgroup
 constexpr int kThreads = 64 * kNW;
 constexpr int kQ = 4;               // home atoms filtered together by one wave, one FIFO each
-static_assert(kQ == 4, "the FIFO append writes four home atoms' FIFOs in one block");
+static_assert(kQ % 4 == 0, "FIFO appends are written four home atoms at a time");
+static_assert(kNW % 4 == 0 && kNW * 64 <= 1024, "waves per workgroup");
 constexpr int kDrain = 2;           // force batches of 64 drained together from a full FIFO
 constexpr int kFifo = 64 * (kDrain + 1);   // FIFO entries (uint16 neighbour index) per atom
 constexpr int kWaveFifo = kQ * kFifo;
@@ -569,7 +570,10 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
                 (unsigned)(m[k] >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m[k], 0u));
             adr[k] = fb[k] + 2u * rank;
           }
-          lds_store_u16_lanes4(adr[0], adr[1], adr[2], adr[3], (uint32_t)j, m[0], m[1], m[2], m[3]);
+#pragma unroll
+          for (int k = 0; k < kQ; k += 4)
+            lds_store_u16_lanes4(adr[k], adr[k + 1], adr[k + 2], adr[k + 3], (uint32_t)j, m[k],
+                                 m[k + 1], m[k + 2], m[k + 3]);
 #pragma unroll
           for (int k = 0; k < kQ; ++k) fb[k] = lshl1_add((uint32_t)__builtin_popcountll(m[k]), fb[k]);
           if (diag) {
@@ -640,8 +644,9 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
   // workgroup energy: each pair was seen from both atoms
   long long* sE = reinterpret_cast<long long*>(s_dyn + LL.f4);
   sE[tid] = e_fix;
+  for (int e = kThreads + tid; e < 1024; e += kThreads) sE[e] = 0;   // pad the tree to 1024
   __syncthreads();
-  for (int off = kThreads / 2; off > 0; off >>= 1) {
+  for (int off = 512; off > 0; off >>= 1) {
     if (tid < off) sE[tid] += sE[tid + off];
     __syncthreads();
   }
@@ -661,7 +666,7 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
 }
 
 template <bool kSwitchCoulomb, bool kClamp, bool kDiag>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNW / 4, kNW / 4)))
 void k_pair_fs(SysArgs<float> a, int cap) {
   // home cells in decreasing order of atom count, spread over the XCDs in turn
   pair_fs<kSwitchCoulomb, kClamp, kDiag>(a, cap, a.order[blockIdx.x]);
@@ -669,7 +674,7 @@ void k_pair_fs(SysArgs<float> a, int cap) {
 
 // One launch for a batch: block b is cell order[b - cum[s]] of system s.
 template <bool kSwitchCoulomb, bool kClamp, bool kDiag>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNW / 4, kNW / 4)))
 void k_pair_fs_batch(Batch<float> b, int cap) {
   int64_t unit;
   const int s = b.pick(blockIdx.x, unit);
