@@ -32,6 +32,11 @@ PEAK_FP32_TFLOPS = 157.3       # MI355X published float32 vector peak
 FLOP_PER_CANDIDATE = 8         # filter: 3 sub, 1 mul, 2 fma (fma = 2)
 FLOP_PER_PAIR = 40             # force, switch, accumulation
 METRIC = "within-cutoff pair-interactions/s @92k atoms; p50/p99 latency mixed batch"
+# HBM bytes per launch of the pair kernel at 92,224 atoms, from the FETCH_SIZE and
+# WRITE_SIZE counters scaled by a copy of known size (profiles/traffic_pair_fs_92k.md);
+# valid only for the kernel source they were taken on
+PAIR_TRAFFIC = {"kernel_sha256": "0f7167b5040f40bc94cb52ccbdad8f1aa7ed571d225f3bff2c9bbfedea8058ca",
+                "bytes": (14502 + 2205) * 1024}
 
 
 def parse():
@@ -49,7 +54,27 @@ def parse():
                     help="requests of the serving form (0 disables it)")
     ap.add_argument("--scaling-evals", type=int, default=20,
                     help="evaluations of the 1,066,628-atom scaling shape (0 disables it)")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="run a plain copy kernel over this many MiB (read and write) before "
+                         "the benchmark, as the reference point of HBM byte counters")
+    ap.add_argument("--ablation-steps", type=int, default=10,
+                    help="pair-stage timings per data flow in the compacted vs predicated "
+                         "comparison (0 disables it)")
     return ap.parse_args()
+
+
+def pair_traffic(args):
+    """Counter-measured HBM bytes per pair-kernel launch, or None when the kernel source
+    or the configuration differs from the one they were taken on."""
+    import hashlib
+    if args.workload != "apoa1" or args.mode != "compact" or args.accum != "fixed64":
+        return None
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1611_04474_amd",
+                       "csrc", "md_pair_fs.hip")
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != PAIR_TRAFFIC["kernel_sha256"]:
+            return None
+    return PAIR_TRAFFIC["bytes"]
 
 
 def pct(v, q):
@@ -68,6 +93,14 @@ def main():
     from paper_1611_04474_amd import workloads as W
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration_mb > 0:
+        # a plain elementwise copy (y = x + 0): reads and writes exactly this many bytes
+        n_el = args.copy_calibration_mb * (1 << 20) // 4
+        xc = torch.ones(n_el, dtype=torch.float32, device=dev)
+        yc = torch.empty_like(xc)
+        torch.add(xc, 0.0, out=yc)
+        torch.cuda.synchronize()
+        del xc, yc
     s = W.apoa1_system() if args.workload == "apoa1" else W.stmv_system()
     flags = (api.PAIR_PREDICATED if args.mode == "predicated" else 0) | \
             (api.ACCUM_F32_ATOMIC if args.accum == "f32atomic" else 0)
@@ -83,7 +116,7 @@ def main():
     # candidate and pair counts of this workload, from the kernel's own counters
     api.forces(P.with_flags(flags | api.DIAG_COUNTERS), pos, typ, q, force=force, energy=energy,
                workspace=ws)
-    n_cand, n_filter, n_pairs, n_slots = api.read_diag(ws)
+    n_cand, n_filter, n_pairs, n_slots, n_lanes = api.read_diag(ws)
     flop_per_launch = FLOP_PER_CANDIDATE * n_cand + FLOP_PER_PAIR * n_pairs
 
     def step(evs=None):
@@ -147,7 +180,9 @@ def main():
             "r_cut_A": 12.0, "r_switch_A": 10.0, "n_types": 8,
             "pair_mode": args.mode, "accumulation": args.accum,
             "candidates_per_step": n_cand, "filter_passes_per_step": n_filter,
-            "candidates_examined_per_step": n_slots, "pairs_per_step": n_pairs,
+            "candidates_examined_per_step": n_slots, "force_lanes_per_step": n_lanes,
+            "force_lane_utilisation": n_pairs / n_lanes if n_lanes else None,
+            "pairs_per_step": n_pairs,
         },
         "stage_ms": {"bin": statistics.mean(bin_ms), "pair": statistics.mean(pair_ms),
                      "finalize": statistics.mean(fin_ms)},
@@ -163,7 +198,7 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
             "flop_per_launch": flop_per_launch,
-            "traffic": None,
+            "traffic": pair_traffic(args),
         },
     }
     del ws, force, energy, pos, typ, q
@@ -176,6 +211,8 @@ def main():
                                      "2k-200k atoms at 200 req/s, continuous batching"}
     if args.scaling_evals > 0:
         out["scaling_1m"] = scaling(args.scaling_evals, dev)
+    if args.ablation_steps > 0:
+        out["ablation_data_flow"] = ablation(args.ablation_steps, dev)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds)
         out["config"]["pairs_oracle_fp64"] = out["cpu_baseline"].pop("n_pairs")
@@ -233,7 +270,7 @@ def scaling(n_eval, dev):
     ws = api.alloc_workspace(P, s.n, dev)
     api.forces(P.with_flags(api.DIAG_COUNTERS), pos, typ, q, force=force, energy=energy,
                workspace=ws)
-    n_cand, _, n_pairs, _ = api.read_diag(ws)
+    n_cand, _, n_pairs, _, _ = api.read_diag(ws)
     stream = torch.cuda.current_stream()
     # positions of each evaluation: x += N(0, 0.01 A) per call, wrapped by the call
     xs, x = [], s.pos
@@ -260,6 +297,48 @@ def scaling(n_eval, dev):
             "pairs_first_eval": n_pairs, "candidates_first_eval": n_cand,
             "pairs_per_s": n_pairs / (med * 1e-3),
             "whole_eval_algorithmic_TFLOPs": flop / (med * 1e-3) / 1e12}
+
+
+def ablation(steps, dev):
+    """The paper's dynamic data flow on a GPU: the compacted kernel (cutoff filter feeding
+    dense force passes through FIFOs) against the predicated one (every candidate through
+    the force arithmetic under the cutoff predicate), on the 92,224-atom system: pair-stage
+    time, force-stage lane utilisation (pairs / lanes through the force arithmetic)."""
+    import torch
+    from paper_1611_04474_amd import api
+    from paper_1611_04474_amd import workloads as W
+    s = W.apoa1_system()
+    pos = torch.as_tensor(s.pos).to(dev)
+    typ = torch.as_tensor(s.types).to(dev)
+    q = torch.as_tensor(s.charges).to(dev)
+    force = torch.empty((s.n, 3), dtype=torch.float32, device=dev)
+    energy = torch.empty(1, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, flags in (("compacted_full_shell", 0), ("predicated_half_shell", api.PAIR_PREDICATED)):
+        P = api.Params.from_dict(s.params(), flags)
+        ws = api.alloc_workspace(P, s.n, dev)
+        api.forces(P.with_flags(flags | api.DIAG_COUNTERS), pos, typ, q, force=force,
+                   energy=energy, workspace=ws)
+        cand, _, pairs, _, lanes = api.read_diag(ws)
+        ms = []
+        for k in range(steps + 2):
+            api.forces_stages(P, pos, typ, q, force, energy, ws, api.STAGE_BIN)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            api.forces_stages(P, pos, typ, q, force, energy, ws, api.STAGE_PAIR)
+            b.record(stream)
+            api.forces_stages(P, pos, typ, q, force, energy, ws, api.STAGE_FINALIZE)
+            torch.cuda.synchronize()
+            if k >= 2:
+                ms.append(a.elapsed_time(b))
+        med = pct(ms, 50)
+        out[name] = {"pair_ms_median": med, "pairs": pairs, "force_lanes": lanes,
+                     "force_lane_utilisation": pairs / lanes if lanes else None,
+                     "pairs_per_s_pair_stage": pairs / (med * 1e-3)}
+    out["speedup_compacted"] = (out["predicated_half_shell"]["pair_ms_median"] /
+                                out["compacted_full_shell"]["pair_ms_median"])
+    return out
 
 
 def cpu_baseline(s, budget_s):

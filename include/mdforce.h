@@ -166,10 +166,13 @@ md_status md_read_device_status(const void* d_ws, void* stream, uint32_t* bits);
  *       kernel, the cutoff test itself for the predicated one);
  *   [2] pairs inside the cutoff;
  *   [3] candidate pairs the filter stage actually examined (the compacted kernel skips
- *       neighbours outside an x-window of its home atoms; equal to [0] otherwise).
- * For the float32 compacted kernel, which sees every pair from both atoms, [1] and [3]
- * are half of its per-atom counts. Synchronises `stream`. */
-md_status md_read_diag(const void* d_ws, void* stream, uint64_t counters[4]);
+ *       neighbours outside an x-window of its home atoms; equal to [0] otherwise);
+ *   [4] lanes that went through the force arithmetic (the compacted kernel's dense
+ *       passes; every candidate for the predicated kernel), so [2] / [4] is the force
+ *       stage's lane utilisation.
+ * For the float32 compacted kernel, which sees every pair from both atoms, [1], [3] and
+ * [4] are half of its per-atom counts. Synchronises `stream`. */
+md_status md_read_diag(const void* d_ws, void* stream, uint64_t counters[5]);
 
 /* Layout of the workspace, for inspection of intermediate results. Offsets are in
  * bytes from the workspace start.

@@ -285,7 +285,7 @@ def read_status(workspace, stream=None):
 
 
 def read_diag(workspace, stream=None):
-    v = (C.c_uint64 * 4)()
+    v = (C.c_uint64 * 5)()
     rc = lib().md_read_diag(C.c_void_p(workspace.data_ptr()), _stream_ptr(stream), v)
     if rc != MD_OK:
         raise MDError(rc, "md_read_diag")

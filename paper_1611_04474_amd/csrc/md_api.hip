@@ -308,14 +308,14 @@ md_status md_read_device_status(const void* d_ws, void* stream, uint32_t* bits) 
   return MD_OK;
 }
 
-md_status md_read_diag(const void* d_ws, void* stream, uint64_t counters[4]) {
+md_status md_read_diag(const void* d_ws, void* stream, uint64_t counters[5]) {
   if (!d_ws || !counters) return MD_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
   md::WsHeader h;
   if (hipMemcpyAsync(&h, d_ws, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess)
     return MD_ERR_HIP;
   if (hipStreamSynchronize(st) != hipSuccess) return MD_ERR_HIP;
-  for (int k = 0; k < 4; ++k) counters[k] = h.diag[k];
+  for (int k = 0; k < 5; ++k) counters[k] = h.diag[k];
   return MD_OK;
 }
 

@@ -116,7 +116,7 @@ __global__ void k_setup(SysArgs<Real> a) {
   for (int64_t i = tid; i < a.n; i += stride) clear_atom(a, i);
   if (tid == 0) {
     a.hdr->status = 0;
-    for (int k = 0; k < 4; ++k) a.hdr->diag[k] = 0;
+    for (int k = 0; k < 5; ++k) a.hdr->diag[k] = 0;
   }
 }
 
@@ -236,7 +236,7 @@ __device__ inline void bin_scan(const SysArgs<Real>& a, const TypeTable& tt, int
     uint32_t st = 0;
     for (int b = 0; b < B; ++b) st |= a.bstat[b];
     a.hdr->status = st;
-    for (int k = 0; k < 4; ++k) a.hdr->diag[k] = 0;
+    for (int k = 0; k < 5; ++k) a.hdr->diag[k] = 0;
   }
 }
 

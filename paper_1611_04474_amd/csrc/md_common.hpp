@@ -25,8 +25,9 @@ constexpr int kBinMinChunk = 4096;   // atoms per block at least
 struct WsHeader {
   uint32_t status;
   uint32_t pad0;
-  unsigned long long diag[4];   // candidates, filter passes, cutoff passes, filtered slots
-  uint32_t pad1[54];
+  unsigned long long diag[5];   // candidates, filter passes, cutoff passes, filtered slots,
+                                // force lanes evaluated
+  uint32_t pad1[52];
 };
 static_assert(sizeof(WsHeader) == 256, "header size");
 

@@ -63,7 +63,7 @@ __device__ inline void finalize(const SysArgs<Real>& a, int64_t blk) {
 
 __device__ inline void energy(const double* epart, int64_t n_tasks, double* out, WsHeader* hdr,
                               int halve_diag) {
-  if (halve_diag && threadIdx.x < 4) hdr->diag[threadIdx.x] /= 2;
+  if (halve_diag && threadIdx.x < 5) hdr->diag[threadIdx.x] /= 2;
   __shared__ double s[256];
   double acc = 0.0;
   for (int64_t t = threadIdx.x; t < n_tasks; t += 256) acc += epart[t];

@@ -306,6 +306,7 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_predicated(SysArgs<Real> 
     atomicAdd(&a.hdr->diag[1], sDiag[1]);
     atomicAdd(&a.hdr->diag[2], sDiag[1]);
     atomicAdd(&a.hdr->diag[3], sDiag[0]);
+    atomicAdd(&a.hdr->diag[4], sDiag[0]);   // every candidate goes through the force arithmetic
   }
 }
 

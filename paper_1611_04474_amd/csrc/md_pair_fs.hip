@@ -311,7 +311,7 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
   const int n_grp_q = (nA + kQ - 1) / kQ;
   const float R = __builtin_sqrtf(rc2) + kWin;
   long long e_fix = 0;   // energy in units of 2^-24 kcal/mol: exact, order-independent sums
-  unsigned long long pass_count = 0, filt_count = 0, slot_count = 0;
+  unsigned long long pass_count = 0, filt_count = 0, slot_count = 0, lane_count = 0;
   uint32_t st = 0;
   uint16_t* fifo = sFifo + w * kWaveFifo;
   // LDS byte address where FIFO k of this wave starts: fk0 + 2 k kFifo
@@ -473,6 +473,7 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
         float2 lj[kDrain];
 #pragma unroll
         for (int b = 0; b < kDrain; ++b) jj[b] = fifo[k * kFifo + 64 * b + lane];
+        if (diag) lane_count += 64 * kDrain;
 #pragma unroll
         for (int b = 0; b < kDrain; ++b) {
           pj[b] = sF[jj[b]];
@@ -662,6 +663,7 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
     atomicAdd(&a.hdr->diag[1], filt_count);
     atomicAdd(&a.hdr->diag[2], pass_count);
     atomicAdd(&a.hdr->diag[3], slot_count);
+    atomicAdd(&a.hdr->diag[4], lane_count);
   }
 }
 
