@@ -135,10 +135,33 @@ __global__ void k_bin_count(SysArgs<Real> a) {
 // counts become exclusive offsets (in place) and their total the cell count. Then the
 // exclusive scan of the counts into start[] (start[n_cells] = n), in chunks of 4096
 // with a running carry, the mixed LJ table, and (own_header) the status word.
+// Exclusive prefix sum of one value per thread over a 1024-thread workgroup: a scan
+// within each wave, then the 16 wave totals through LDS. *total gets the sum of all.
+__device__ inline int32_t block_scan_excl(int32_t v, int32_t* s_tot, int32_t* total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int32_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) s_tot[w] = x;
+  __syncthreads();
+  int32_t before = 0, all = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int32_t tk = s_tot[k];
+    before += k < w ? tk : 0;
+    all += tk;
+  }
+  __syncthreads();   // s_tot may be reused after this
+  *total = all;
+  return before + x - v;
+}
+
 template <typename Real>
 __device__ inline void bin_scan(const SysArgs<Real>& a, const TypeTable& tt, int own_header) {
-  __shared__ int32_t s[1024];
-  __shared__ int32_t carry;
+  __shared__ int32_t s_tot[16];
   const int t = threadIdx.x;
   const int64_t nc = a.n_cells;
   const int B = a.bin_blocks;
@@ -164,8 +187,8 @@ __device__ inline void bin_scan(const SysArgs<Real>& a, const TypeTable& tt, int
       a.count[c] = acc;
     }
   }
-  if (t == 0) carry = 0;
-  __syncthreads();
+  __syncthreads();   // the counts written above are read by other threads below
+  int32_t carry = 0;
   for (int64_t base = 0; base < nc; base += 4096) {
     int32_t v[4];
     int32_t sum = 0;
@@ -174,23 +197,14 @@ __device__ inline void bin_scan(const SysArgs<Real>& a, const TypeTable& tt, int
       v[k] = idx < nc ? a.count[idx] : 0;
       sum += v[k];
     }
-    s[t] = sum;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {   // inclusive Hillis-Steele scan
-      const int32_t add = t >= off ? s[t - off] : 0;
-      __syncthreads();
-      s[t] += add;
-      __syncthreads();
-    }
-    int32_t run = carry + s[t] - sum;             // exclusive prefix of this thread
+    int32_t chunk;
+    int32_t run = carry + block_scan_excl(sum, s_tot, &chunk);
     for (int k = 0; k < 4; ++k) {
       const int64_t idx = base + 4 * t + k;
       if (idx < nc) a.start[idx] = run;
       run += v[k];
     }
-    __syncthreads();
-    if (t == 1023) carry += s[1023];
-    __syncthreads();
+    carry += chunk;
   }
   if (t == 0) a.start[nc] = carry;
   // launch order of the pair kernel: counting sort of the cells by decreasing count
@@ -206,16 +220,9 @@ __device__ inline void bin_scan(const SysArgs<Real>& a, const TypeTable& tt, int
   }
   __syncthreads();
   {
-    const int32_t own = s_bin[t];
-    for (int off = 1; off < 1024; off <<= 1) {
-      const int32_t add = t >= off ? s_bin[t - off] : 0;
-      __syncthreads();
-      s_bin[t] += add;
-      __syncthreads();
-    }
-    const int32_t excl = s_bin[t] - own;
-    __syncthreads();
-    s_bin[t] = excl;
+    int32_t all;
+    const int32_t excl = block_scan_excl(s_bin[t], s_tot, &all);
+    s_bin[t] = excl;   // each thread rewrites only its own bin, read above
     __syncthreads();
   }
   for (int64_t c = t; c < nc; c += 1024) {
@@ -252,6 +259,25 @@ __global__ __launch_bounds__(1024) void k_bin_scan_batch(Batch<float> b, TypeTab
   bin_scan(b.sys[s], tt, 1);
 }
 
+// z half of an atom in its cell: 1 if 2 z n_z / L_z reaches the cell's middle.
+template <typename Real>
+__device__ inline int z_half(const SysArgs<Real>& a, Real z, int cz) {
+  return (int)(z * a.inv_w[2] * Real(2)) >= 2 * cz + 1 ? 1 : 0;
+}
+
+// Sort key of atom i of cell cz (z index) with wrapped x and z: (z half, x as float32
+// bits, original index) in bits 63, 62..31 and 30..0. Wrapped x is >= +0, where the bits
+// of a float order as its value (31 bits: the sign bit is 0).
+template <typename Real>
+__device__ inline unsigned long long sort_key(const SysArgs<Real>& a, int32_t i, float x, Real z,
+                                              int cz) {
+  return ((unsigned long long)z_half(a, z, cz) << 63) |
+         ((unsigned long long)__builtin_bit_cast(uint32_t, x + 0.f) << 31) | (uint32_t)i;
+}
+
+// Each atom goes to its cell's range (in arbitrary order) with its sort key, its wrapped
+// (x, y, z, q) and its type, read here in the caller's order (coalesced), so the in-cell
+// sort only touches its own cell's range.
 template <typename Real>
 __device__ inline void scatter(const SysArgs<Real>& a, int64_t blk) {
   const int64_t i = blk * 256 + threadIdx.x;
@@ -259,7 +285,18 @@ __device__ inline void scatter(const SysArgs<Real>& a, int64_t blk) {
   const int c = a.cell[i];
   int32_t slot = a.start[c] + a.rank[i];
   if (a.bin_blocks > 0) slot += a.bhist[(i / a.bin_chunk) * a.n_cells + c];
-  a.unsorted[slot] = (int32_t)i;
+  const int cz = (int)(c / ((int64_t)a.nx * a.ny));
+  uint32_t st = 0;
+  P4<Real> p;
+  p.x = wrap_coord(a.pos_in[3 * i + 0], a.L[0], st);
+  p.y = wrap_coord(a.pos_in[3 * i + 1], a.L[1], st);
+  p.z = wrap_coord(a.pos_in[3 * i + 2], a.L[2], st);
+  p.w = a.q_in[i];
+  int t = a.type_in[i];
+  if (t < 0 || t >= a.n_types) t = 0;
+  a.ukey[slot] = sort_key(a, (int32_t)i, (float)p.x, p.z, cz);
+  a.upos[slot] = p;
+  a.unsorted[slot] = t;
 }
 
 template <typename Real>
@@ -271,27 +308,9 @@ __global__ __launch_bounds__(256) void k_scatter_batch(Batch<float> b) {
   scatter(b.sys[s], blk);
 }
 
-// z half of an atom in its cell: 1 if 2 z n_z / L_z reaches the cell's middle.
-template <typename Real>
-__device__ inline int z_half(const SysArgs<Real>& a, Real z, int cz) {
-  return (int)(z * a.inv_w[2] * Real(2)) >= 2 * cz + 1 ? 1 : 0;
-}
-
-// Sort key of an atom of cell cz (z index): (z half, wrapped x as float32 bits, original
-// index) in bits 63, 62..31 and 30..0. Wrapped x is >= +0, where the bits of a float
-// order as its value (31 bits: the sign bit is 0).
-template <typename Real>
-__device__ inline unsigned long long sort_key(const SysArgs<Real>& a, int32_t i, int cz) {
-  uint32_t st = 0;
-  const float x = (float)wrap_coord(a.pos_in[3 * (int64_t)i], a.L[0], st) + 0.f;
-  const Real z = wrap_coord(a.pos_in[3 * (int64_t)i + 2], a.L[2], st);
-  return ((unsigned long long)z_half(a, z, cz) << 63) |
-         ((unsigned long long)__builtin_bit_cast(uint32_t, x) << 31) | (uint32_t)i;
-}
-
 // One workgroup per cell. Each member's position in the cell is the number of members
-// with a smaller key, counted over LDS chunks of the member list, so any cell
-// occupancy is handled.
+// with a smaller key, counted over LDS chunks of the cell's keys, so any cell occupancy
+// is handled; the member's data then move to that position.
 template <typename Real>
 __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
   constexpr int kChunk = 1024;
@@ -300,23 +319,20 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
   __shared__ int32_t s_low;
   const int32_t s0 = a.start[c];
   const int32_t m = a.start[c + 1] - s0;
-  const int cz = (int)(c / ((int64_t)a.nx * a.ny));
   if (threadIdx.x == 0) s_low = 0;
   for (int32_t a0 = 0; a0 < m; a0 += kChunk) {
     const int kk = min(kPer, (m - a0 + 255) / 256);   // member slots in use (uniform)
-    int32_t my_idx[kPer];
     unsigned long long my_key[kPer];
     int32_t my_rank[kPer];
     for (int k = 0; k < kPer; ++k) {
       const int32_t e = a0 + (int32_t)threadIdx.x + 256 * k;
-      my_idx[k] = (k < kk && e < m) ? a.unsorted[s0 + e] : -1;
-      my_key[k] = my_idx[k] >= 0 ? sort_key(a, my_idx[k], cz) : ~0ull;
+      my_key[k] = (k < kk && e < m) ? a.ukey[s0 + e] : ~0ull;
       my_rank[k] = 0;
     }
     for (int32_t b0 = 0; b0 < m; b0 += kChunk) {
       const int32_t mb = min(kChunk, m - b0);
       __syncthreads();
-      for (int32_t e = threadIdx.x; e < mb; e += 256) s_key[e] = sort_key(a, a.unsorted[s0 + b0 + e], cz);
+      for (int32_t e = threadIdx.x; e < mb; e += 256) s_key[e] = a.ukey[s0 + b0 + e];
       for (int32_t e = mb + (int32_t)threadIdx.x; e < ((mb + 3) & ~3); e += 256) s_key[e] = ~0ull;
       __syncthreads();
       for (int32_t e = 0; e < mb; e += 4) {
@@ -329,24 +345,13 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
       }
     }
     for (int k = 0; k < kPer; ++k) {
-      const int32_t i = my_idx[k];
-      if (i < 0) continue;
-      uint32_t st = 0;
-      const Real x = wrap_coord(a.pos_in[3 * (int64_t)i + 0], a.L[0], st);
-      const Real y = wrap_coord(a.pos_in[3 * (int64_t)i + 1], a.L[1], st);
-      const Real z = wrap_coord(a.pos_in[3 * (int64_t)i + 2], a.L[2], st);
-      int t = a.type_in[i];
-      if (t < 0 || t >= a.n_types) t = 0;
+      const int32_t e = a0 + (int32_t)threadIdx.x + 256 * k;
+      if (!(k < kk && e < m)) continue;
       const int32_t d = s0 + my_rank[k];
       if (!(my_key[k] >> 63)) atomicAdd(&s_low, 1);
-      P4<Real> p;
-      p.x = x;
-      p.y = y;
-      p.z = z;
-      p.w = a.q_in[i];
-      a.pos[d] = p;
-      a.type[d] = t;
-      a.perm[d] = i;
+      a.pos[d] = a.upos[s0 + e];
+      a.type[d] = a.unsorted[s0 + e];
+      a.perm[d] = (int32_t)(my_key[k] & 0x7fffffffull);
     }
   }
   __syncthreads();

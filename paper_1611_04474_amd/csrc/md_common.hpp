@@ -19,7 +19,7 @@ constexpr int64_t kMaxCells = 1 << 24;
 constexpr int64_t kMaxAtoms = (int64_t)1 << 30;
 constexpr int kBinLdsCells = 32768;  // largest grid binned with a per-block LDS histogram
 constexpr int kBinMaxBlocks = 64;    // blocks of that pass
-constexpr int kBinMinChunk = 4096;   // atoms per block at least
+constexpr int kBinMinChunk = 2048;   // atoms per block at least
 
 // Workspace header (first 256 bytes).
 struct WsHeader {
@@ -46,7 +46,7 @@ struct Plan {
   // byte offsets
   size_t off_count, off_start, off_cell, off_rank, off_unsorted, off_pos, off_type, off_perm,
       off_part, off_facc, off_epart, off_lj, off_paircount, off_bhist, off_bstat, off_order,
-      off_zsplit, total;
+      off_zsplit, off_ukey, off_upos, total;
   int bin_blocks;               // blocks of the LDS-histogram binning pass (0: global atomics)
   int64_t bin_chunk;            // atoms per such block
 };
@@ -69,7 +69,9 @@ struct SysArgs {
   int32_t* start;              // [n_cells+1]
   int32_t* cell;               // [n]
   int32_t* rank;               // [n]
-  int32_t* unsorted;           // [n]
+  int32_t* unsorted;           // [n] types, in cell order before the in-cell sort
+  unsigned long long* ukey;    // [n] in-cell sort keys, same order
+  P4<Real>* upos;              // [n] wrapped (x, y, z, q), same order
   P4<Real>* pos;               // [n] sorted (x,y,z,q)
   int32_t* type;               // [n] sorted
   int32_t* perm;               // [n] sorted -> original
