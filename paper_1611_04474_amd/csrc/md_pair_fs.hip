@@ -466,7 +466,34 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
       // dense force passes over the first c entries of FIFO k (c <= 64 * kDrain): the exact
       // distance in the current frame, the strict cutoff (u > 0 drops the home atom
       // itself) and the force. All LDS reads of the kDrain batches precede the arithmetic.
-      auto force = [&](int k, int c) __attribute__((always_inline)) {
+      // the force on home atom k from one lane's FIFO entry: the exact distance in the
+      // current frame, the strict cutoff (u > 0 drops the home atom itself) and the force;
+      // `in` is false for lanes past the FIFO's fill level
+      auto pair_lane = [&](int k, const float4& pj, float qj, const float2& lj, bool in)
+          __attribute__((always_inline)) {
+        const float dx = xs[k] - pj.x, dy = ys[k] - pj.y, dz = zs[k] - pj.z;
+        float u = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        float e, f;
+        if (kClamp) {
+          u = (in && u > 0.f) ? u : kBigU;
+          f = pair_f<kSwitchCoulomb>(u, lj.x, lj.y, kq[k] * qj, rs2, inv_sw, sw12, e);
+          if (diag) cnt[k] += __builtin_popcountll(__builtin_amdgcn_ballot_w64(u < rc2));
+        } else {
+          const bool lv = in && u < rc2 && u > 0.f;
+          f = pair_f<kSwitchCoulomb>(u, lj.x, lj.y, kq[k] * qj, rs2, inv_sw, sw12, e);
+          f = lv ? f : 0.f;
+          e = lv ? e : 0.f;
+          if (diag) cnt[k] += __builtin_popcountll(__builtin_amdgcn_ballot_w64(lv));
+        }
+        fx[k] = fmaf(f, dx, fx[k]);
+        fy[k] = fmaf(f, dy, fy[k]);
+        fz[k] = fmaf(f, dz, fz[k]);
+        e_lane += e;
+      };
+      // dense force passes over the first 64 kDrain entries of FIFO k, every lane busy; all
+      // LDS reads of the kDrain batches precede the arithmetic. The remainder (fewer than
+      // 64 entries) moves to the front.
+      auto force = [&](int k) __attribute__((always_inline)) {
         int jj[kDrain], tj[kDrain];
         float4 pj[kDrain];
         float qj[kDrain];
@@ -483,28 +510,8 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
 #pragma unroll
         for (int b = 0; b < kDrain; ++b) lj[b] = sLJ[row[k] + tj[b]];
 #pragma unroll
-        for (int b = 0; b < kDrain; ++b) {
-          const float dx = xs[k] - pj[b].x, dy = ys[k] - pj[b].y, dz = zs[k] - pj[b].z;
-          float u = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-          const bool in = c >= 64 * kDrain || 64 * b + lane < c;   // full passes: all lanes
-          float e, f;
-          if (kClamp) {
-            u = (in && u > 0.f) ? u : kBigU;
-            f = pair_f<kSwitchCoulomb>(u, lj[b].x, lj[b].y, kq[k] * qj[b], rs2, inv_sw, sw12, e);
-            if (diag) cnt[k] += __builtin_popcountll(__builtin_amdgcn_ballot_w64(u < rc2));
-          } else {
-            const bool lv = in && u < rc2 && u > 0.f;
-            f = pair_f<kSwitchCoulomb>(u, lj[b].x, lj[b].y, kq[k] * qj[b], rs2, inv_sw, sw12, e);
-            f = lv ? f : 0.f;
-            e = lv ? e : 0.f;
-            if (diag) cnt[k] += __builtin_popcountll(__builtin_amdgcn_ballot_w64(lv));
-          }
-          fx[k] = fmaf(f, dx, fx[k]);
-          fy[k] = fmaf(f, dy, fy[k]);
-          fz[k] = fmaf(f, dz, fz[k]);
-          e_lane += e;
-        }
-        // drop the first c entries; the remainder (fewer than 64) moves to the front
+        for (int b = 0; b < kDrain; ++b) pair_lane(k, pj[b], qj[b], lj[b], true);
+        const int c = 64 * kDrain;
         const int rem = fill(k) - c;
         if (rem > 0) {
           uint16_t v = 0;
@@ -513,10 +520,21 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
         }
         fb[k] = fk0 + 2u * (uint32_t)(k * kFifo + rem);
       };
+      // every entry left in the FIFOs, one 64-lane pass at a time (the home side is about
+      // to change frame, or the group is done)
       auto flush = [&]() __attribute__((always_inline)) {
 #pragma unroll
         for (int k = 0; k < kQ; ++k) {
-          while (fill(k) > 0) force(k, fill(k) < 64 * kDrain ? fill(k) : 64 * kDrain);
+          const int n = fill(k);
+          for (int off = 0; off < n; off += 64) {
+            const int jj = fifo[k * kFifo + off + lane];   // entries past n: valid indices
+            if (diag) lane_count += 64;
+            const float4 pj = sF[jj];
+            const float qj = sQ[jj];
+            const float2 lj = sLJ[row[k] + sT[jj]];
+            pair_lane(k, pj, qj, lj, off + lane < n);
+          }
+          fb[k] = fk0 + 2u * (uint32_t)(k * kFifo);
         }
       };
 
@@ -583,7 +601,7 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
           }
 #pragma unroll
           for (int k = 0; k < kQ; ++k) {
-            if (fb[k] >= fl[k]) force(k, 64 * kDrain);
+            if (fb[k] >= fl[k]) force(k);
           }
         }
       }
