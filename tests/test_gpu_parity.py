@@ -424,3 +424,38 @@ def test_precision_form_report(gpu):
     for name in report:
         assert report[name]["max_norm"] <= 1e-5 and report[name]["rms"] <= 1e-5, report
         assert report[name]["energy_rel"] <= 1e-6, report
+
+
+@pytest.mark.parametrize("case", ["truncated_coulomb", "no_switch", "sixty_four_types"])
+def test_fp32_kernel_variants(gpu, case):
+    """The float32 compacted kernel's other instantiations against the oracle: Coulomb
+    truncated (only LJ switched), switching off (r_switch = r_cut: lanes are masked, not
+    clamped), and 64 atom types (the largest LJ table, the smallest LDS neighbour load)."""
+    _say("case: float32 kernel variant", case)
+    if case == "sixty_four_types":
+        s = W.gen_system(20000, (60.0, 60.0, 55.0), 13, n_types=64)
+        p = s.params()
+    else:
+        s = W.small_system()
+        p = s.params()
+        if case == "truncated_coulomb":
+            p = dict(p, flags=api.COULOMB_TRUNCATED)
+        else:
+            p = dict(p, r_switch=p["r_cut"])
+    f, e, ws, cnt = run(p, s.pos, s.types, s.charges, gpu, flags=p.get("flags", 0) | api.DIAG_COUNTERS)
+    if case == "sixty_four_types":
+        _check_fp32(p, s.pos, s.types, s.charges, f, e, cnt)
+        return
+    # without a switch at r_cut the force jumps there: an atom with a partner within 8
+    # float32 ulps of rc^2 may see that pair classified differently in float32 and FP64,
+    # so those atoms are compared for partner counts only and reported
+    r = _ref(p, s.pos, s.types, s.charges)
+    band, nb = oracle.band_atoms(p, s.pos, BAND)
+    keep = band == 0
+    err = force_errors(f[keep], r.force[keep], r.abs_sum[keep])
+    _say("fp32 errors (atoms off the cutoff band)", err, "band atoms", int((~keep).sum()))
+    assert err["max_norm"] <= 1e-5 and err["rms"] <= 1e-5, err
+    ok = (cnt == r.count) | (band > 0)
+    assert ok.all()
+    if nb == 0:
+        assert e == pytest.approx(r.energy, rel=1e-6, abs=1e-6)
