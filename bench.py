@@ -35,8 +35,8 @@ METRIC = "within-cutoff pair-interactions/s @92k atoms; p50/p99 latency mixed ba
 # HBM bytes per launch of the pair kernel at 92,224 atoms, from the FETCH_SIZE and
 # WRITE_SIZE counters scaled by a copy of known size (profiles/traffic_pair_fs_92k.md);
 # valid only for the kernel source they were taken on
-PAIR_TRAFFIC = {"kernel_sha256": "0f7167b5040f40bc94cb52ccbdad8f1aa7ed571d225f3bff2c9bbfedea8058ca",
-                "bytes": (14502 + 2205) * 1024}
+PAIR_TRAFFIC = {"kernel_sha256": "ef8ef20c0a9d4386d2a394b4e72353e9bbd4a3de820fa9089f77c3180e32b67b",
+                "bytes": (14463 + 2205) * 1024}
 
 
 def parse():
@@ -44,7 +44,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--mode", choices=["compact", "predicated"], default="compact")
+    ap.add_argument("--mode", choices=["compact", "compact_full", "predicated"], default="compact",
+                    help="compacted half shell (default), compacted full shell, or the "
+                         "predicated (uncompacted) half shell")
     ap.add_argument("--accum", choices=["fixed64", "f32atomic"], default="fixed64")
     ap.add_argument("--workload", choices=["apoa1", "stmv"], default="apoa1")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -106,7 +108,8 @@ def main():
         torch.cuda.synchronize()
         del xc, yc
     s = W.apoa1_system() if args.workload == "apoa1" else W.stmv_system()
-    flags = (api.PAIR_PREDICATED if args.mode == "predicated" else 0) | \
+    flags = {"compact": 0, "compact_full": api.PAIR_FULL_SHELL,
+             "predicated": api.PAIR_PREDICATED}[args.mode] | \
             (api.ACCUM_F32_ATOMIC if args.accum == "f32atomic" else 0)
     P = api.Params.from_dict(s.params(), flags)
     pos = torch.as_tensor(s.pos).to(dev)
@@ -195,7 +198,7 @@ def main():
         "latency_ms_plain_92k": {"p50": pct(lat, 50), "p99": pct(lat, 99),
                                  "kind": "plain path, one 92,224-atom system per call"},
         "roofline": {
-            "kernel": "k_pair_fs (filter + force)",
+            "kernel": "k_pair_fs (filter + force; half shell unless --mode says otherwise)",
             "bound": "alu",
             "achieved": achieved,
             "peak": PEAK_FP32_TFLOPS,
@@ -313,9 +316,11 @@ def scaling(n_eval, dev):
 
 def ablation(steps, dev):
     """The paper's dynamic data flow on a GPU: the compacted kernel (cutoff filter feeding
-    dense force passes through FIFOs) against the predicated one (every candidate through
-    the force arithmetic under the cutoff predicate), on the 92,224-atom system: pair-stage
-    time, force-stage lane utilisation (pairs / lanes through the force arithmetic)."""
+    dense force passes through FIFOs), in its half-shell and full-shell forms, against the
+    predicated one (every candidate through the force arithmetic under the cutoff
+    predicate), on the 92,224-atom system: pair-stage time, force-stage lane utilisation
+    (unique pairs / lanes through the force arithmetic; the full shell evaluates every
+    pair twice, so its figure is at most 0.5)."""
     import torch
     from paper_1611_04474_amd import api
     from paper_1611_04474_amd import workloads as W
@@ -327,7 +332,8 @@ def ablation(steps, dev):
     energy = torch.empty(1, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
     out = {}
-    for name, flags in (("compacted_full_shell", 0), ("predicated_half_shell", api.PAIR_PREDICATED)):
+    for name, flags in (("compacted_half_shell", 0), ("compacted_full_shell", api.PAIR_FULL_SHELL),
+                        ("predicated_half_shell", api.PAIR_PREDICATED)):
         P = api.Params.from_dict(s.params(), flags)
         ws = api.alloc_workspace(P, s.n, dev)
         api.forces(P.with_flags(flags | api.DIAG_COUNTERS), pos, typ, q, force=force,
@@ -349,7 +355,9 @@ def ablation(steps, dev):
                      "force_lane_utilisation": pairs / lanes if lanes else None,
                      "pairs_per_s_pair_stage": pairs / (med * 1e-3)}
     out["speedup_compacted"] = (out["predicated_half_shell"]["pair_ms_median"] /
-                                out["compacted_full_shell"]["pair_ms_median"])
+                                out["compacted_half_shell"]["pair_ms_median"])
+    out["speedup_half_over_full_shell"] = (out["compacted_full_shell"]["pair_ms_median"] /
+                                           out["compacted_half_shell"]["pair_ms_median"])
     return out
 
 

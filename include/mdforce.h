@@ -58,13 +58,19 @@ typedef enum {
 enum {
   MD_ACCUM_FIXED64 = 0,         /* default: per-atom sums in 64-bit fixed point (2^-32 kcal/mol/A) */
   MD_ACCUM_F32_ATOMIC = 1 << 0, /* per-atom sums in float32: with float32 atomics (order-
-                                   dependent) in the half-shell kernels; in the compacted
-                                   float32 kernel, which owns each atom in one wave, as a
-                                   fixed-order float32 sum */
+                                   dependent) in the predicated kernels; on the compacted path
+                                   by the full-shell kernel, which owns each atom in one wave,
+                                   as a fixed-order float32 sum */
   MD_COULOMB_TRUNCATED = 1 << 1,/* switch only the LJ energy; Coulomb is Eq. 2 up to r_cut */
   MD_DIAG_COUNTERS = 1 << 2,    /* count candidates, filter passes and per-atom partners */
-  MD_PAIR_PREDICATED = 1 << 3   /* evaluate the force under the cutoff predicate, without
+  MD_PAIR_PREDICATED = 1 << 3,  /* evaluate the force under the cutoff predicate, without
                                    compacting passing pairs (the uncompacted data flow) */
+  MD_PAIR_FULL_SHELL = 1 << 4   /* compacted float32 path: evaluate every pair from both of
+                                   its atoms, in the loop order of Algorithm 1 (Section 2.1),
+                                   each atom's sum kept by one wave, no atomics. Default: each
+                                   pair once (Newton's third law), the partner's share added
+                                   with 64-bit integer atomics, which give the same sum in
+                                   any order */
 };
 
 /* Device status bits (sticky until the next force call on the workspace). */

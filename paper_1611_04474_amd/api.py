@@ -23,6 +23,7 @@ ACCUM_F32_ATOMIC = 1 << 0
 COULOMB_TRUNCATED = 1 << 1
 DIAG_COUNTERS = 1 << 2
 PAIR_PREDICATED = 1 << 3
+PAIR_FULL_SHELL = 1 << 4
 
 STATUS_NAN = 1 << 0
 STATUS_OUT_OF_BOX = 1 << 1

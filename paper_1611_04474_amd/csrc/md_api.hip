@@ -22,7 +22,7 @@ static md_status check_params(const md_params* p) {
   if (!(p->r_switch > 0) || p->r_switch > p->r_cut) return MD_ERR_INVALID_ARG;
   if (!isfinite(p->coulomb_k)) return MD_ERR_INVALID_ARG;
   const uint32_t known = MD_ACCUM_F32_ATOMIC | MD_COULOMB_TRUNCATED | MD_DIAG_COUNTERS |
-                         MD_PAIR_PREDICATED;
+                         MD_PAIR_PREDICATED | MD_PAIR_FULL_SHELL;
   if (p->flags & ~known) return MD_ERR_INVALID_ARG;
   for (int d = 0; d < 3; ++d)
     if (!isfinite(p->box[d]) || !(p->box[d] > 0)) return MD_ERR_INVALID_ARG;
@@ -63,11 +63,11 @@ md_status make_plan(const md_params* p, int64_t n, int real_bytes, Plan* pl) {
   pl->off_pos = o;       o = align_up(o + (size_t)4 * real_bytes * nn);
   pl->off_type = o;      o = align_up(o + sizeof(int32_t) * nn);
   pl->off_perm = o;      o = align_up(o + sizeof(int32_t) * nn);
-  // per-atom partials: 27 slots x 3 components for the half-shell kernel, or three
-  // 64-bit fixed-point sums for the float32 compacted full-shell kernel
-  const bool full_shell = real_bytes == 4 && !(p->flags & MD_PAIR_PREDICATED);
+  // per-atom partials: 27 slots x 3 components for the predicated kernel, or three
+  // 64-bit fixed-point sums for the float32 compacted kernel
+  const bool compact = real_bytes == 4 && !(p->flags & MD_PAIR_PREDICATED);
   pl->off_part = o;
-  o = align_up(o + (full_shell ? sizeof(long long) * 3 * nn : (size_t)real_bytes * kSlots * 3 * nn));
+  o = align_up(o + (compact ? sizeof(long long) * 3 * nn : (size_t)real_bytes * kSlots * 3 * nn));
   pl->off_facc = o;      o = align_up(o + sizeof(float) * 3 * nn);
   pl->off_epart = o;     o = align_up(o + sizeof(double) * pl->n_tasks);
   pl->off_lj = o;        o = align_up(o + (size_t)real_bytes * 2 * kMaxTypes * kMaxTypes);
@@ -117,7 +117,7 @@ SysArgs<Real> make_args(const md_params* p, const Plan& pl, int64_t n, const Rea
   a.epart = (double*)(b + pl.off_epart);
   a.lj = (Real*)(b + pl.off_lj);
   a.paircount = (int32_t*)(b + pl.off_paircount);
-  a.acc64 = (long long*)(b + pl.off_part);   // the full-shell path reuses the partial buffer
+  a.acc64 = (long long*)(b + pl.off_part);   // the compacted kernel reuses the partial buffer
   a.bhist = (int32_t*)(b + pl.off_bhist);
   a.bstat = (uint32_t*)(b + pl.off_bstat);
   a.order = (int32_t*)(b + pl.off_order);
@@ -143,7 +143,9 @@ SysArgs<Real> make_args(const md_params* p, const Plan& pl, int64_t n, const Rea
   a.inv_sw = p->r_switch < p->r_cut ? (Real)(1.0 / (rc2 - rs2)) : Real(0);
   a.coulomb_k = (Real)p->coulomb_k;
   a.flags = p->flags;
-  a.full_shell = (sizeof(Real) == 4 && !(p->flags & MD_PAIR_PREDICATED)) ? 1 : 0;
+  a.compact = (sizeof(Real) == 4 && !(p->flags & MD_PAIR_PREDICATED)) ? 1 : 0;
+  a.half_shell =
+      (a.compact && !(p->flags & (MD_ACCUM_F32_ATOMIC | MD_PAIR_FULL_SHELL))) ? 1 : 0;
   return a;
 }
 

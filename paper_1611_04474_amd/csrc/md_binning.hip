@@ -73,6 +73,11 @@ __device__ inline void clear_atom(const SysArgs<Real>& a, int64_t i) {
     a.facc[a.n + i] = 0.f;
     a.facc[2 * a.n + i] = 0.f;
   }
+  if (a.half_shell) {
+    a.acc64[i] = 0;
+    a.acc64[a.n + i] = 0;
+    a.acc64[2 * a.n + i] = 0;
+  }
   if (a.flags & MD_DIAG_COUNTERS) a.paircount[a.n + i] = 0;
 }
 

@@ -80,7 +80,7 @@ struct SysArgs {
   double* epart;               // [n_tasks]
   Real* lj;                    // [n_types^2][2] (c12, c6)
   int32_t* paircount;          // [2][n]: caller order (after finalize), sorted order (pass)
-  long long* acc64;            // [3][n] per-atom fixed-point sums (full-shell path)
+  long long* acc64;            // [3][n] per-atom fixed-point sums (compacted kernel)
   int32_t* bhist;              // [bin_blocks][n_cells] per-block cell counts, then offsets
   uint32_t* bstat;             // [bin_blocks] per-block status bits
   int32_t* order;              // [n_cells] cells by decreasing atom count (launch order)
@@ -95,7 +95,10 @@ struct SysArgs {
   Real rc2, rs2, inv_sw;       // inv_sw = 1/(rc2 - rs2), 0 when switching is off
   Real coulomb_k;
   uint32_t flags;
-  int full_shell;              // 1: per-atom sums come from the full-shell pair kernel
+  int compact;                 // 1: per-atom sums come from the compacted pair kernel (acc64,
+                               //    or facc with MD_ACCUM_F32_ATOMIC)
+  int half_shell;              // 1: the compacted kernel visits each pair once and adds
+                               //    into acc64 with integer atomics (acc64 starts at zero)
 };
 
 // Up to kBatchMax systems evaluated by one launch of each kernel of the path. The
@@ -137,10 +140,9 @@ hipError_t launch_pair(const SysArgs<Real>& a, hipStream_t stream);
 template <typename Real>
 hipError_t launch_finalize(const SysArgs<Real>& a, hipStream_t stream);
 hipError_t launch_pair_fs(const SysArgs<float>& a, hipStream_t stream);
-size_t pair_fs_lds_bytes(int n_types);
 
 // Batched float32 launchers. Every system of the batch has n > 0, uses the LDS-histogram
-// binning (bin_blocks > 0), the compacted full-shell kernel, and the same flags and
+// binning (bin_blocks > 0), the compacted kernel, and the same flags and
 // type table.
 hipError_t launch_binning_batch(const Batch<float>& b, const TypeTable& tt, hipStream_t stream);
 hipError_t launch_pair_fs_batch(const Batch<float>& b, hipStream_t stream);

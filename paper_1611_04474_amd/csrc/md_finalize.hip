@@ -46,7 +46,7 @@ __device__ inline void finalize(const SysArgs<Real>& a, int64_t blk) {
     Real v;
     if (a.flags & MD_ACCUM_F32_ATOMIC) {
       v = (Real)a.facc[(int64_t)c * a.n + s];
-    } else if (a.full_shell) {
+    } else if (a.compact) {
       v = (Real)(__ll2float_rn(a.acc64[(int64_t)c * a.n + s]) * 2.3283064365386963e-10f);
     } else if (sizeof(Real) == 4) {
       v = (Real)fixed_sum(reinterpret_cast<const float*>(a.part), a.n, c, s, st);
@@ -78,12 +78,12 @@ __device__ inline void energy(const double* epart, int64_t n_tasks, double* out,
 
 template <typename Real>
 __host__ __device__ inline int64_t energy_parts(const SysArgs<Real>& a) {
-  return a.n > 0 ? (a.full_shell ? a.n_cells * kFsSplit : a.n_tasks) : 0;
+  return a.n > 0 ? (a.compact ? a.n_cells * kFsSplit : a.n_tasks) : 0;
 }
 
 template <typename Real>
 __host__ __device__ inline int halve_diag(const SysArgs<Real>& a) {
-  return (a.full_shell && (a.flags & MD_DIAG_COUNTERS) && a.n > 0) ? 1 : 0;
+  return (a.compact && !a.half_shell && (a.flags & MD_DIAG_COUNTERS) && a.n > 0) ? 1 : 0;
 }
 
 // Blocks 0 .. ceil(n/256) - 1 finalize atoms; the block after them sums the energy

@@ -316,7 +316,7 @@ template <typename Real>
 hipError_t launch_pair(const SysArgs<Real>& a, hipStream_t stream) {
   if (a.n == 0) return hipSuccess;
   if constexpr (sizeof(Real) == 4) {
-    if (a.full_shell) return launch_pair_fs(a, stream);
+    if (a.compact) return launch_pair_fs(a, stream);
   }
   const int64_t blocks = 8 * ((a.n_tasks + 7) / 8);
   const size_t shmem = sizeof(Real) * 2 * a.n_types * a.n_types;

@@ -1,12 +1,11 @@
-// Compacted pair kernel, full shell: the loop order of Algorithm 1 (Section 2.1)
-// -- foreach home cell, foreach of its 27 neighbour cells, foreach home atom,
-// foreach neighbour atom, test the cutoff and accumulate the force on the home atom --
-// with the dynamic data flow of the enhanced design (Section 5.2, Fig. 4; Algorithm 3):
-// several cutoff filters feed one force stage through FIFOs, and the force stage only
-// ever works on pairs that passed.
+// Compacted pair kernel: the loop order of Algorithm 1 (Section 2.1) -- foreach home
+// cell, foreach of its neighbour cells, foreach home atom, foreach neighbour atom, test
+// the cutoff and accumulate the force -- with the dynamic data flow of the enhanced
+// design (Section 5.2, Fig. 4; Algorithm 3): several cutoff filters feed one force stage
+// through FIFOs, and the force stage only ever works on pairs that passed.
 //
-// One workgroup (16 waves) takes one home cell. It stages the atoms of the 27
-// neighbour-cell images in LDS, periodic images shifted exactly (the side lying in the
+// One workgroup (16 waves) takes one home cell. It stages the atoms of its neighbour-
+// cell images in LDS, periodic images shifted exactly (the side lying in the
 // last cell of an axis subtracts L, which is Sterbenz-exact). Cells are sorted by x, so
 // the images of one (dy, dz) row, laid out in x order, form one x-sorted "segment".
 // Each wave takes groups of kQ home atoms (consecutive in x) and, per segment, only the
@@ -20,12 +19,25 @@
 //   force   -- whenever a FIFO holds kDrain x 64 entries, dense passes over them with
 //              every lane busy (the "force PE"): the exact distance, the strict test
 //              u < rc^2, and the force summed on the home atom in registers.
-// Each home atom is owned by one wave, so no atomics are needed and every sum runs in
-// a fixed order. At the end the 64 lane partials are added per 16-lane row in a fixed
-// DPP order and the four row sums in 64-bit fixed point (2^-32 kcal/mol/A), exactly;
-// lane energies are summed in 64-bit fixed point (2^-24 kcal/mol), so the energy does
-// not depend on how groups of home atoms were spread over the waves either.
-// Every pair is evaluated from both of its atoms, as in Algorithm 1.
+// Each home atom is owned by one wave and its sum runs in a fixed order: the 64 lane
+// partials are added per 16-lane row in a fixed DPP order and the four row sums in
+// 64-bit fixed point (2^-32 kcal/mol/A), exactly; lane energies are summed in 64-bit
+// fixed point (2^-24 kcal/mol), so the energy does not depend on how groups of home
+// atoms were spread over the waves either.
+//
+// Two shells:
+//   full (kHalf = false) -- every pair is evaluated from both of its atoms, as in
+//              Algorithm 1, over the 27 images; each atom's sum is written by the one
+//              wave that owns it, so no atomics are needed;
+//   half (kHalf = true)  -- every pair is evaluated once (Newton's third law, F_j = -F_i):
+//              the home cell with j > i and the 13 images ahead of it. The force on the
+//              neighbour atom, rounded to 2^-24, is added in 64-bit fixed point into an
+//              LDS accumulator per staged atom (integer atomics, so the sum does not
+//              depend on the order of the adds), and the accumulators go to the per-atom
+//              sums with 64-bit global integer atomics when the workgroup is done. Integer
+//              addition is associative: the result is the same bits on every run.
+#include <type_traits>
+
 #include "md_common.hpp"
 
 namespace md {
@@ -52,6 +64,13 @@ __constant__ int8_t c_img[27][3] = {
     {-1, 1, -1},  {0, 1, -1},   {1, 1, -1},  {-1, -1, 0}, {0, -1, 0},  {1, -1, 0}, {-1, 0, 0},
     {1, 0, 0},    {-1, 1, 0},   {0, 1, 0},   {1, 1, 0},   {-1, -1, 1}, {0, -1, 1}, {1, -1, 1},
     {-1, 0, 1},   {0, 0, 1},    {1, 0, 1},   {-1, 1, 1},  {0, 1, 1},   {1, 1, 1}};
+
+// Half shell: the home image and the 13 images ahead of it (dz = +1; dz = 0 and
+// dy = +1; dz = dy = 0 and dx = +1). Of two opposite offsets exactly one is here, so
+// every pair of distinct images is visited once, from the cell that has the other ahead.
+__constant__ int8_t c_himg[14][3] = {
+    {0, 0, 0},  {-1, -1, 1}, {0, -1, 1}, {1, -1, 1}, {-1, 0, 1}, {0, 0, 1}, {1, 0, 1},
+    {-1, 1, 1}, {0, 1, 1},   {1, 1, 1},  {-1, 1, 0}, {0, 1, 0},  {1, 1, 0}, {1, 0, 0}};
 
 struct Img {
   int start;   // first sorted index of the cell
@@ -81,21 +100,28 @@ struct Hdr {
 };
 
 // LDS layout in bytes: type u8 [cap] | header | FIFOs | LJ (c12, c6) [nt^2] |
-// (x, y, z, |r - o_g|^2) [cap] | q [cap]
+// (x, y, z, |r - o_g|^2) [cap] | q [cap], and for the half shell the neighbour-side
+// accumulators (x, y, z) int64 [cap] and, with counters, partner counts int32 [cap]
 struct Lds {
-  int hdr, fifo, lj, f4, q, total;
+  int hdr, fifo, lj, f4, q, jacc, jcnt, total;
 };
 
 __host__ __device__ constexpr int align_up(int v, int a) { return (v + a - 1) / a * a; }
 
-__host__ __device__ inline Lds lds_layout(int cap, int n_types) {
+__host__ __device__ inline int slot_bytes(bool half, bool diag) {
+  return 21 + (half ? 24 + (diag ? 4 : 0) : 0);
+}
+
+__host__ __device__ inline Lds lds_layout(int cap, int n_types, bool half, bool diag) {
   Lds L;
   L.hdr = align_up(cap, 16);
   L.fifo = align_up(L.hdr + (int)sizeof(Hdr), 16);
   L.lj = align_up(L.fifo + 2 * kNW * kWaveFifo, 16);
   L.f4 = align_up(L.lj + 8 * n_types * n_types, 16);
   L.q = L.f4 + 16 * cap;
-  L.total = L.q + 4 * cap;
+  L.jacc = align_up(L.q + 4 * cap, 16);
+  L.jcnt = L.jacc + (half ? 24 * cap : 0);
+  L.total = half ? L.jcnt + (diag ? 4 * cap : 0) : L.q + 4 * cap;
   return L;
 }
 
@@ -121,6 +147,27 @@ __device__ inline long long to_fixed(float v, uint32_t& st) {
   unsigned long long m =
       ((unsigned long long)(unsigned)hi << 32) + (unsigned long long)(unsigned)lo;
   return v < 0.f ? -(long long)m : (long long)m;
+}
+
+// s * v in 64-bit fixed point of unit 2^-32, with v rounded (to nearest even) to a
+// multiple of 2^-24 on the way, for s = +-1 and |v| < 2^27. The fma places round(s v 2^24)
+// in the low mantissa bits of 1.5 * 2^52, whose bit pattern then differs from that of
+// 1.5 * 2^52 by exactly that integer.
+__device__ inline long long to_fixed24(float v, float s) {
+  const double t = __builtin_fma((double)v, (double)s * 16777216.0, 6755399441055744.0);
+  return (long long)((unsigned long long)(__builtin_bit_cast(long long, t) -
+                                          0x4338000000000000ll)
+                     << 8);
+}
+
+__device__ inline void lds_add(long long* p, long long v) {
+  __hip_atomic_fetch_add(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v,
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ inline void global_add(long long* p, long long v) {
+  __hip_atomic_fetch_add(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v,
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Pair force factor f (F_i = f r_ij) and pair energy e at squared distance u.
@@ -188,23 +235,27 @@ __device__ inline void lds_store_u16_lanes4(uint32_t a0, uint32_t a1, uint32_t a
 // nothing (a partial batch, the home atom itself) get u = kBigU instead of masks on f
 // and e, and pairs beyond the cutoff need no test (t clamps to 1).
 // kDiag: count filter passes, cutoff passes and filtered slots (MD_DIAG_COUNTERS).
-template <bool kSwitchCoulomb, bool kClamp, bool kDiag>
+// kHalf: the half shell (64-bit fixed-point sums only).
+template <bool kHalf, bool kSwitchCoulomb, bool kClamp, bool kDiag>
 __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<float>& a, int cap,
                                                               int64_t cellA) {
   extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
-  const Lds LL = lds_layout(cap, a.n_types);
+  constexpr int kImg = kHalf ? 14 : 27;   // neighbour images
+  const Lds LL = lds_layout(cap, a.n_types, kHalf, kDiag);
   uint8_t* sT = s_dyn;
   Hdr& H = *reinterpret_cast<Hdr*>(s_dyn + LL.hdr);
   uint16_t* sFifo = reinterpret_cast<uint16_t*>(s_dyn + LL.fifo);
   float2* sLJ = reinterpret_cast<float2*>(s_dyn + LL.lj);
   float4* sF = reinterpret_cast<float4*>(s_dyn + LL.f4);
   float* sQ = reinterpret_cast<float*>(s_dyn + LL.q);
+  long long* sJ = reinterpret_cast<long long*>(s_dyn + LL.jacc);   // [cap][3], half shell
+  int* sJn = reinterpret_cast<int*>(s_dyn + LL.jcnt);               // [cap], half + counters
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int nt = a.n_types;
   constexpr bool diag = kDiag;
-  const bool f32 = (a.flags & MD_ACCUM_F32_ATOMIC) != 0;
+  const bool f32 = !kHalf && (a.flags & MD_ACCUM_F32_ATOMIC) != 0;
   const float rc2 = a.rc2, rs2 = a.rs2, inv_sw = a.inv_sw, sw12 = 12.f * a.inv_sw;
   const float kc = a.coulomb_k;
   const float L0 = a.L[0], L1 = a.L[1], L2 = a.L[2];
@@ -223,20 +274,24 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
   const int sA = a.start[cellA];
   const int nA = a.start[cellA + 1] - sA;
 
-  // image table and segments (wave 0; lane l < 54 = half l & 1 of image l >> 1). Pieces
-  // are ordered by (group, dz, dy, z half, dx): the pieces of one (dy, dz) row, one z half
-  // and one group form a segment, sorted in x because each half of a cell is and the
-  // cells follow each other in x.
+  // image table and segments (wave 0; lane l < 2 kImg = half l & 1 of image l >> 1).
+  // Pieces are ordered by (group, dz, dy, z half, dx): the pieces of one (dy, dz) row, one
+  // z half and one group form a segment, sorted in x because each half of a cell is and
+  // the cells follow each other in x. The half shell puts the home image's two halves
+  // first, as segments of their own: its neighbour-list positions 0 .. nA-1 are then the
+  // home atoms in their sorted order, which the j > i rule compares.
   if (tid < 64) {
     const int m = lane >> 1, h = lane & 1;
-    const bool act = lane < 54;
+    const bool act = lane < 2 * kImg;
     const int nd[3] = {a.nx, a.ny, a.nz};
     const int ac[3] = {ac0, ac1, ac2};
     int grp = 0, jsh = 0, st0 = 0, cnt = 0, n0 = 0, key = 1 << 20, ox = 0;
+    int io[3] = {0, 0, 0};   // the image's cell offset
     if (act) {
+      for (int d = 0; d < 3; ++d) io[d] = kHalf ? c_himg[m][d] : c_img[m][d];
       int b[3];
       for (int d = 0; d < 3; ++d) {
-        b[d] = ac[d] + c_img[m][d];
+        b[d] = ac[d] + io[d];
         if (b[d] >= nd[d]) {
           b[d] -= nd[d];
           grp |= 1 << d;
@@ -249,13 +304,14 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
       st0 = a.start[cb];
       cnt = a.start[cb + 1] - st0;
       n0 = a.zsplit[cb];
-      key = (grp * 9 + (c_img[m][1] + 1) + 3 * (c_img[m][2] + 1)) * 2 + h;
-      ox = c_img[m][0];
+      key = (grp * 9 + (io[1] + 1) + 3 * (io[2] + 1)) * 2 + h;
+      if (kHalf) key = m == 0 ? h : key + 2;
+      ox = io[0];
     }
     const int pc = act ? (h ? cnt - n0 : n0) : 0;   // atoms of this piece
     int off = 0, seg_len = 0, tot = 0;
     bool head = act;
-    for (int l2 = 0; l2 < 54; ++l2) {
+    for (int l2 = 0; l2 < 2 * kImg; ++l2) {
       const int km = __builtin_amdgcn_readlane(key, l2);
       const int cm = __builtin_amdgcn_readlane(pc, l2);
       const int xm = __builtin_amdgcn_readlane(ox, l2);
@@ -268,7 +324,7 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
     // a head (the first piece of its segment) is numbered by the heads with smaller keys
     const unsigned long long heads = __builtin_amdgcn_ballot_w64(head);
     int seg_idx = 0;
-    for (int l2 = 0; l2 < 54; ++l2) {
+    for (int l2 = 0; l2 < 2 * kImg; ++l2) {
       const int km = __builtin_amdgcn_readlane(key, l2);
       seg_idx += (((heads >> l2) & 1ull) && km < key) ? 1 : 0;
     }
@@ -287,10 +343,10 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
         sg_.begin = off;
         sg_.end = off + seg_len;
         sg_.grp = grp;
-        sg_.y0 = (float)(ac1 + c_img[m][1]) * wy;
-        sg_.y1 = (float)(ac1 + c_img[m][1] + 1) * wy;
-        sg_.z0 = ((float)(ac2 + c_img[m][2]) + 0.5f * (float)h) * wz;
-        sg_.z1 = ((float)(ac2 + c_img[m][2]) + 0.5f * (float)(h + 1)) * wz;
+        sg_.y0 = (float)(ac1 + io[1]) * wy;
+        sg_.y1 = (float)(ac1 + io[1] + 1) * wy;
+        sg_.z0 = ((float)(ac2 + io[2]) + 0.5f * (float)h) * wz;
+        sg_.z1 = ((float)(ac2 + io[2]) + 0.5f * (float)(h + 1)) * wz;
       }
     }
     int ml = head ? seg_len : 0;
@@ -321,8 +377,8 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
     const int P1 = min(total, P0 + cap);
     // stage the neighbour-list slice [P0, P1): wave w copies images w and w + 16 (both z
     // halves, to their two segments), issuing all loads of up to 4 x 64 atoms before the
-    // LDS stores
-    for (int m = w; m < 27; m += kNW) {
+    // LDS stores; the half shell also clears the slots' accumulators
+    for (int m = w; m < kImg; m += kNW) {
       const Img im = H.img[m];
       // o_g = o - h: the origin in this image's frame
       const float og0 = O0 - ((im.grp & 1) ? L0 : 0.f);
@@ -350,6 +406,12 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
             sF[dst - P0] = make_float4(x, y, z, fmaf(rz, rz, fmaf(ry, ry, rx * rx)));
             sQ[dst - P0] = v[r].w;
             sT[dst - P0] = (uint8_t)tv[r];
+            if (kHalf) {
+              sJ[3 * (dst - P0)] = 0;
+              sJ[3 * (dst - P0) + 1] = 0;
+              sJ[3 * (dst - P0) + 2] = 0;
+              if (kDiag) sJn[dst - P0] = 0;
+            }
           }
         }
       }
@@ -418,6 +480,7 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
         cnt[k] = 0;
       }
       float e_lane = 0.f;
+      float jmax = 0.f;   // largest |F_j| component handed to to_fixed24 (half shell)
 
       // x-window of every segment: lane s finds [lo, hi) of segment s with x in
       // [min x_i - w, max x_i + w) in the segment's frame (two lower_bound searches), where
@@ -466,11 +529,12 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
       // dense force passes over the first c entries of FIFO k (c <= 64 * kDrain): the exact
       // distance in the current frame, the strict cutoff (u > 0 drops the home atom
       // itself) and the force. All LDS reads of the kDrain batches precede the arithmetic.
-      // the force on home atom k from one lane's FIFO entry: the exact distance in the
+      // the force on home atom k from one lane's FIFO entry j: the exact distance in the
       // current frame, the strict cutoff (u > 0 drops the home atom itself) and the force;
-      // `in` is false for lanes past the FIFO's fill level
-      auto pair_lane = [&](int k, const float4& pj, float qj, const float2& lj, bool in)
-          __attribute__((always_inline)) {
+      // `in` is false for lanes past the FIFO's fill level. The half shell adds -F to
+      // neighbour j's accumulator as well (zero for lanes that add nothing).
+      auto pair_lane = [&](int k, int jl, const float4& pj, float qj, const float2& lj,
+                           bool in) __attribute__((always_inline)) {
         const float dx = xs[k] - pj.x, dy = ys[k] - pj.y, dz = zs[k] - pj.z;
         float u = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
         float e, f;
@@ -478,17 +542,27 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
           u = (in && u > 0.f) ? u : kBigU;
           f = pair_f<kSwitchCoulomb>(u, lj.x, lj.y, kq[k] * qj, rs2, inv_sw, sw12, e);
           if (diag) cnt[k] += __builtin_popcountll(__builtin_amdgcn_ballot_w64(u < rc2));
+          if (kHalf && diag && u < rc2) atomicAdd(&sJn[jl], 1);
         } else {
           const bool lv = in && u < rc2 && u > 0.f;
           f = pair_f<kSwitchCoulomb>(u, lj.x, lj.y, kq[k] * qj, rs2, inv_sw, sw12, e);
           f = lv ? f : 0.f;
           e = lv ? e : 0.f;
           if (diag) cnt[k] += __builtin_popcountll(__builtin_amdgcn_ballot_w64(lv));
+          if (kHalf && diag && lv) atomicAdd(&sJn[jl], 1);
         }
         fx[k] = fmaf(f, dx, fx[k]);
         fy[k] = fmaf(f, dy, fy[k]);
         fz[k] = fmaf(f, dz, fz[k]);
         e_lane += e;
+        if (kHalf) {
+          const float px = f * dx, py = f * dy, pz = f * dz;
+          jmax = fmaxf(jmax, fmaxf(fabsf(px), fmaxf(fabsf(py), fabsf(pz))));
+          long long* d = sJ + 3 * jl;
+          lds_add(d, to_fixed24(px, -1.f));
+          lds_add(d + 1, to_fixed24(py, -1.f));
+          lds_add(d + 2, to_fixed24(pz, -1.f));
+        }
       };
       // dense force passes over the first 64 kDrain entries of FIFO k, every lane busy; all
       // LDS reads of the kDrain batches precede the arithmetic. The remainder (fewer than
@@ -510,7 +584,7 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
 #pragma unroll
         for (int b = 0; b < kDrain; ++b) lj[b] = sLJ[row[k] + tj[b]];
 #pragma unroll
-        for (int b = 0; b < kDrain; ++b) pair_lane(k, pj[b], qj[b], lj[b], true);
+        for (int b = 0; b < kDrain; ++b) pair_lane(k, jj[b], pj[b], qj[b], lj[b], true);
         const int c = 64 * kDrain;
         const int rem = fill(k) - c;
         if (rem > 0) {
@@ -532,7 +606,7 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
             const float4 pj = sF[jj];
             const float qj = sQ[jj];
             const float2 lj = sLJ[row[k] + sT[jj]];
-            pair_lane(k, pj, qj, lj, off + lane < n);
+            pair_lane(k, jj, pj, qj, lj, off + lane < n);
           }
           fb[k] = fk0 + 2u * (uint32_t)(k * kFifo);
         }
@@ -540,8 +614,13 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
 
       int cur_g = -1;
       for (int s = 0; s < n_seg; ++s) {
-        const int lo = __builtin_amdgcn_readlane(wlo, s);
+        int lo = __builtin_amdgcn_readlane(wlo, s);
         const int hi = __builtin_amdgcn_readlane(whi, s);
+        // half shell, home image (segments 0 and 1, positions = home atom indices): only
+        // j > i, so the window starts past the group's first atom, and the first batch
+        // drops, for each home atom, the lanes at or before it
+        const bool home_seg = kHalf && s < 2;
+        if (home_seg) lo = max(lo, ib + 1 - P0);
         if (lo >= hi) continue;
         const int g = __builtin_amdgcn_readlane(sg, s);
         if (g != cur_g) {
@@ -581,6 +660,14 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
 #pragma unroll
             for (int k = 0; k < kQ; ++k) m[k] &= vm;
           }
+          if (home_seg && jb + P0 < ib + kQ) {
+#pragma unroll
+            for (int k = 1; k < kQ; ++k) {
+              // lanes 0 .. c-1 hold j <= i = ib + k; c <= k since jb + P0 > ib
+              const int c = ib + k + 1 - (jb + P0);
+              if (c > 0) m[k] &= ~((1ull << c) - 1ull);
+            }
+          }
           // passing lanes append at their prefix rank
           uint32_t adr[kQ];
 #pragma unroll
@@ -610,7 +697,8 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
       // per home atom and component: the 64 lane partials summed in one fixed order (a
       // butterfly within each 16-lane row, then rows 0+1 and 2+3, then the two halves), the
       // twelve sums side by side; every lane ends with the same total, which lane 0 adds
-      // to the atom's 64-bit fixed-point sum (exact conversion) or float32 sum
+      // to the atom's 64-bit fixed-point sum (exact conversion; with an integer atomic in
+      // the half shell, where other workgroups add to the same atom) or float32 sum
       float r[3 * kQ];
 #pragma unroll
       for (int k = 0; k < kQ; ++k) {
@@ -639,13 +727,19 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
             const long long qv = to_fixed(r[3 * k + c], st);
             if (lane == 0) {
               long long* dst = &a.acc64[(int64_t)c * a.n + s];
-              *dst = P0 == 0 ? qv : *dst + qv;
+              if (kHalf)
+                global_add(dst, qv);
+              else
+                *dst = P0 == 0 ? qv : *dst + qv;
             }
           }
         }
         if (diag && lane == 0) {
           int* dst = &a.paircount[a.n + s];
-          *dst = P0 == 0 ? (int)cnt[k] : *dst + (int)cnt[k];
+          if (kHalf)
+            atomicAdd(dst, (int)cnt[k]);
+          else
+            *dst = P0 == 0 ? (int)cnt[k] : *dst + (int)cnt[k];
         }
         pass_count += cnt[k];
       }
@@ -656,11 +750,33 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
         if (!(fabsf(v) < 4.6116860184273879e18f)) st |= MD_STATUS_FIXED_OVERFLOW;
         else e_fix += __float2ll_rn(v);
       }
+      if (kHalf && !(jmax < 134217728.f)) st |= MD_STATUS_FIXED_OVERFLOW;   // 2^27
     }
     __syncthreads();
+    if (kHalf) {
+      // neighbour-side sums of this slice to the per-atom sums (wave w: images w, w + 16)
+      for (int m = w; m < kImg; m += kNW) {
+        const Img im = H.img[m];
+        for (int e = lane; e < im.count; e += 64) {
+          const int dst = e < im.n0 ? im.off[0] + e : im.off[1] + (e - im.n0);
+          if (dst < P0 || dst >= P1) continue;
+          const int64_t src = im.start + e;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const long long v = sJ[3 * (dst - P0) + c];
+            if (v != 0) global_add(&a.acc64[(int64_t)c * a.n + src], v);
+          }
+          if (kDiag) {
+            const int v = sJn[dst - P0];
+            if (v != 0) atomicAdd(&a.paircount[a.n + src], v);
+          }
+        }
+      }
+      __syncthreads();
+    }
   }
 
-  // workgroup energy: each pair was seen from both atoms
+  // workgroup energy (the full shell saw each pair from both atoms)
   long long* sE = reinterpret_cast<long long*>(s_dyn + LL.f4);
   sE[tid] = e_fix;
   for (int e = kThreads + tid; e < 1024; e += kThreads) sE[e] = 0;   // pad the tree to 1024
@@ -669,13 +785,18 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
     if (tid < off) sE[tid] += sE[tid + off];
     __syncthreads();
   }
-  if (tid == 0) a.epart[cellA] = 0.5 * ((double)sE[0] * 5.9604644775390625e-08);   // 2^-24
+  if (tid == 0)
+    a.epart[cellA] = (kHalf ? 1.0 : 0.5) * ((double)sE[0] * 5.9604644775390625e-08);   // 2^-24
   if (st) atomicOr(&a.hdr->status, st);
   if (diag && lane == 0) {
     // candidates of Algorithm 1: every (home atom, other neighbour-list atom), counted
-    // from both atoms; the neighbour slots this kernel actually filtered come separately
+    // from both atoms in the full shell (halved after the kernel) and once in the half
+    // shell; the neighbour slots this kernel actually filtered come separately
     if (w == 0) {
-      const unsigned long long cand = (unsigned long long)nA * (unsigned long long)(total - 1);
+      const unsigned long long nA_ = (unsigned long long)nA;
+      const unsigned long long cand =
+          kHalf ? nA_ * (nA_ - 1) / 2 + nA_ * (unsigned long long)(total - nA)
+                : nA_ * (unsigned long long)(total - 1);
       atomicAdd(&a.hdr->diag[0], cand);
     }
     atomicAdd(&a.hdr->diag[1], filt_count);
@@ -685,60 +806,77 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
   }
 }
 
-template <bool kSwitchCoulomb, bool kClamp, bool kDiag>
+template <bool kHalf, bool kSwitchCoulomb, bool kClamp, bool kDiag>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNW / 4, kNW / 4)))
 void k_pair_fs(SysArgs<float> a, int cap) {
   // home cells in decreasing order of atom count, spread over the XCDs in turn
-  pair_fs<kSwitchCoulomb, kClamp, kDiag>(a, cap, a.order[blockIdx.x]);
+  pair_fs<kHalf, kSwitchCoulomb, kClamp, kDiag>(a, cap, a.order[blockIdx.x]);
 }
 
 // One launch for a batch: block b is cell order[b - cum[s]] of system s.
-template <bool kSwitchCoulomb, bool kClamp, bool kDiag>
+template <bool kHalf, bool kSwitchCoulomb, bool kClamp, bool kDiag>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNW / 4, kNW / 4)))
 void k_pair_fs_batch(Batch<float> b, int cap) {
   int64_t unit;
   const int s = b.pick(blockIdx.x, unit);
-  pair_fs<kSwitchCoulomb, kClamp, kDiag>(b.sys[s], cap, b.sys[s].order[unit]);
+  pair_fs<kHalf, kSwitchCoulomb, kClamp, kDiag>(b.sys[s], cap, b.sys[s].order[unit]);
 }
 
-// Neighbour atoms staged in LDS per pass for n_types types (a multiple of 64).
-int fs_cap(int n_types) {
-  int cap = (kLdsBytes - lds_layout(0, n_types).total) / 21;
+template <bool H, bool S, bool C, bool D>
+struct launch_tag {
+  static constexpr bool half = H, sw = S, clamp = C, diag = D;
+};
+
+// Neighbour atoms staged in LDS per pass (a multiple of 64).
+int fs_cap(int n_types, bool half, bool diag) {
+  int cap = (kLdsBytes - lds_layout(0, n_types, half, diag).total) / slot_bytes(half, diag);
   cap -= cap % 64;
-  while (cap > 0 && lds_layout(cap, n_types).total > kLdsBytes) cap -= 64;
+  while (cap > 0 && lds_layout(cap, n_types, half, diag).total > kLdsBytes) cap -= 64;
   return cap;
+}
+
+// The kernel instance for a system's flags: half or full shell, and how the switch
+// applies (whole energy with the clamp, whole energy, or LJ only).
+template <typename Args, typename Launch>
+hipError_t dispatch(const SysArgs<float>& a, const Args& args, int n_types, int64_t blocks,
+                    hipStream_t stream, Launch launch) {
+  const bool half = a.half_shell != 0;
+  const bool diag = (a.flags & MD_DIAG_COUNTERS) != 0;
+  const bool trunc = (a.flags & MD_COULOMB_TRUNCATED) != 0;
+  const bool clamp = !trunc && a.inv_sw > 0.f;
+  const int cap = fs_cap(n_types, half, diag);
+  const size_t shmem = (size_t)lds_layout(cap, n_types, half, diag).total;
+  const dim3 grid((unsigned)blocks), block(kThreads);
+  auto go = [&](auto h, auto d) {
+    constexpr bool H = decltype(h)::value, D = decltype(d)::value;
+    if (clamp)
+      launch(launch_tag<H, true, true, D>(), grid, block, shmem, stream, args, cap);
+    else if (!trunc)
+      launch(launch_tag<H, true, false, D>(), grid, block, shmem, stream, args, cap);
+    else
+      launch(launch_tag<H, false, false, D>(), grid, block, shmem, stream, args, cap);
+  };
+  using T = std::true_type;
+  using F = std::false_type;
+  if (half) {
+    if (diag) go(T(), T()); else go(T(), F());
+  } else {
+    if (diag) go(F(), T()); else go(F(), F());
+  }
+  return hipGetLastError();
 }
 
 }  // namespace
 
-size_t pair_fs_lds_bytes(int n_types) {
-  return (size_t)lds_layout(fs_cap(n_types), n_types).total;
-}
-
 hipError_t launch_pair_fs(const SysArgs<float>& a, hipStream_t stream) {
   if (a.n == 0) return hipSuccess;
-  const int64_t blocks = a.n_cells;
-  const int cap = fs_cap(a.n_types);
-  const size_t shmem = pair_fs_lds_bytes(a.n_types);
-  const bool trunc = (a.flags & MD_COULOMB_TRUNCATED) != 0;
-  const bool clamp = !trunc && a.inv_sw > 0.f;
-  const dim3 grid((unsigned)blocks), block(kThreads);
-  if (a.flags & MD_DIAG_COUNTERS) {
-    if (clamp)
-      hipLaunchKernelGGL((k_pair_fs<true, true, true>), grid, block, shmem, stream, a, cap);
-    else if (!trunc)
-      hipLaunchKernelGGL((k_pair_fs<true, false, true>), grid, block, shmem, stream, a, cap);
-    else
-      hipLaunchKernelGGL((k_pair_fs<false, false, true>), grid, block, shmem, stream, a, cap);
-  } else {
-    if (clamp)
-      hipLaunchKernelGGL((k_pair_fs<true, true, false>), grid, block, shmem, stream, a, cap);
-    else if (!trunc)
-      hipLaunchKernelGGL((k_pair_fs<true, false, false>), grid, block, shmem, stream, a, cap);
-    else
-      hipLaunchKernelGGL((k_pair_fs<false, false, false>), grid, block, shmem, stream, a, cap);
-  }
-  return hipGetLastError();
+  return dispatch(a, a, a.n_types, a.n_cells, stream,
+                  [](auto tag, dim3 g, dim3 b, size_t sh, hipStream_t st, const SysArgs<float>& x,
+                     int cap) {
+                    using Tg = decltype(tag);
+                    hipLaunchKernelGGL((k_pair_fs<Tg::half, Tg::sw, Tg::clamp, Tg::diag>), g, b,
+                                       sh, st, x, cap);
+                  });
 }
 
 hipError_t launch_pair_fs_batch(const Batch<float>& b0, hipStream_t stream) {
@@ -749,29 +887,13 @@ hipError_t launch_pair_fs_batch(const Batch<float>& b0, hipStream_t stream) {
     b.cum[s + 1] = b.cum[s] + b.sys[s].n_cells;
     nt = b.sys[s].n_types > nt ? b.sys[s].n_types : nt;
   }
-  const int64_t blocks = b.cum[b.n];
-  const int cap = fs_cap(nt);
-  const size_t shmem = pair_fs_lds_bytes(nt);
-  const SysArgs<float>& a = b.sys[0];
-  const bool trunc = (a.flags & MD_COULOMB_TRUNCATED) != 0;
-  const bool clamp = !trunc && a.inv_sw > 0.f;
-  const dim3 grid((unsigned)blocks), block(kThreads);
-  if (a.flags & MD_DIAG_COUNTERS) {
-    if (clamp)
-      hipLaunchKernelGGL((k_pair_fs_batch<true, true, true>), grid, block, shmem, stream, b, cap);
-    else if (!trunc)
-      hipLaunchKernelGGL((k_pair_fs_batch<true, false, true>), grid, block, shmem, stream, b, cap);
-    else
-      hipLaunchKernelGGL((k_pair_fs_batch<false, false, true>), grid, block, shmem, stream, b, cap);
-  } else {
-    if (clamp)
-      hipLaunchKernelGGL((k_pair_fs_batch<true, true, false>), grid, block, shmem, stream, b, cap);
-    else if (!trunc)
-      hipLaunchKernelGGL((k_pair_fs_batch<true, false, false>), grid, block, shmem, stream, b, cap);
-    else
-      hipLaunchKernelGGL((k_pair_fs_batch<false, false, false>), grid, block, shmem, stream, b, cap);
-  }
-  return hipGetLastError();
+  return dispatch(b.sys[0], b, nt, b.cum[b.n], stream,
+                  [](auto tag, dim3 g, dim3 bl, size_t sh, hipStream_t st, const Batch<float>& x,
+                     int cap) {
+                    using Tg = decltype(tag);
+                    hipLaunchKernelGGL((k_pair_fs_batch<Tg::half, Tg::sw, Tg::clamp, Tg::diag>),
+                                       g, bl, sh, st, x, cap);
+                  });
 }
 
 }  // namespace md

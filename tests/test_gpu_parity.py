@@ -78,7 +78,7 @@ def sum_candidates(params, pos):
     return total
 
 
-@pytest.mark.parametrize("flags", [0, api.PAIR_PREDICATED])
+@pytest.mark.parametrize("flags", [0, api.PAIR_FULL_SHELL, api.PAIR_PREDICATED])
 def test_fp32_small_config(gpu, flags):
     _say("case: 3,000-atom system, float32 path, flags", flags)
     s = W.small_system()
@@ -88,11 +88,12 @@ def test_fp32_small_config(gpu, flags):
     assert api.read_status(ws) == 0
 
 
-def test_fp32_apoa1_full(gpu):
-    _say("case: 92,224-atom system, float32 path, all atoms")
+@pytest.mark.parametrize("flags", [0, api.PAIR_FULL_SHELL])
+def test_fp32_apoa1_full(gpu, flags):
+    _say("case: 92,224-atom system, float32 path, all atoms, flags", flags)
     s = W.apoa1_system()
     p = s.params()
-    f, e, ws, cnt = run(p, s.pos, s.types, s.charges, gpu, flags=api.DIAG_COUNTERS)
+    f, e, ws, cnt = run(p, s.pos, s.types, s.charges, gpu, flags=flags | api.DIAG_COUNTERS)
     r, err = _check_fp32(p, s.pos, s.types, s.charges, f, e, cnt)
     diag = api.read_diag(ws)
     band, nb = oracle.band_atoms(p, s.pos, BAND)
@@ -139,12 +140,13 @@ def test_binning_matches_oracle(gpu):
         assert np.min(np.abs(frac - np.round(frac)) * w) < 1e-4, (i, pos64[i])
 
 
-def test_fixed64_bitwise_reproducible(gpu):
-    _say("case: 92,224 atoms, 10 runs, fixed-point accumulation")
+@pytest.mark.parametrize("flags", [0, api.PAIR_FULL_SHELL])
+def test_fixed64_bitwise_reproducible(gpu, flags):
+    _say("case: 92,224 atoms, 10 runs, fixed-point accumulation, flags", flags)
     import torch
     from _gpu import to_dev
     s = W.apoa1_system()
-    p = api.Params.from_dict(s.params())
+    p = api.Params.from_dict(s.params(), flags)
     d = to_dev((s.pos, s.types, s.charges), gpu)
     ws = api.alloc_workspace(p, s.n, gpu)
     f0, e0 = api.forces(p, *d, workspace=ws)
@@ -225,9 +227,11 @@ def test_clustered_cell_beyond_one_tile(gpu):
         assert err["max_norm"] <= 1e-12, (flags, err)
         assert e == pytest.approx(r.energy, rel=1e-12)
         assert np.array_equal(cnt, r.count)
-        f32, e32, _, _ = run(p, pos, t, q, gpu, flags=flags)
-        err32 = force_errors(f32, r.force, r.abs_sum)
-        assert err32["max_norm"] <= 1e-5 and err32["rms"] <= 1e-5, (flags, err32)
+        for f32_flags in ((flags,) if flags else (0, api.PAIR_FULL_SHELL)):
+            f32, e32, _, _ = run(p, pos, t, q, gpu, flags=f32_flags)
+            err32 = force_errors(f32, r.force, r.abs_sum)
+            assert err32["max_norm"] <= 1e-5 and err32["rms"] <= 1e-5, (f32_flags, err32)
+            assert e32 == pytest.approx(r.energy, rel=1e-6), f32_flags
 
 
 def _lattice_blob(rng, origin, n_side, spacing, jitter):
@@ -236,10 +240,12 @@ def _lattice_blob(rng, origin, n_side, spacing, jitter):
     return origin + pts + rng.uniform(-jitter, jitter, pts.shape)
 
 
-def test_fullshell_multi_pass(gpu):
-    """8,000 atoms in a 3x3x3 grid: every home cell sees all of them, more than one LDS
-    load of neighbours, so the float32 kernel stages and filters in several passes."""
-    _say("case: 8,000 atoms, 37 A box, neighbour list beyond LDS")
+@pytest.mark.parametrize("flags", [0, api.PAIR_FULL_SHELL])
+def test_compact_multi_pass(gpu, flags):
+    """8,000 atoms in a 3x3x3 grid: every home cell sees all of them (27 images, or 14
+    in the half shell), more than one LDS load of neighbours, so the float32 kernel
+    stages, filters and (half shell) hands back neighbour sums in several passes."""
+    _say("case: 8,000 atoms, 37 A box, neighbour list beyond LDS, flags", flags)
     rng = np.random.default_rng(11)
     L = 37.0
     pos = np.mod(_lattice_blob(rng, np.zeros(3), 20, 1.85, 0.3), L)
@@ -249,7 +255,7 @@ def test_fullshell_multi_pass(gpu):
     q = rng.normal(0, 0.3, n)
     p = dict(box=(L, L, L), r_cut=12.0, r_switch=10.0, coulomb_k=W.COULOMB_K,
              sigma=np.array([1.0, 1.2]), epsilon=np.array([0.05, 0.1]), flags=0)
-    f, e, ws, cnt = run(p, pos, t, q, gpu, flags=api.DIAG_COUNTERS)
+    f, e, ws, cnt = run(p, pos, t, q, gpu, flags=flags | api.DIAG_COUNTERS)
     _check_fp32(p, pos, t, q, f, e, cnt)
 
 
@@ -355,8 +361,9 @@ def test_stmv_sampled(gpu):
 
 def test_batched_matches_alone(gpu):
     """Serving form: systems of different sizes in one batched call give bitwise the
-    results of evaluating each alone. 13 systems exceed one launch batch, and one
-    predicated system is evaluated on its own inside the call."""
+    results of evaluating each alone. 13 systems exceed one launch batch, one predicated
+    system is evaluated on its own inside the call, and two full-shell systems split
+    the batches by kind."""
     _say("case: 13 serving requests, batched vs alone")
     import torch
     from _gpu import to_dev
@@ -365,7 +372,7 @@ def test_batched_matches_alone(gpu):
     systems, alone = [], []
     for k, r in enumerate(picks):
         s = W.request_system(reqs[r], table)
-        flags = api.PAIR_PREDICATED if k == 6 else 0
+        flags = api.PAIR_PREDICATED if k == 6 else api.PAIR_FULL_SHELL if k in (3, 4) else 0
         p = api.Params.from_dict(s.params(), flags)
         d = to_dev((s.pos, s.types, s.charges), gpu)
         f, e = api.forces(p, *d)
@@ -401,9 +408,11 @@ def test_precision_form_report(gpu):
     r = _ref(s.params(), s.pos, s.types, s.charges)
     d = to_dev((s.pos, s.types, s.charges), gpu)
     report = {}
-    # float32 sums: the compacted kernel owns each atom in one wave, so its float32 sums
-    # run in a fixed order too; the half-shell kernel adds them with float32 atomics
-    for name, flags in (("fixed64", 0), ("f32_sums_full_shell", api.ACCUM_F32_ATOMIC),
+    # float32 sums: the compacted full-shell kernel owns each atom in one wave, so its
+    # float32 sums run in a fixed order too; the predicated half-shell kernel adds them
+    # with float32 atomics
+    for name, flags in (("fixed64", 0), ("fixed64_full_shell", api.PAIR_FULL_SHELL),
+                        ("f32_sums_full_shell", api.ACCUM_F32_ATOMIC),
                         ("f32_atomic_half_shell", api.ACCUM_F32_ATOMIC | api.PAIR_PREDICATED)):
         p = api.Params.from_dict(s.params(), flags)
         ws = api.alloc_workspace(p, s.n, gpu)
@@ -421,17 +430,19 @@ def test_precision_form_report(gpu):
         report[name] = err
     _say("PRECISION_REPORT " + json.dumps(report))
     assert report["fixed64"]["bitwise_identical_runs_of_10"] == 10
+    assert report["fixed64_full_shell"]["bitwise_identical_runs_of_10"] == 10
     for name in report:
         assert report[name]["max_norm"] <= 1e-5 and report[name]["rms"] <= 1e-5, report
         assert report[name]["energy_rel"] <= 1e-6, report
 
 
+@pytest.mark.parametrize("shell", [0, api.PAIR_FULL_SHELL])
 @pytest.mark.parametrize("case", ["truncated_coulomb", "no_switch", "sixty_four_types"])
-def test_fp32_kernel_variants(gpu, case):
+def test_fp32_kernel_variants(gpu, case, shell):
     """The float32 compacted kernel's other instantiations against the oracle: Coulomb
     truncated (only LJ switched), switching off (r_switch = r_cut: lanes are masked, not
     clamped), and 64 atom types (the largest LJ table, the smallest LDS neighbour load)."""
-    _say("case: float32 kernel variant", case)
+    _say("case: float32 kernel variant", case, "flags", shell)
     if case == "sixty_four_types":
         s = W.gen_system(20000, (60.0, 60.0, 55.0), 13, n_types=64)
         p = s.params()
@@ -442,7 +453,8 @@ def test_fp32_kernel_variants(gpu, case):
             p = dict(p, flags=api.COULOMB_TRUNCATED)
         else:
             p = dict(p, r_switch=p["r_cut"])
-    f, e, ws, cnt = run(p, s.pos, s.types, s.charges, gpu, flags=p.get("flags", 0) | api.DIAG_COUNTERS)
+    f, e, ws, cnt = run(p, s.pos, s.types, s.charges, gpu,
+                        flags=p.get("flags", 0) | shell | api.DIAG_COUNTERS)
     if case == "sixty_four_types":
         _check_fp32(p, s.pos, s.types, s.charges, f, e, cnt)
         return
