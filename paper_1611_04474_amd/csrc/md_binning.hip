@@ -244,11 +244,13 @@ __device__ inline void bin_scan(const SysArgs<Real>& a, const TypeTable& tt, int
     a.lj[2 * e + 0] = (Real)(4.0 * ep * s6 * s6);
     a.lj[2 * e + 1] = (Real)(4.0 * ep * s6);
   }
-  if (own_header && t == 0) {
-    uint32_t st = 0;
-    for (int b = 0; b < B; ++b) st |= a.bstat[b];
-    a.hdr->status = st;
-    for (int k = 0; k < 5; ++k) a.hdr->diag[k] = 0;
+  static_assert(kBinMaxBlocks <= 64, "one block's status per lane of wave 0");
+  if (own_header && t < 64) {
+    // the blocks' status bits, one block per lane of wave 0
+    uint32_t st = t < B ? a.bstat[t] : 0u;
+    for (int o = 32; o > 0; o >>= 1) st |= __shfl_xor(st, o);
+    if (t == 0) a.hdr->status = st;
+    if (t < 5) a.hdr->diag[t] = 0;
   }
 }
 

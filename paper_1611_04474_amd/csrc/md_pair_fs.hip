@@ -31,11 +31,11 @@
 //              wave that owns it, so no atomics are needed;
 //   half (kHalf = true)  -- every pair is evaluated once (Newton's third law, F_j = -F_i):
 //              the home cell with j > i and the 13 images ahead of it. The force on the
-//              neighbour atom, rounded to 2^-24, is added in 64-bit fixed point into an
-//              LDS accumulator per staged atom (integer atomics, so the sum does not
-//              depend on the order of the adds), and the accumulators go to the per-atom
-//              sums with 64-bit global integer atomics when the workgroup is done. Integer
-//              addition is associative: the result is the same bits on every run.
+//              neighbour atom, rounded to a multiple of 2^-24, is added in 64-bit fixed
+//              point into an LDS accumulator per staged atom (integer atomics, so the sum
+//              does not depend on the order of the adds), and the accumulators go to the
+//              per-atom sums with 64-bit global integer atomics when the workgroup is
+//              done. Integer addition is associative: the same bits on every run.
 #include <type_traits>
 
 #include "md_common.hpp"
@@ -149,15 +149,12 @@ __device__ inline long long to_fixed(float v, uint32_t& st) {
   return v < 0.f ? -(long long)m : (long long)m;
 }
 
-// s * v in 64-bit fixed point of unit 2^-32, with v rounded (to nearest even) to a
-// multiple of 2^-24 on the way, for s = +-1 and |v| < 2^27. The fma places round(s v 2^24)
-// in the low mantissa bits of 1.5 * 2^52, whose bit pattern then differs from that of
+// round(x) (to nearest even) as a 64-bit integer, for |x| < 2^51: the add places it in
+// the low mantissa bits of 1.5 * 2^52, whose bit pattern then differs from that of
 // 1.5 * 2^52 by exactly that integer.
-__device__ inline long long to_fixed24(float v, float s) {
-  const double t = __builtin_fma((double)v, (double)s * 16777216.0, 6755399441055744.0);
-  return (long long)((unsigned long long)(__builtin_bit_cast(long long, t) -
-                                          0x4338000000000000ll)
-                     << 8);
+__device__ inline long long round_to_i64(float x) {
+  const double t = (double)x + 6755399441055744.0;
+  return __builtin_bit_cast(long long, t) - 0x4338000000000000ll;
 }
 
 __device__ inline void lds_add(long long* p, long long v) {
@@ -480,7 +477,7 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
         cnt[k] = 0;
       }
       float e_lane = 0.f;
-      float jmax = 0.f;   // largest |F_j| component handed to to_fixed24 (half shell)
+      float jmax = 0.f;   // largest |F_j| component, in units of 2^-24, handed to round_to_i64
 
       // x-window of every segment: lane s finds [lo, hi) of segment s with x in
       // [min x_i - w, max x_i + w) in the segment's frame (two lower_bound searches), where
@@ -532,7 +529,9 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
       // the force on home atom k from one lane's FIFO entry j: the exact distance in the
       // current frame, the strict cutoff (u > 0 drops the home atom itself) and the force;
       // `in` is false for lanes past the FIFO's fill level. The half shell adds -F to
-      // neighbour j's accumulator as well (zero for lanes that add nothing).
+      // neighbour j's accumulator as well (zero for lanes that add nothing), in units of
+      // 2^-24 kcal/mol/A: -f 2^24 dx is an exact scaling of the float32 product, rounded
+      // once to an integer.
       auto pair_lane = [&](int k, int jl, const float4& pj, float qj, const float2& lj,
                            bool in) __attribute__((always_inline)) {
         const float dx = xs[k] - pj.x, dy = ys[k] - pj.y, dz = zs[k] - pj.z;
@@ -556,12 +555,13 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
         fz[k] = fmaf(f, dz, fz[k]);
         e_lane += e;
         if (kHalf) {
-          const float px = f * dx, py = f * dy, pz = f * dz;
+          const float g24 = f * -16777216.f;
+          const float px = g24 * dx, py = g24 * dy, pz = g24 * dz;
           jmax = fmaxf(jmax, fmaxf(fabsf(px), fmaxf(fabsf(py), fabsf(pz))));
           long long* d = sJ + 3 * jl;
-          lds_add(d, to_fixed24(px, -1.f));
-          lds_add(d + 1, to_fixed24(py, -1.f));
-          lds_add(d + 2, to_fixed24(pz, -1.f));
+          lds_add(d, round_to_i64(px));
+          lds_add(d + 1, round_to_i64(py));
+          lds_add(d + 2, round_to_i64(pz));
         }
       };
       // dense force passes over the first 64 kDrain entries of FIFO k, every lane busy; all
@@ -750,7 +750,7 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
         if (!(fabsf(v) < 4.6116860184273879e18f)) st |= MD_STATUS_FIXED_OVERFLOW;
         else e_fix += __float2ll_rn(v);
       }
-      if (kHalf && !(jmax < 134217728.f)) st |= MD_STATUS_FIXED_OVERFLOW;   // 2^27
+      if (kHalf && !(jmax < 2251799813685248.f)) st |= MD_STATUS_FIXED_OVERFLOW;   // 2^51
     }
     __syncthreads();
     if (kHalf) {
@@ -763,8 +763,12 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
           const int64_t src = im.start + e;
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
+            // units of 2^-24 to the sums' 2^-32; beyond 2^55 the sum would not fit them
             const long long v = sJ[3 * (dst - P0) + c];
-            if (v != 0) global_add(&a.acc64[(int64_t)c * a.n + src], v);
+            if (v >= (1ll << 55) || v < -(1ll << 55)) st |= MD_STATUS_FIXED_OVERFLOW;
+            else if (v != 0)
+              global_add(&a.acc64[(int64_t)c * a.n + src],
+                         (long long)((unsigned long long)v << 8));
           }
           if (kDiag) {
             const int v = sJn[dst - P0];
