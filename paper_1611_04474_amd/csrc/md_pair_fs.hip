@@ -694,11 +694,14 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
       }
       if (cur_g >= 0) flush();
 
-      // per home atom and component: the 64 lane partials summed in one fixed order (a
-      // butterfly within each 16-lane row, then rows 0+1 and 2+3, then the two halves), the
-      // twelve sums side by side; every lane ends with the same total, which lane 0 adds
-      // to the atom's 64-bit fixed-point sum (exact conversion; with an integer atomic in
-      // the half shell, where other workgroups add to the same atom) or float32 sum
+      // per home atom and component: the 64 lane partials summed in one fixed order. The
+      // two wave halves exchange the sums the other one keeps (lanes l and l ^ 32: home
+      // atoms 0, 1 stay in the lower half, 2, 3 in the upper), then the two rows of each
+      // half (l and l ^ 16), so that the 16 lanes of row g hold home atom g's three
+      // components; a butterfly within the row completes them. Lane 16 g adds atom g's
+      // totals to its 64-bit fixed-point sum (exact conversion; with an integer atomic in
+      // the half shell, where other workgroups add to the same atom) or float32 sum.
+      static_assert(kQ == 4, "one 16-lane row per home atom");
       float r[3 * kQ];
 #pragma unroll
       for (int k = 0; k < kQ; ++k) {
@@ -706,26 +709,33 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
         r[3 * k + 1] = fy[k];
         r[3 * k + 2] = fz[k];
       }
+      float r6[6], r3[3];
+      const bool up32 = lane >= 32, up16 = (lane & 16) != 0;
 #pragma unroll
-      for (int i = 0; i < 3 * kQ; ++i) r[i] = rowsum16(r[i]);
+      for (int i = 0; i < 6; ++i) {
+        const float keep = up32 ? r[i + 6] : r[i];
+        const float give = up32 ? r[i] : r[i + 6];
+        r6[i] = keep + __shfl_xor(give, 32);
+      }
 #pragma unroll
-      for (int i = 0; i < 3 * kQ; ++i) r[i] += __shfl_xor(r[i], 16);
+      for (int i = 0; i < 3; ++i) {
+        const float keep = up16 ? r6[i + 3] : r6[i];
+        const float give = up16 ? r6[i] : r6[i + 3];
+        r3[i] = keep + __shfl_xor(give, 16);
+      }
 #pragma unroll
-      for (int i = 0; i < 3 * kQ; ++i) r[i] += __shfl_xor(r[i], 32);
+      for (int i = 0; i < 3; ++i) r3[i] = rowsum16(r3[i]);
+      {
+        const int kr = lane >> 4;   // this row's home atom
+        if ((lane & 15) == 0 && kr < nv) {
+          const int64_t s = sA + ib + kr;
 #pragma unroll
-      for (int k = 0; k < kQ; ++k) {
-        if (k >= nv) continue;
-        const int64_t s = sA + ib + k;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          if (f32) {
-            if (lane == 0) {
+          for (int c = 0; c < 3; ++c) {
+            if (f32) {
               float* dst = &a.facc[(int64_t)c * a.n + s];
-              *dst = P0 == 0 ? r[3 * k + c] : *dst + r[3 * k + c];
-            }
-          } else {
-            const long long qv = to_fixed(r[3 * k + c], st);
-            if (lane == 0) {
+              *dst = P0 == 0 ? r3[c] : *dst + r3[c];
+            } else {
+              const long long qv = to_fixed(r3[c], st);
               long long* dst = &a.acc64[(int64_t)c * a.n + s];
               if (kHalf)
                 global_add(dst, qv);
@@ -733,16 +743,20 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
                 *dst = P0 == 0 ? qv : *dst + qv;
             }
           }
+          if (diag) {
+            unsigned ck = cnt[0];
+#pragma unroll
+            for (int k = 1; k < kQ; ++k) ck = kr == k ? cnt[k] : ck;
+            int* dst = &a.paircount[a.n + s];
+            if (kHalf)
+              atomicAdd(dst, (int)ck);
+            else
+              *dst = P0 == 0 ? (int)ck : *dst + (int)ck;
+          }
         }
-        if (diag && lane == 0) {
-          int* dst = &a.paircount[a.n + s];
-          if (kHalf)
-            atomicAdd(dst, (int)cnt[k]);
-          else
-            *dst = P0 == 0 ? (int)cnt[k] : *dst + (int)cnt[k];
-        }
-        pass_count += cnt[k];
       }
+#pragma unroll
+      for (int k = 0; k < kQ; ++k) pass_count += k < nv ? cnt[k] : 0u;
       {
         // the group's lane energy in 64-bit fixed point (exact scaling by 2^24, then one
         // rounding), so the workgroup total does not depend on which wave took which group
