@@ -57,6 +57,7 @@ constexpr int kLdsBytes = 160 * 1024;
 constexpr float kMargin = 0.05f;    // A^2 added to rc^2 by the expanded-form prefilter
 constexpr float kWin = 1.0e-3f;     // A added to r_cut for the x-window
 constexpr float kBigU = 1.0e30f;    // squared distance given to lanes that must add nothing
+static_assert(kMaxTypes <= 64, "a type must fit the low 6 bits of a staged c_j");
 
 // The 27 neighbour images.
 __constant__ int8_t c_img[27][3] = {
@@ -99,8 +100,8 @@ struct Hdr {
   int next;         // next group of home atoms to hand out
 };
 
-// LDS layout in bytes: type u8 [cap] | header | FIFOs | LJ (c12, c6) [nt^2] |
-// (x, y, z, |r - o_g|^2) [cap] | q [cap], and for the half shell the neighbour-side
+// LDS layout in bytes: header | FIFOs | LJ (c12, c6) [nt^2] | (x, y, z, |r - o_g|^2 with
+// the type in its low bits) [cap] | q [cap], and for the half shell the neighbour-side
 // accumulators (x, y, z) int64 [cap] and, with counters, partner counts int32 [cap]
 struct Lds {
   int hdr, fifo, lj, f4, q, jacc, jcnt, total;
@@ -109,12 +110,12 @@ struct Lds {
 __host__ __device__ constexpr int align_up(int v, int a) { return (v + a - 1) / a * a; }
 
 __host__ __device__ inline int slot_bytes(bool half, bool diag) {
-  return 21 + (half ? 24 + (diag ? 4 : 0) : 0);
+  return 20 + (half ? 24 + (diag ? 4 : 0) : 0);
 }
 
 __host__ __device__ inline Lds lds_layout(int cap, int n_types, bool half, bool diag) {
   Lds L;
-  L.hdr = align_up(cap, 16);
+  L.hdr = 0;
   L.fifo = align_up(L.hdr + (int)sizeof(Hdr), 16);
   L.lj = align_up(L.fifo + 2 * kNW * kWaveFifo, 16);
   L.f4 = align_up(L.lj + 8 * n_types * n_types, 16);
@@ -239,7 +240,6 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
   extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
   constexpr int kImg = kHalf ? 14 : 27;   // neighbour images
   const Lds LL = lds_layout(cap, a.n_types, kHalf, kDiag);
-  uint8_t* sT = s_dyn;
   Hdr& H = *reinterpret_cast<Hdr*>(s_dyn + LL.hdr);
   uint16_t* sFifo = reinterpret_cast<uint16_t*>(s_dyn + LL.fifo);
   float2* sLJ = reinterpret_cast<float2*>(s_dyn + LL.lj);
@@ -251,6 +251,8 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int nt = a.n_types;
+  // low bits of a staged c_j that carry the atom's type
+  const uint32_t tmask = nt > 1 ? (2u << (31 - __builtin_clz((unsigned)(nt - 1)))) - 1u : 0u;
   constexpr bool diag = kDiag;
   const bool f32 = !kHalf && (a.flags & MD_ACCUM_F32_ATOMIC) != 0;
   const float rc2 = a.rc2, rs2 = a.rs2, inv_sw = a.inv_sw, sw12 = 12.f * a.inv_sw;
@@ -400,9 +402,13 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
             const float y = (im.jsh & 2) ? v[r].y - L1 : v[r].y;
             const float z = (im.jsh & 4) ? v[r].z - L2 : v[r].z;
             const float rx = x - og0, ry = y - og1, rz = z - og2;
-            sF[dst - P0] = make_float4(x, y, z, fmaf(rz, rz, fmaf(ry, ry, rx * rx)));
+            // c_j with its low mantissa bits (as many as the types need, at most 6)
+            // replaced by the type: under 64 ulps of c_j, at most 1.6e-2 A^2 for the
+            // largest cells (18 A), well inside the prefilter's margin
+            const float cj = fmaf(rz, rz, fmaf(ry, ry, rx * rx));
+            const uint32_t w4 = (__float_as_uint(cj) & ~tmask) | (uint32_t)tv[r];
+            sF[dst - P0] = make_float4(x, y, z, __uint_as_float(w4));
             sQ[dst - P0] = v[r].w;
-            sT[dst - P0] = (uint8_t)tv[r];
             if (kHalf) {
               sJ[3 * (dst - P0)] = 0;
               sJ[3 * (dst - P0) + 1] = 0;
@@ -579,7 +585,7 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
         for (int b = 0; b < kDrain; ++b) {
           pj[b] = sF[jj[b]];
           qj[b] = sQ[jj[b]];
-          tj[b] = sT[jj[b]];
+          tj[b] = (int)(__float_as_uint(pj[b].w) & tmask);
         }
 #pragma unroll
         for (int b = 0; b < kDrain; ++b) lj[b] = sLJ[row[k] + tj[b]];
@@ -605,7 +611,7 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
             if (diag) lane_count += 64;
             const float4 pj = sF[jj];
             const float qj = sQ[jj];
-            const float2 lj = sLJ[row[k] + sT[jj]];
+            const float2 lj = sLJ[row[k] + (int)(__float_as_uint(pj.w) & tmask)];
             pair_lane(k, jj, pj, qj, lj, off + lane < n);
           }
           fb[k] = fk0 + 2u * (uint32_t)(k * kFifo);
