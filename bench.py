@@ -35,8 +35,8 @@ METRIC = "within-cutoff pair-interactions/s @92k atoms; p50/p99 latency mixed ba
 # HBM bytes per launch of the pair kernel at 92,224 atoms, from the FETCH_SIZE and
 # WRITE_SIZE counters scaled by a copy of known size (profiles/traffic_pair_fs_92k.md);
 # valid only for the kernel source they were taken on
-PAIR_TRAFFIC = {"kernel_sha256": "ef8ef20c0a9d4386d2a394b4e72353e9bbd4a3de820fa9089f77c3180e32b67b",
-                "bytes": (14463 + 2205) * 1024}
+PAIR_TRAFFIC = {"kernel_sha256": "a3d4a26585d361f9a68d8178a9fc8afe0c30684ca278224682308436c0e06bcf",
+                "bytes": (17867 + 35430) * 1024}
 
 
 def parse():
