@@ -316,8 +316,9 @@ __global__ __launch_bounds__(256) void k_scatter_batch(Batch<float> b) {
 }
 
 // One workgroup per cell. Each member's position in the cell is the number of members
-// with a smaller key, counted over LDS chunks of the cell's keys, so any cell occupancy
-// is handled; the member's data then move to that position.
+// with a smaller key (keys are distinct: they hold the atom index), counted over LDS
+// chunks of the cell's keys, so any cell occupancy is handled; the member's data then
+// move to that position.
 template <typename Real>
 __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
   constexpr int kChunk = 1024;
@@ -327,6 +328,67 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
   const int32_t s0 = a.start[c];
   const int32_t m = a.start[c + 1] - s0;
   if (threadIdx.x == 0) s_low = 0;
+  if (m == 0) {
+    if (threadIdx.x == 0) a.zsplit[c] = 0;
+    return;
+  }
+  if (m <= kChunk) {
+    // the whole cell in one LDS chunk: each member's key, position and type are loaded
+    // once, together, and the keys go to LDS from registers
+    const int kk = (m + 255) / 256;   // member slots in use (uniform)
+    unsigned long long my_key[kPer];
+    Real px[kPer], py[kPer], pz[kPer], pq[kPer];
+    int32_t my_t[kPer], my_rank[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int32_t e = (int32_t)threadIdx.x + 256 * k;
+      const bool in = k < kk && e < m;
+      const int32_t src = s0 + (in ? e : 0);   // m >= 1 here: a valid member
+      my_key[k] = in ? a.ukey[src] : ~0ull;
+      const P4<Real> p = a.upos[src];
+      px[k] = p.x;
+      py[k] = p.y;
+      pz[k] = p.z;
+      pq[k] = p.w;
+      my_t[k] = a.unsorted[src];
+      my_rank[k] = 0;
+    }
+    // slots m .. 256 kk - 1 (a multiple of 8) hold ~0, which is below no key
+#pragma unroll
+    for (int k = 0; k < kPer; ++k)
+      if (k < kk) s_key[threadIdx.x + 256 * k] = my_key[k];
+    __syncthreads();
+    for (int32_t e = 0; e < m; e += 8) {
+      unsigned long long kx[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) kx[u] = s_key[e + u];
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) {
+        if (k < kk) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) my_rank[k] += kx[u] < my_key[k];
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int32_t e = (int32_t)threadIdx.x + 256 * k;
+      if (!(k < kk && e < m)) continue;
+      const int32_t d = s0 + my_rank[k];
+      if (!(my_key[k] >> 63)) atomicAdd(&s_low, 1);
+      P4<Real> p;
+      p.x = px[k];
+      p.y = py[k];
+      p.z = pz[k];
+      p.w = pq[k];
+      a.pos[d] = p;
+      a.type[d] = my_t[k];
+      a.perm[d] = (int32_t)(my_key[k] & 0x7fffffffull);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) a.zsplit[c] = s_low;
+    return;
+  }
   for (int32_t a0 = 0; a0 < m; a0 += kChunk) {
     const int kk = min(kPer, (m - a0 + 255) / 256);   // member slots in use (uniform)
     unsigned long long my_key[kPer];
