@@ -320,7 +320,9 @@ def ablation(steps, dev):
     predicated one (every candidate through the force arithmetic under the cutoff
     predicate), on the 92,224-atom system: pair-stage time, force-stage lane utilisation
     (unique pairs / lanes through the force arithmetic; the full shell evaluates every
-    pair twice, so its figure is at most 0.5)."""
+    pair twice, so its figure is at most 0.5). Then the half-shell kernel with 1 to 4
+    candidate batches of 64 per force pass (the drain depth; 2 is the default): the GPU
+    analog of the paper's sweep of distance PEs per force PE."""
     import torch
     from paper_1611_04474_amd import api
     from paper_1611_04474_amd import workloads as W
@@ -356,6 +358,31 @@ def ablation(steps, dev):
                      "pairs_per_s_pair_stage": pairs / (med * 1e-3)}
     out["speedup_compacted"] = (out["predicated_half_shell"]["pair_ms_median"] /
                                 out["compacted_half_shell"]["pair_ms_median"])
+    # candidate batches per force pass: 64 d passing pairs drained together from a FIFO
+    P0 = api.Params.from_dict(s.params())
+    sweep = {}
+    for d in (1, 2, 3, 4):
+        P = P0.with_flags(api.PAIR_DRAIN(d))
+        ws = api.alloc_workspace(P, s.n, dev)
+        api.forces(P.with_flags(P.flags | api.DIAG_COUNTERS), pos, typ, q, force=force,
+                   energy=energy, workspace=ws)
+        _, _, pairs, _, lanes = api.read_diag(ws)
+        ms = []
+        for k in range(steps + 2):
+            api.forces_stages(P, pos, typ, q, force, energy, ws, api.STAGE_BIN)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            api.forces_stages(P, pos, typ, q, force, energy, ws, api.STAGE_PAIR)
+            b.record(stream)
+            api.forces_stages(P, pos, typ, q, force, energy, ws, api.STAGE_FINALIZE)
+            torch.cuda.synchronize()
+            if k >= 2:
+                ms.append(a.elapsed_time(b))
+        med = pct(ms, 50)
+        sweep[str(d)] = {"pair_ms_median": med, "force_lanes": lanes,
+                         "force_lane_utilisation": pairs / lanes if lanes else None,
+                         "pairs_per_s_pair_stage": pairs / (med * 1e-3)}
+    out["drain_depth_sweep_half_shell"] = sweep
     out["speedup_half_over_full_shell"] = (out["compacted_full_shell"]["pair_ms_median"] /
                                            out["compacted_half_shell"]["pair_ms_median"])
     return out

@@ -73,6 +73,15 @@ enum {
                                    any order */
 };
 
+/* md_params.flags bits 5-6: force batches of 64 pairs drained together from a full FIFO
+ * by the compacted half-shell kernel with the whole energy switched -- the candidate
+ * batches per force pass, swept like the distance PEs per force PE of Section 5.2
+ * (Table 6). 0 keeps the default depth 2; MD_PAIR_DRAIN(d) selects d = 1, 3 or 4. Any other
+ * configuration (float64, predicated, full shell, float32 sums, Coulomb truncated,
+ * r_switch == r_cut) accepts only 0 and returns MD_ERR_INVALID_ARG otherwise. */
+#define MD_PAIR_DRAIN_MASK (3u << 5)
+#define MD_PAIR_DRAIN(d) ((uint32_t)((d) == 1 ? 1 : (d) == 3 ? 2 : (d) == 4 ? 3 : 0) << 5)
+
 /* Device status bits (sticky until the next force call on the workspace). */
 enum {
   MD_STATUS_NAN = 1u << 0,          /* a position is NaN */

@@ -24,6 +24,13 @@ COULOMB_TRUNCATED = 1 << 1
 DIAG_COUNTERS = 1 << 2
 PAIR_PREDICATED = 1 << 3
 PAIR_FULL_SHELL = 1 << 4
+PAIR_DRAIN_MASK = 3 << 5
+
+
+def PAIR_DRAIN(d):
+    """Flag bits selecting d force batches per FIFO drain (d = 1..4; 2 is the default)."""
+    return {2: 0, 1: 1 << 5, 3: 2 << 5, 4: 3 << 5}[int(d)]
+
 
 STATUS_NAN = 1 << 0
 STATUS_OUT_OF_BOX = 1 << 1

@@ -22,8 +22,15 @@ static md_status check_params(const md_params* p) {
   if (!(p->r_switch > 0) || p->r_switch > p->r_cut) return MD_ERR_INVALID_ARG;
   if (!isfinite(p->coulomb_k)) return MD_ERR_INVALID_ARG;
   const uint32_t known = MD_ACCUM_F32_ATOMIC | MD_COULOMB_TRUNCATED | MD_DIAG_COUNTERS |
-                         MD_PAIR_PREDICATED | MD_PAIR_FULL_SHELL;
+                         MD_PAIR_PREDICATED | MD_PAIR_FULL_SHELL | MD_PAIR_DRAIN_MASK;
   if (p->flags & ~known) return MD_ERR_INVALID_ARG;
+  // another drain depth only for the kernel that has it: the compacted half shell with the
+  // whole energy switched (the float64 path is checked in check_call)
+  if ((p->flags & MD_PAIR_DRAIN_MASK) &&
+      ((p->flags & (MD_ACCUM_F32_ATOMIC | MD_COULOMB_TRUNCATED | MD_PAIR_PREDICATED |
+                    MD_PAIR_FULL_SHELL)) ||
+       !(p->r_switch < p->r_cut)))
+    return MD_ERR_INVALID_ARG;
   for (int d = 0; d < 3; ++d)
     if (!isfinite(p->box[d]) || !(p->box[d] > 0)) return MD_ERR_INVALID_ARG;
   return MD_OK;
@@ -162,6 +169,7 @@ static md_status check_call(const md_params* p, int64_t n, const Real* pos, cons
                             const void* ws, size_t ws_bytes, Plan* pl) {
   md_status s = make_plan(p, n, (int)sizeof(Real), pl);
   if (s != MD_OK) return s;
+  if (sizeof(Real) == 8 && (p->flags & MD_PAIR_DRAIN_MASK)) return MD_ERR_INVALID_ARG;
   if (!energy || ((uintptr_t)energy & 7)) return MD_ERR_INVALID_ARG;
   if (n > 0) {
     if (!pos || !type || !q || !force) return MD_ERR_INVALID_ARG;

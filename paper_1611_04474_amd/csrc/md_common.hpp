@@ -14,7 +14,7 @@ constexpr int kTasksPerCell = 14;    // home cell + 13 forward neighbours (half 
 constexpr int kSlots = 27;           // partial-force slots per atom: 14 as home, 13 as neighbour
 constexpr int kTile = 256;           // atoms of one cell staged in LDS at a time
 constexpr int kPairThreads = 256;    // threads of one half-shell pair workgroup (4 waves)
-constexpr int kFsSplit = 1;          // full-shell workgroups per home cell
+constexpr int kFsSplit = 1;          // compacted-kernel workgroups per home cell
 constexpr int64_t kMaxCells = 1 << 24;
 constexpr int64_t kMaxAtoms = (int64_t)1 << 30;
 constexpr int kBinLdsCells = 32768;  // largest grid binned with a per-block LDS histogram
@@ -22,6 +22,12 @@ constexpr int kBinMaxBlocks = 64;    // blocks of that pass
 constexpr int kBinMinChunk = 2048;   // atoms per block at least
 
 // Workspace header (first 256 bytes).
+// Drain depth selected by MD_PAIR_DRAIN in md_params.flags (2 when the field is 0).
+__host__ __device__ inline int md_pair_drain(uint32_t flags) {
+  const uint32_t v = (flags & MD_PAIR_DRAIN_MASK) >> 5;
+  return v == 0 ? 2 : v == 1 ? 1 : v == 2 ? 3 : 4;
+}
+
 struct WsHeader {
   uint32_t status;
   uint32_t pad0;

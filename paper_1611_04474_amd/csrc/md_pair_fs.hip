@@ -48,9 +48,11 @@ constexpr int kThreads = 64 * kNW;
 constexpr int kQ = 4;               // home atoms filtered together by one wave, one FIFO each
 static_assert(kQ % 4 == 0, "FIFO appends are written four home atoms at a time");
 static_assert(kNW % 4 == 0 && kNW * 64 <= 1024, "waves per workgroup");
-constexpr int kDrain = 2;           // force batches of 64 drained together from a full FIFO
-constexpr int kFifo = 64 * (kDrain + 1);   // FIFO entries (uint16 neighbour index) per atom
-constexpr int kWaveFifo = kQ * kFifo;
+// Force batches of 64 drained together from a full FIFO (kD, a template parameter: 2 by
+// default, 1 to 4 for the drain-depth sweep); a FIFO holds 64 (kD + 1) uint16 neighbour
+// indices.
+constexpr int kDrainDefault = 2;
+__host__ __device__ constexpr int fifo_entries(int drain) { return 64 * (drain + 1); }
 constexpr int kMaxSeg = 36;         // 9 (dy, dz) rows x 2 z halves, each split at most once by
                                     // an x wrap
 constexpr int kLdsBytes = 160 * 1024;
@@ -113,11 +115,11 @@ __host__ __device__ inline int slot_bytes(bool half, bool diag) {
   return 20 + (half ? 24 + (diag ? 4 : 0) : 0);
 }
 
-__host__ __device__ inline Lds lds_layout(int cap, int n_types, bool half, bool diag) {
+__host__ __device__ inline Lds lds_layout(int cap, int n_types, bool half, bool diag, int drain) {
   Lds L;
   L.hdr = 0;
   L.fifo = align_up(L.hdr + (int)sizeof(Hdr), 16);
-  L.lj = align_up(L.fifo + 2 * kNW * kWaveFifo, 16);
+  L.lj = align_up(L.fifo + 2 * kNW * kQ * fifo_entries(drain), 16);
   L.f4 = align_up(L.lj + 8 * n_types * n_types, 16);
   L.q = L.f4 + 16 * cap;
   L.jacc = align_up(L.q + 4 * cap, 16);
@@ -233,13 +235,15 @@ __device__ inline void lds_store_u16_lanes4(uint32_t a0, uint32_t a1, uint32_t a
 // nothing (a partial batch, the home atom itself) get u = kBigU instead of masks on f
 // and e, and pairs beyond the cutoff need no test (t clamps to 1).
 // kDiag: count filter passes, cutoff passes and filtered slots (MD_DIAG_COUNTERS).
-// kHalf: the half shell (64-bit fixed-point sums only).
-template <bool kHalf, bool kSwitchCoulomb, bool kClamp, bool kDiag>
+// kHalf: the half shell (64-bit fixed-point sums only). kDrain: force batches per drain.
+template <bool kHalf, bool kSwitchCoulomb, bool kClamp, bool kDiag, int kDrain>
 __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<float>& a, int cap,
                                                               int64_t cellA) {
   extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
   constexpr int kImg = kHalf ? 14 : 27;   // neighbour images
-  const Lds LL = lds_layout(cap, a.n_types, kHalf, kDiag);
+  constexpr int kFifo = fifo_entries(kDrain);
+  constexpr int kWaveFifo = kQ * kFifo;
+  const Lds LL = lds_layout(cap, a.n_types, kHalf, kDiag, kDrain);
   Hdr& H = *reinterpret_cast<Hdr*>(s_dyn + LL.hdr);
   uint16_t* sFifo = reinterpret_cast<uint16_t*>(s_dyn + LL.fifo);
   float2* sLJ = reinterpret_cast<float2*>(s_dyn + LL.lj);
@@ -830,37 +834,39 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
   }
 }
 
-template <bool kHalf, bool kSwitchCoulomb, bool kClamp, bool kDiag>
+template <bool kHalf, bool kSwitchCoulomb, bool kClamp, bool kDiag, int kDrain>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNW / 4, kNW / 4)))
 void k_pair_fs(SysArgs<float> a, int cap) {
   // home cells in decreasing order of atom count, spread over the XCDs in turn
-  pair_fs<kHalf, kSwitchCoulomb, kClamp, kDiag>(a, cap, a.order[blockIdx.x]);
+  pair_fs<kHalf, kSwitchCoulomb, kClamp, kDiag, kDrain>(a, cap, a.order[blockIdx.x]);
 }
 
 // One launch for a batch: block b is cell order[b - cum[s]] of system s.
-template <bool kHalf, bool kSwitchCoulomb, bool kClamp, bool kDiag>
+template <bool kHalf, bool kSwitchCoulomb, bool kClamp, bool kDiag, int kDrain>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNW / 4, kNW / 4)))
 void k_pair_fs_batch(Batch<float> b, int cap) {
   int64_t unit;
   const int s = b.pick(blockIdx.x, unit);
-  pair_fs<kHalf, kSwitchCoulomb, kClamp, kDiag>(b.sys[s], cap, b.sys[s].order[unit]);
+  pair_fs<kHalf, kSwitchCoulomb, kClamp, kDiag, kDrain>(b.sys[s], cap, b.sys[s].order[unit]);
 }
 
-template <bool H, bool S, bool C, bool D>
+template <bool H, bool S, bool C, bool D, int R>
 struct launch_tag {
   static constexpr bool half = H, sw = S, clamp = C, diag = D;
+  static constexpr int drain = R;
 };
 
 // Neighbour atoms staged in LDS per pass (a multiple of 64).
-int fs_cap(int n_types, bool half, bool diag) {
-  int cap = (kLdsBytes - lds_layout(0, n_types, half, diag).total) / slot_bytes(half, diag);
+int fs_cap(int n_types, bool half, bool diag, int drain) {
+  int cap = (kLdsBytes - lds_layout(0, n_types, half, diag, drain).total) / slot_bytes(half, diag);
   cap -= cap % 64;
-  while (cap > 0 && lds_layout(cap, n_types, half, diag).total > kLdsBytes) cap -= 64;
+  while (cap > 0 && lds_layout(cap, n_types, half, diag, drain).total > kLdsBytes) cap -= 64;
   return cap;
 }
 
-// The kernel instance for a system's flags: half or full shell, and how the switch
-// applies (whole energy with the clamp, whole energy, or LJ only).
+// The kernel instance for a system's flags: half or full shell, how the switch applies
+// (whole energy with the clamp, whole energy, or LJ only), and the drain depth (other
+// depths than the default only for the half shell with the clamp; the API checks that).
 template <typename Args, typename Launch>
 hipError_t dispatch(const SysArgs<float>& a, const Args& args, int n_types, int64_t blocks,
                     hipStream_t stream, Launch launch) {
@@ -868,17 +874,25 @@ hipError_t dispatch(const SysArgs<float>& a, const Args& args, int n_types, int6
   const bool diag = (a.flags & MD_DIAG_COUNTERS) != 0;
   const bool trunc = (a.flags & MD_COULOMB_TRUNCATED) != 0;
   const bool clamp = !trunc && a.inv_sw > 0.f;
-  const int cap = fs_cap(n_types, half, diag);
-  const size_t shmem = (size_t)lds_layout(cap, n_types, half, diag).total;
+  const int drain = md_pair_drain(a.flags);
+  if (drain != kDrainDefault && !(half && clamp)) return hipErrorInvalidValue;
+  const int cap = fs_cap(n_types, half, diag, drain);
+  const size_t shmem = (size_t)lds_layout(cap, n_types, half, diag, drain).total;
   const dim3 grid((unsigned)blocks), block(kThreads);
   auto go = [&](auto h, auto d) {
     constexpr bool H = decltype(h)::value, D = decltype(d)::value;
-    if (clamp)
-      launch(launch_tag<H, true, true, D>(), grid, block, shmem, stream, args, cap);
-    else if (!trunc)
-      launch(launch_tag<H, true, false, D>(), grid, block, shmem, stream, args, cap);
-    else
-      launch(launch_tag<H, false, false, D>(), grid, block, shmem, stream, args, cap);
+    if (clamp) {
+      if constexpr (H) {
+        if (drain == 1) return launch(launch_tag<H, true, true, D, 1>(), grid, block, shmem, stream, args, cap);
+        if (drain == 3) return launch(launch_tag<H, true, true, D, 3>(), grid, block, shmem, stream, args, cap);
+        if (drain == 4) return launch(launch_tag<H, true, true, D, 4>(), grid, block, shmem, stream, args, cap);
+      }
+      launch(launch_tag<H, true, true, D, kDrainDefault>(), grid, block, shmem, stream, args, cap);
+    } else if (!trunc) {
+      launch(launch_tag<H, true, false, D, kDrainDefault>(), grid, block, shmem, stream, args, cap);
+    } else {
+      launch(launch_tag<H, false, false, D, kDrainDefault>(), grid, block, shmem, stream, args, cap);
+    }
   };
   using T = std::true_type;
   using F = std::false_type;
@@ -898,8 +912,8 @@ hipError_t launch_pair_fs(const SysArgs<float>& a, hipStream_t stream) {
                   [](auto tag, dim3 g, dim3 b, size_t sh, hipStream_t st, const SysArgs<float>& x,
                      int cap) {
                     using Tg = decltype(tag);
-                    hipLaunchKernelGGL((k_pair_fs<Tg::half, Tg::sw, Tg::clamp, Tg::diag>), g, b,
-                                       sh, st, x, cap);
+                    hipLaunchKernelGGL((k_pair_fs<Tg::half, Tg::sw, Tg::clamp, Tg::diag, Tg::drain>),
+                                       g, b, sh, st, x, cap);
                   });
 }
 
@@ -915,8 +929,9 @@ hipError_t launch_pair_fs_batch(const Batch<float>& b0, hipStream_t stream) {
                   [](auto tag, dim3 g, dim3 bl, size_t sh, hipStream_t st, const Batch<float>& x,
                      int cap) {
                     using Tg = decltype(tag);
-                    hipLaunchKernelGGL((k_pair_fs_batch<Tg::half, Tg::sw, Tg::clamp, Tg::diag>),
-                                       g, bl, sh, st, x, cap);
+                    hipLaunchKernelGGL(
+                        (k_pair_fs_batch<Tg::half, Tg::sw, Tg::clamp, Tg::diag, Tg::drain>), g, bl,
+                        sh, st, x, cap);
                   });
 }
 

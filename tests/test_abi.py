@@ -92,6 +92,21 @@ def test_argument_errors_are_synchronous():
                           double_precision=True) == -3             # f64 needs more workspace
 
 
+def test_drain_depth_only_where_the_kernel_has_it():
+    base = W.small_system().params()
+    need = api.workspace_bytes(base, 10)
+    assert [api.PAIR_DRAIN(d) for d in (2, 1, 3, 4)] == [0, 1 << 5, 2 << 5, 3 << 5]
+    for bad in (api.PAIR_FULL_SHELL, api.PAIR_PREDICATED, api.ACCUM_F32_ATOMIC,
+                api.COULOMB_TRUNCATED):
+        assert _call_f32(dict(base, flags=api.PAIR_DRAIN(3) | bad), ws_bytes=need) == -1
+    # r_switch == r_cut: no clamp, so no other drain depth
+    assert _call_f32(dict(base, r_switch=base["r_cut"], flags=api.PAIR_DRAIN(1)),
+                     ws_bytes=need) == -1
+    need64 = api.workspace_bytes(base, 10, True)
+    assert api.forces_raw(dict(base, flags=api.PAIR_DRAIN(4)), 10, 4096, 4096, 4096, 4096, 4096,
+                          256, need64, 0, double_precision=True) == -1
+
+
 def test_batched_rejects_before_enqueue():
     base = W.small_system().params()
 

@@ -436,6 +436,28 @@ def test_precision_form_report(gpu):
         assert report[name]["energy_rel"] <= 1e-6, report
 
 
+@pytest.mark.parametrize("drain", [1, 3, 4])
+def test_drain_depths(gpu, drain):
+    """The half-shell kernel instantiated with other drain depths (the candidate-batches
+    per force pass sweep) against the oracle, with a multi-pass neighbour load too."""
+    _say("case: drain depth", drain)
+    s = W.small_system()
+    p = s.params()
+    f, e, ws, cnt = run(p, s.pos, s.types, s.charges, gpu,
+                        flags=api.PAIR_DRAIN(drain) | api.DIAG_COUNTERS)
+    _check_fp32(p, s.pos, s.types, s.charges, f, e, cnt)
+    assert api.read_status(ws) == 0
+    rng = np.random.default_rng(11)
+    L = 37.0
+    pos = np.mod(_lattice_blob(rng, np.zeros(3), 20, 1.85, 0.3), L).astype(np.float32).astype(np.float64)
+    t = rng.integers(0, 2, len(pos)).astype(np.int32)
+    q = rng.normal(0, 0.3, len(pos))
+    p2 = dict(box=(L, L, L), r_cut=12.0, r_switch=10.0, coulomb_k=W.COULOMB_K,
+              sigma=np.array([1.0, 1.2]), epsilon=np.array([0.05, 0.1]), flags=0)
+    f2, e2, ws2, cnt2 = run(p2, pos, t, q, gpu, flags=api.PAIR_DRAIN(drain) | api.DIAG_COUNTERS)
+    _check_fp32(p2, pos, t, q, f2, e2, cnt2)
+
+
 @pytest.mark.parametrize("shell", [0, api.PAIR_FULL_SHELL])
 @pytest.mark.parametrize("case", ["truncated_coulomb", "no_switch", "sixty_four_types"])
 def test_fp32_kernel_variants(gpu, case, shell):
