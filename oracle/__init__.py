@@ -240,3 +240,47 @@ def band_atoms(params, pos, band, n_threads=0):
     _check(lib().mdo_band_atoms(p.ref(), n, _ptr(pos64, C.c_double), float(band), C.byref(tot),
                                 _ptr(per, C.c_int64), int(n_threads)), "mdo_band_atoms")
     return per, int(tot.value)
+
+
+# ---------------------------------------------------------------------------------------
+# Motion update around the force call. Each MD iteration first computes the forces on
+# every atom and then updates the atoms' motion (Section 1; Section 2.1). The paper names
+# no integrator; this is velocity Verlet, written out plainly in float64:
+#   v(t + dt/2) = v(t) + (dt/2) a(t)
+#   x(t + dt)   = x(t) + dt v(t + dt/2), wrapped into [0, L)
+#   a(t + dt)   = F(x(t + dt)) / m
+#   v(t + dt)   = v(t + dt/2) + (dt/2) a(t + dt)
+# Units: A, fs, amu, kcal/mol. (kcal/mol/A)/amu = 4.184e-4 A/fs^2: 1 cal = 4.184 J and an
+# amu times Avogadro's number is one gram.
+
+ACCEL = 4.184e-4
+
+
+def kinetic_energy(vel, inv_mass):
+    """sum of m v^2 / 2 in kcal/mol, for velocities in A/fs and 1/m in 1/amu."""
+    v = np.asarray(vel, dtype=np.float64)
+    return float(0.5 * np.sum(np.sum(v * v, axis=1) / np.asarray(inv_mass, dtype=np.float64)) / ACCEL)
+
+
+def vv_steps(params, pos, vel, types, charges, inv_mass, dt, n_steps, method="celllist",
+             n_threads=0):
+    """n_steps velocity-Verlet steps of dt fs from positions pos [n,3] and velocities vel
+    [n,3] (A/fs). Returns (pos, vel, force, pe [n_steps], ke [n_steps]), all float64; pe[k]
+    and ke[k] are the potential and kinetic energy after step k + 1."""
+    L = np.asarray(params["box"], dtype=np.float64)
+    x, _ = canonicalize(pos, L)
+    v = np.array(vel, dtype=np.float64)
+    im = np.asarray(inv_mass, dtype=np.float64)[:, None]
+    F = forces(params, x, types, charges, method, n_threads).force
+    pe = np.zeros(n_steps)
+    ke = np.zeros(n_steps)
+    for k in range(n_steps):
+        v = v + 0.5 * dt * (F * im * ACCEL)
+        x = x + dt * v
+        x = x - L * np.floor(x / L)
+        r = forces(params, x, types, charges, method, n_threads)
+        F = r.force
+        v = v + 0.5 * dt * (F * im * ACCEL)
+        pe[k] = r.energy
+        ke[k] = kinetic_energy(v, im[:, 0])
+    return x, v, F, pe, ke
