@@ -58,6 +58,8 @@ def parse():
                     help="most requests in one batched launch sequence")
     ap.add_argument("--serving-inflight", type=int, default=2,
                     help="most batches on the GPU at once")
+    ap.add_argument("--md-steps", type=int, default=200,
+                    help="velocity-Verlet steps of the motion-update run (0 disables it)")
     ap.add_argument("--scaling-evals", type=int, default=20,
                     help="evaluations of the 1,066,628-atom scaling shape (0 disables it)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -219,6 +221,8 @@ def main():
                                      "2k-200k atoms at 200 req/s, continuous batching"}
     if args.scaling_evals > 0:
         out["scaling_1m"] = scaling(args.scaling_evals, dev)
+    if args.md_steps > 0:
+        out["md_vv_92k"] = md_loop(args.md_steps, dev)
     if args.ablation_steps > 0:
         out["ablation_data_flow"] = ablation(args.ablation_steps, dev)
     if args.cpu_seconds > 0:
@@ -268,6 +272,58 @@ def serving(n_req, dev, max_batch, inflight):
         both(f"poisson_{int(rate)}hz", arr - arr[0], 64 << 30)
     gc.enable()
     return out
+
+
+def md_loop(steps, dev, dt=0.5):
+    """The motion update around the force path: velocity Verlet (md_run_vv_f32) on 92,224
+    atoms in the force benchmark's box and density, with LJ parameters that keep the
+    dynamics bounded (workloads.liquid_system) and velocities of about 300 K. One call
+    of `steps` steps is timed with HIP events after a 10-step warm-up, next to the force
+    call alone on the same system; the energies of every step give the deviation of the
+    total energy from its start."""
+    import torch
+    from paper_1611_04474_amd import api
+    from paper_1611_04474_amd import workloads as W
+    s = W.liquid_system(W.APOA1_N, W.APOA1_BOX)
+    v, im = W.velocities(s.types)
+    P = api.Params.from_dict(s.params())
+    pos = torch.as_tensor(s.pos).to(dev)
+    typ = torch.as_tensor(s.types).to(dev)
+    q = torch.as_tensor(s.charges).to(dev)
+    vel = torch.as_tensor(v).to(dev)
+    inv_m = torch.as_tensor(im).to(dev)
+    ws = api.alloc_workspace(P, s.n, dev)
+    force, e0 = api.forces(P, pos, typ, q, workspace=ws)
+    stream = torch.cuda.current_stream()
+    api.run_vv(P, pos, vel, typ, q, inv_m, force, dt, 10, workspace=ws)
+    en = torch.empty((steps, 2), dtype=torch.float64, device=dev)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(stream)
+    api.run_vv(P, pos, vel, typ, q, inv_m, force, dt, steps, energies=en, workspace=ws)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    status = api.read_status(ws)
+    # the force call alone on the final positions
+    f2 = torch.empty_like(force)
+    e2 = torch.empty(1, dtype=torch.float64, device=dev)
+    fms = []
+    for k in range(steps // 4 + 2):
+        c, d = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c.record(stream)
+        api.forces(P, pos, typ, q, force=f2, energy=e2, workspace=ws)
+        d.record(stream)
+        torch.cuda.synchronize()
+        if k >= 2:
+            fms.append(c.elapsed_time(d))
+    e = en.cpu().numpy()
+    tot = e[:, 0] + e[:, 1]
+    return {"n_atoms": s.n, "dt_fs": dt, "steps": steps, "ms_per_step": ms,
+            "force_call_ms_median": pct(fms, 50), "ns_per_day": dt * 1e-6 * 86400e3 / ms,
+            "energy_first": float(tot[0]), "energy_max_dev": float(np.abs(tot - tot[0]).max()),
+            "kinetic_first": float(e[0, 1]), "kinetic_last": float(e[-1, 1]),
+            "status": int(status)}
 
 
 def scaling(n_eval, dev):

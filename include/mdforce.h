@@ -169,6 +169,26 @@ typedef struct {
  * anything is enqueued. */
 md_status md_forces_batched(const md_system* systems, int32_t n_sys, void* stream);
 
+/* Motion update around the force call: n_steps velocity-Verlet steps of dt fs on
+ * device-resident state (each MD iteration computes the forces on every atom, then updates
+ * the atoms' motion: Section 1, Section 2.1; the paper names no integrator). Per step:
+ *   v += (dt/2) F/m;  x += dt v, wrapped into [0, L) by one add or subtract of L;
+ *   F = the force path of md_forces_f32 at the new x;  v += (dt/2) F/m.
+ * Units: A, fs, amu, kcal/mol; F/m in (kcal/mol/A)/amu is 4.184e-4 A/fs^2.
+ *   d_pos      float32 [n][3], in/out: positions (caller order), as for md_forces_f32
+ *   d_vel      float32 [n][3], in/out: velocities, A/fs
+ *   d_inv_mass float32 [n]: 1/m per atom, 1/amu (0 pins an atom)
+ *   d_force    float32 [n][3], in: the forces at d_pos (from md_forces_f32 with the same
+ *              parameters); out: the forces at the final positions
+ *   d_energies double [n_steps][2], out: potential and kinetic energy (kcal/mol) after
+ *              each step, the kinetic energy summed in a fixed order
+ * Workspace, stream, status word and errors as for md_forces_f32; dt must be finite and
+ * n_steps >= 0 (0 does nothing). All device pointers are caller-owned. */
+md_status md_run_vv_f32(const md_params* p, int64_t n_atoms, float* d_pos, float* d_vel,
+                        const int32_t* d_type, const float* d_charge, const float* d_inv_mass,
+                        float* d_force, double dt_fs, int32_t n_steps, double* d_energies,
+                        void* d_ws, size_t ws_bytes, void* stream);
+
 /* Copies the sticky device status word of a workspace to *bits (MD_STATUS_* bits).
  * Synchronises `stream`. */
 md_status md_read_device_status(const void* d_ws, void* stream, uint32_t* bits);

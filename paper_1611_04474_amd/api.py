@@ -92,6 +92,9 @@ def lib():
         L.md_forces_f32_stages.restype = C.c_int
         L.md_forces_batched.argtypes = [C.POINTER(_System), C.c_int32, vp]
         L.md_forces_batched.restype = C.c_int
+        L.md_run_vv_f32.argtypes = [pp, C.c_int64, vp, vp, vp, vp, vp, vp, C.c_double, C.c_int32,
+                                    vp, vp, C.c_size_t, vp]
+        L.md_run_vv_f32.restype = C.c_int
         L.md_read_device_status.argtypes = [vp, vp, C.POINTER(C.c_uint32)]
         L.md_read_device_status.restype = C.c_int
         L.md_read_diag.argtypes = [vp, vp, C.POINTER(C.c_uint64)]
@@ -103,7 +106,7 @@ def lib():
 
 
 EXPORTED = ("md_workspace_bytes", "md_forces_f32", "md_forces_f32_stages", "md_forces_f64",
-            "md_forces_batched",
+            "md_forces_batched", "md_run_vv_f32",
             "md_read_device_status", "md_read_diag", "md_workspace_layout", "md_status_string")
 
 
@@ -281,6 +284,37 @@ def forces_batched(systems, stream=None):
     rc = lib().md_forces_batched(arr, len(systems), _stream_ptr(stream))
     if rc != MD_OK:
         raise MDError(rc, "md_forces_batched")
+
+
+def run_vv(params, pos, vel, types, charges, inv_mass, force, dt, n_steps, *, energies=None,
+           workspace=None, stream=None):
+    """n_steps velocity-Verlet steps of dt fs (md_run_vv_f32). pos, vel, force float32 [n,3]
+    on the device, updated in place; force must hold the forces at pos on entry. Returns
+    the energies tensor [n_steps, 2] float64 (potential, kinetic) on the device."""
+    import torch
+    p = _as_params(params)
+    n = int(pos.shape[0])
+    _check_tensor(pos, torch.float32, (n, 3), "pos")
+    _check_tensor(vel, torch.float32, (n, 3), "vel")
+    _check_tensor(force, torch.float32, (n, 3), "force")
+    _check_tensor(types, torch.int32, (n,), "types")
+    _check_tensor(charges, torch.float32, (n,), "charges")
+    _check_tensor(inv_mass, torch.float32, (n,), "inv_mass")
+    if energies is None:
+        energies = torch.empty((max(int(n_steps), 1), 2), dtype=torch.float64, device=pos.device)
+    if workspace is None:
+        workspace = alloc_workspace(p, n, pos.device)
+    elif isinstance(workspace, Workspace):
+        workspace = workspace.get(p, n, pos.device, False)
+    rc = lib().md_run_vv_f32(p.ref(), n, C.c_void_p(pos.data_ptr()), C.c_void_p(vel.data_ptr()),
+                             C.c_void_p(types.data_ptr()), C.c_void_p(charges.data_ptr()),
+                             C.c_void_p(inv_mass.data_ptr()), C.c_void_p(force.data_ptr()),
+                             float(dt), int(n_steps), C.c_void_p(energies.data_ptr()),
+                             C.c_void_p(workspace.data_ptr()), int(workspace.numel()),
+                             _stream_ptr(stream))
+    if rc != MD_OK:
+        raise MDError(rc, "md_run_vv_f32")
+    return energies
 
 
 def read_status(workspace, stream=None):

@@ -95,6 +95,7 @@ md_status make_plan(const md_params* p, int64_t n, int real_bytes, Plan* pl) {
   pl->off_zsplit = o;    o = align_up(o + sizeof(int32_t) * cells);
   pl->off_ukey = o;      o = align_up(o + sizeof(unsigned long long) * nn);
   pl->off_upos = o;      o = align_up(o + (size_t)4 * real_bytes * nn);
+  pl->off_kpart = o;     o = align_up(o + sizeof(double) * (size_t)ke_blocks(n));
   pl->total = o;
   return MD_OK;
 }
@@ -268,6 +269,36 @@ md_status md_forces_f64(const md_params* p, int64_t n_atoms, const double* d_pos
                         double* d_energy, void* d_ws, size_t ws_bytes, void* stream) {
   return md::forces_impl<double>(p, n_atoms, d_pos, d_type, d_charge, d_force, d_energy, d_ws,
                                  ws_bytes, stream);
+}
+
+md_status md_run_vv_f32(const md_params* p, int64_t n_atoms, float* d_pos, float* d_vel,
+                        const int32_t* d_type, const float* d_charge, const float* d_inv_mass,
+                        float* d_force, double dt_fs, int32_t n_steps, double* d_energies,
+                        void* d_ws, size_t ws_bytes, void* stream) {
+  if (n_steps < 0 || !isfinite(dt_fs)) return MD_ERR_INVALID_ARG;
+  md::Plan pl;
+  md_status s = md::check_call<float>(p, n_atoms, d_pos, d_type, d_charge, d_force, d_energies,
+                                      d_ws, ws_bytes, &pl);
+  if (s != MD_OK) return s;
+  if (n_atoms > 0 && (!d_vel || !d_inv_mass || (((uintptr_t)d_vel | (uintptr_t)d_inv_mass) & 3)))
+    return MD_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  // the box rounded once to float32, as the force path has it
+  const float L[3] = {(float)p->box[0], (float)p->box[1], (float)p->box[2]};
+  const float dt = (float)dt_fs, h = (float)(0.5 * dt_fs);
+  double* kpart = (double*)((char*)d_ws + pl.off_kpart);
+  for (int32_t k = 0; k < n_steps; ++k) {
+    if (md::launch_vv_kick_drift(n_atoms, d_pos, d_vel, d_force, d_inv_mass, h, dt, L, st) !=
+        hipSuccess)
+      return MD_ERR_HIP;
+    s = md::forces_impl<float>(p, n_atoms, d_pos, d_type, d_charge, d_force, d_energies + 2 * k,
+                               d_ws, ws_bytes, stream);
+    if (s != MD_OK) return s;
+    if (md::launch_vv_kick(n_atoms, d_vel, d_force, d_inv_mass, h, kpart, d_energies + 2 * k + 1,
+                           st) != hipSuccess)
+      return MD_ERR_HIP;
+  }
+  return MD_OK;
 }
 
 md_status md_forces_batched(const md_system* sys, int32_t n_sys, void* stream) {

@@ -52,7 +52,7 @@ struct Plan {
   // byte offsets
   size_t off_count, off_start, off_cell, off_rank, off_unsorted, off_pos, off_type, off_perm,
       off_part, off_facc, off_epart, off_lj, off_paircount, off_bhist, off_bstat, off_order,
-      off_zsplit, off_ukey, off_upos, total;
+      off_zsplit, off_ukey, off_upos, off_kpart, total;
   int bin_blocks;               // blocks of the LDS-histogram binning pass (0: global atomics)
   int64_t bin_chunk;            // atoms per such block
 };
@@ -153,5 +153,15 @@ hipError_t launch_pair_fs(const SysArgs<float>& a, hipStream_t stream);
 hipError_t launch_binning_batch(const Batch<float>& b, const TypeTable& tt, hipStream_t stream);
 hipError_t launch_pair_fs_batch(const Batch<float>& b, hipStream_t stream);
 hipError_t launch_finalize_batch(const Batch<float>& b, hipStream_t stream);
+
+// Velocity-Verlet kernels of md_run_vv_f32 (md_integrate.hip). kick_drift: v += h F/m,
+// x += dt v wrapped into [0, L). kick: v += h F/m, and the kinetic energy, from per-block
+// partials in kpart ([ke_blocks(n)] doubles) summed in a fixed order into *ke.
+int64_t ke_blocks(int64_t n);
+hipError_t launch_vv_kick_drift(int64_t n, float* pos, float* vel, const float* force,
+                                const float* inv_mass, float h, float dt, const float* L,
+                                hipStream_t stream);
+hipError_t launch_vv_kick(int64_t n, float* vel, const float* force, const float* inv_mass,
+                          float h, double* kpart, double* ke, hipStream_t stream);
 
 }  // namespace md

@@ -181,3 +181,51 @@ def serving_trace(n_req: int = 512, rate_hz: float = 200.0, n_min: int = 2000,
 def request_system(req: Request, table, density: float = SERVING_DENSITY) -> System:
     L = cube_for(req.n, density)
     return gen_system(req.n, (L, L, L), req.seed, type_table=table)
+
+
+# Masses (amu) of the 8 synthetic atom types for the motion update: H, C, N, O, P, S, Na,
+# Cl -- an input table, like sigma and epsilon.
+TYPE_MASS = np.array([1.008, 12.011, 14.007, 15.999, 30.974, 32.06, 22.990, 35.45])
+SEED_VELOCITIES = 7
+
+
+def velocities(types, masses=TYPE_MASS, scale=0.005, seed=SEED_VELOCITIES):
+    """Seeded initial velocities (A/fs): each component normal with standard deviation
+    scale * sqrt(12 / m) for an atom of mass m (about 300 K for scale 0.005), total
+    momentum removed. Returns (float32 [n,3] velocities, float32 [n] inverse masses)."""
+    rng = np.random.default_rng(seed)
+    m = np.asarray(masses, dtype=np.float64)[np.asarray(types)]
+    v = rng.normal(0.0, 1.0, (m.shape[0], 3)) * (scale * np.sqrt(12.0 / m))[:, None]
+    v -= (m[:, None] * v).sum(axis=0) / m.sum()
+    return v.astype(np.float32), (1.0 / m).astype(np.float32)
+
+
+SEED_LIQUID = 9
+
+
+def liquid_system(n: int, box, seed=SEED_LIQUID, n_types: int = N_TYPES) -> System:
+    """Input for the motion update: a jittered lattice of n atoms in the box (the same
+    lattice rule as gen_system, jitter 0.1 A), with LJ sigma 1.8-2.0 A so that lattice
+    neighbours (about 2.1 A apart at 0.1 atoms/A^3) sit near the LJ minimum, epsilon
+    0.05-0.2 kcal/mol and charges N(0, 0.2) e, neutral in total: a system whose dynamics
+    stays bounded, unlike the force benchmark's (sigma up to 4 A at the same spacing)."""
+    rng = np.random.default_rng(seed)
+    sigma = rng.uniform(1.8, 2.0, n_types)
+    epsilon = rng.uniform(0.05, 0.2, n_types)
+    base = gen_system(n, box, seed, n_types, type_table=(sigma, epsilon))
+    L = base.box
+    a0 = (float(np.prod(L)) / n) ** (1.0 / 3.0)
+    # redraw the jitter at 0.1 A around the same lattice sites
+    nd = np.array([int(math.ceil(L[d] / a0)) for d in range(3)], dtype=np.int64)
+    sp = L / nd
+    site = np.floor(base.pos.astype(np.float64) / sp)   # each atom's lattice site (jitter < s/2)
+    x = (site + 0.5) * sp + rng.uniform(-0.1, 0.1, (n, 3))
+    pos = np.mod(x, L).astype(np.float32)
+    L32 = L.astype(np.float32)
+    for d in range(3):
+        col = pos[:, d]
+        col[col >= L32[d]] = np.float32(0.0)
+    q = rng.normal(0.0, 0.2, n)
+    q -= q.mean()
+    return System(pos=pos, types=base.types, charges=q.astype(np.float32), box=L, sigma=sigma,
+                  epsilon=epsilon, seed=seed)
