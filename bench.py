@@ -31,6 +31,7 @@ import numpy as np
 PEAK_FP32_TFLOPS = 157.3       # MI355X published float32 vector peak
 FLOP_PER_CANDIDATE = 8         # filter: 3 sub, 1 mul, 2 fma (fma = 2)
 FLOP_PER_PAIR = 40             # force, switch, accumulation
+BIN_BYTES_PER_ATOM = 20 + 24 + 24
 METRIC = "within-cutoff pair-interactions/s @92k atoms; p50/p99 latency mixed batch"
 # HBM bytes per launch of the pair kernel at 92,224 atoms, from the FETCH_SIZE and
 # WRITE_SIZE counters scaled by a copy of known size (profiles/traffic_pair_fs_92k.md);
@@ -350,20 +351,28 @@ def scaling(n_eval, dev):
         xs.append(torch.as_tensor(x))
     for _ in range(2):
         api.forces(P, pos, typ, q, force=force, energy=energy, workspace=ws)
-    ms = []
+    ms, bin_ms = [], []
     for k in range(n_eval):
         pos.copy_(xs[k])
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        api.forces(P, pos, typ, q, force=force, energy=energy, workspace=ws)
-        b.record(stream)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record(stream)
+        api.forces_stages(P, pos, typ, q, force, energy, ws, api.STAGE_BIN)
+        ev[1].record(stream)
+        api.forces_stages(P, pos, typ, q, force, energy, ws, api.STAGE_PAIR | api.STAGE_FINALIZE)
+        ev[2].record(stream)
         torch.cuda.synchronize()
-        ms.append(a.elapsed_time(b))
+        ms.append(ev[0].elapsed_time(ev[2]))
+        bin_ms.append(ev[0].elapsed_time(ev[1]))
     if api.read_status(ws) != 0:
         raise SystemExit(f"device status {api.read_status(ws):#x} (1M-atom system)")
     med = pct(ms, 50)
     flop = FLOP_PER_CANDIDATE * n_cand + FLOP_PER_PAIR * n_pairs
+    bmed = pct(bin_ms, 50)
     return {"n_atoms": s.n, "evaluations": n_eval, "eval_ms_median": med,
+            "bin_ms_median": bmed,
+            # algorithmic binning bytes: read x, y, z, q, type (20 B), write the sorted
+            # float4, type and permutation (24 B), clear the per-atom int64 sums (24 B)
+            "bin_GBps_algorithmic": BIN_BYTES_PER_ATOM * s.n / (bmed * 1e-3) / 1e9,
             "eval_ms_p10": pct(ms, 10), "eval_ms_p90": pct(ms, 90),
             "pairs_first_eval": n_pairs, "candidates_first_eval": n_cand,
             "pairs_per_s": n_pairs / (med * 1e-3),
@@ -445,9 +454,21 @@ def ablation(steps, dev):
 
 
 def cpu_baseline(s, budget_s):
-    """The FP64 oracle's cell-list evaluation (Algorithm 1) on this host's cores."""
+    """The FP64 oracle's cell-list evaluation (Algorithm 1) on this host's cores, timed over
+    whole evaluations for about budget_s; then one evaluation on one thread (the paper's
+    1-core vs 12-core comparison, Table 2) and one of the 1,066,628-atom cube on all."""
     import oracle
+    from paper_1611_04474_amd import workloads as W
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     oracle.lib()
     runs = 0
     n_pairs = None
@@ -459,10 +480,22 @@ def cpu_baseline(s, budget_s):
         if time.perf_counter() - t0 >= budget_s:
             break
     el = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    oracle.forces(s.params(), s.pos, s.types, s.charges, "celllist", n_threads=1)
+    one = time.perf_counter() - t1
+    big = W.stmv_system()
+    t2 = time.perf_counter()
+    rb = oracle.forces(big.params(), big.pos, big.types, big.charges, "celllist", n_threads=threads)
+    el_big = time.perf_counter() - t2
     return {"value": n_pairs * runs / el, "unit": "pair-interactions/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{runs} full FP64 cell-list evaluations of the {s.n}-atom system "
-                      f"in {el:.1f} s", "n_pairs": n_pairs}
+                      f"in {el:.1f} s", "n_pairs": n_pairs,
+            "cpu_model": model, "nproc": os.cpu_count(),
+            "one_thread_pairs_per_s": n_pairs / one,
+            "stmv_1m_pairs_per_s": rb.n_pairs / el_big,
+            "stmv_1m_sample": f"1 evaluation of the {big.n}-atom cube on {threads} threads "
+                              f"in {el_big:.1f} s"}
 
 
 if __name__ == "__main__":
