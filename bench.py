@@ -35,9 +35,9 @@ BIN_BYTES_PER_ATOM = 20 + 24 + 24
 METRIC = "within-cutoff pair-interactions/s @92k atoms; p50/p99 latency mixed batch"
 # HBM bytes per launch of the pair kernel at 92,224 atoms, from the FETCH_SIZE and
 # WRITE_SIZE counters scaled by a copy of known size (profiles/traffic_pair_fs_92k.md);
-# valid only for the kernel source they were taken on
-PAIR_TRAFFIC = {"kernel_sha256": "a3d4a26585d361f9a68d8178a9fc8afe0c30684ca278224682308436c0e06bcf",
-                "bytes": (17867 + 35430) * 1024}
+# valid only for the kernel code they were taken on (kernel_code_sha256)
+PAIR_TRAFFIC = {"kernel_sha256": "81352e649874b036d218f29e7b4c3ede647977c119721f8c83a20db8c340cbf9",
+                "bytes": (17850 + 35431) * 1024}
 
 
 def parse():
@@ -72,17 +72,28 @@ def parse():
     return ap.parse_args()
 
 
-def pair_traffic(args):
-    """Counter-measured HBM bytes per pair-kernel launch, or None when the kernel source
-    or the configuration differs from the one they were taken on."""
+def kernel_code_sha256(path):
+    """sha256 of a source file's code: comments removed and whitespace runs collapsed, so
+    that counters stay tied to the code they were taken on and not to its comments."""
     import hashlib
+    import re
+    with open(path) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    text = " ".join(text.split())
+    return hashlib.sha256(text.encode()).hexdigest()
+
+
+def pair_traffic(args):
+    """Counter-measured HBM bytes per pair-kernel launch, or None when the kernel code
+    or the configuration differs from the one they were taken on."""
     if args.workload != "apoa1" or args.mode != "compact" or args.accum != "fixed64":
         return None
     src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1611_04474_amd",
                        "csrc", "md_pair_fs.hip")
-    with open(src, "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != PAIR_TRAFFIC["kernel_sha256"]:
-            return None
+    if kernel_code_sha256(src) != PAIR_TRAFFIC["kernel_sha256"]:
+        return None
     return PAIR_TRAFFIC["bytes"]
 
 

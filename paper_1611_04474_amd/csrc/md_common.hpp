@@ -10,10 +10,10 @@
 namespace md {
 
 constexpr int kMaxTypes = 64;
-constexpr int kTasksPerCell = 14;    // home cell + 13 forward neighbours (half shell)
+constexpr int kTasksPerCell = 14;    // predicated kernel: home cell + 13 forward neighbours
 constexpr int kSlots = 27;           // partial-force slots per atom: 14 as home, 13 as neighbour
 constexpr int kTile = 256;           // atoms of one cell staged in LDS at a time
-constexpr int kPairThreads = 256;    // threads of one half-shell pair workgroup (4 waves)
+constexpr int kPairThreads = 256;    // threads of one predicated pair workgroup (4 waves)
 constexpr int kFsSplit = 1;          // compacted-kernel workgroups per home cell
 constexpr int64_t kMaxCells = 1 << 24;
 constexpr int64_t kMaxAtoms = (int64_t)1 << 30;

@@ -21,7 +21,7 @@
 // candidate fails idle through the force arithmetic -- the conditional data flow that
 // leaves the force unit of the HLS design underused (Section 5.1). It serves the
 // float64 path (bit-for-bit the oracle's predicate) and, in float32, the
-// MD_PAIR_PREDICATED comparison with the compacted full-shell kernel.
+// MD_PAIR_PREDICATED comparison with the compacted kernel.
 #include "md_common.hpp"
 
 namespace md {

@@ -6,8 +6,9 @@
 //
 // One workgroup (16 waves) takes one home cell. It stages the atoms of its neighbour-
 // cell images in LDS, periodic images shifted exactly (the side lying in the
-// last cell of an axis subtracts L, which is Sterbenz-exact). Cells are sorted by x, so
-// the images of one (dy, dz) row, laid out in x order, form one x-sorted "segment".
+// last cell of an axis subtracts L, which is Sterbenz-exact). Each z half of a cell is
+// sorted by x, so one z half of the images of one (dy, dz) row, laid out in x order,
+// forms one x-sorted "segment".
 // Each wave takes groups of kQ home atoms (consecutive in x) and, per segment, only the
 // slice whose x lies within r_cut of the group, found by a binary search (one lane
 // per segment):
@@ -20,10 +21,11 @@
 //              every lane busy (the "force PE"): the exact distance, the strict test
 //              u < rc^2, and the force summed on the home atom in registers.
 // Each home atom is owned by one wave and its sum runs in a fixed order: the 64 lane
-// partials are added per 16-lane row in a fixed DPP order and the four row sums in
-// 64-bit fixed point (2^-32 kcal/mol/A), exactly; lane energies are summed in 64-bit
-// fixed point (2^-24 kcal/mol), so the energy does not depend on how groups of home
-// atoms were spread over the waves either.
+// partials are added in one fixed order (wave halves and rows exchanging partial sums,
+// then a DPP butterfly within a row) and the total converted exactly to 64-bit fixed
+// point (2^-32 kcal/mol/A); lane energies are summed in 64-bit fixed point
+// (2^-24 kcal/mol), so the energy does not depend on how groups of home atoms were
+// spread over the waves either.
 //
 // Two shells:
 //   full (kHalf = false) -- every pair is evaluated from both of its atoms, as in
@@ -48,9 +50,9 @@ constexpr int kThreads = 64 * kNW;
 constexpr int kQ = 4;               // home atoms filtered together by one wave, one FIFO each
 static_assert(kQ % 4 == 0, "FIFO appends are written four home atoms at a time");
 static_assert(kNW % 4 == 0 && kNW * 64 <= 1024, "waves per workgroup");
-// Force batches of 64 drained together from a full FIFO (kD, a template parameter: 2 by
-// default, 1 to 4 for the drain-depth sweep); a FIFO holds 64 (kD + 1) uint16 neighbour
-// indices.
+// Force batches of 64 drained together from a full FIFO (kDrain, a template parameter of
+// the kernel: 2 by default, 1 to 4 for the drain-depth sweep); a FIFO holds
+// 64 (kDrain + 1) uint16 neighbour indices.
 constexpr int kDrainDefault = 2;
 __host__ __device__ constexpr int fifo_entries(int drain) { return 64 * (drain + 1); }
 constexpr int kMaxSeg = 36;         // 9 (dy, dz) rows x 2 z halves, each split at most once by
@@ -278,9 +280,10 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
   const int nA = a.start[cellA + 1] - sA;
 
   // image table and segments (wave 0; lane l < 2 kImg = half l & 1 of image l >> 1).
-  // Pieces are ordered by (group, dz, dy, z half, dx): the pieces of one (dy, dz) row, one
-  // z half and one group form a segment, sorted in x because each half of a cell is and
-  // the cells follow each other in x. The half shell puts the home image's two halves
+  // Pieces are ordered by (shift class, dz, dy, z half, dx), the shift class being the set
+  // of axes along which the image lies at +L (grp): the pieces of one (dy, dz) row, one
+  // z half and one shift class form a segment, sorted in x because each half of a cell is
+  // and the cells follow each other in x. The half shell puts the home image's two halves
   // first, as segments of their own: its neighbour-list positions 0 .. nA-1 are then the
   // home atoms in their sorted order, which the j > i rule compares.
   if (tid < 64) {
@@ -533,9 +536,6 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
       auto fill = [&](int k) __attribute__((always_inline)) {
         return (int)((fb[k] - fk0) >> 1) - k * kFifo;
       };
-      // dense force passes over the first c entries of FIFO k (c <= 64 * kDrain): the exact
-      // distance in the current frame, the strict cutoff (u > 0 drops the home atom
-      // itself) and the force. All LDS reads of the kDrain batches precede the arithmetic.
       // the force on home atom k from one lane's FIFO entry j: the exact distance in the
       // current frame, the strict cutoff (u > 0 drops the home atom itself) and the force;
       // `in` is false for lanes past the FIFO's fill level. The half shell adds -F to
