@@ -126,3 +126,26 @@ def test_batched_rejects_before_enqueue():
     with pytest.raises(api.MDError) as e:
         api.forces_batched([sys_ok], stream=0)
     assert e.value.code == -3
+
+
+def test_motion_update_argument_errors_are_synchronous():
+    import ctypes as C
+    base = W.small_system().params()
+    P = api.Params.from_dict(base)
+    need = api.workspace_bytes(base, 10)
+    L = api.lib()
+
+    def call(n=10, vel=4096, inv_m=4096, dt=0.5, steps=3, ws_bytes=need, energies=4096, p=P):
+        return L.md_run_vv_f32(p.ref(), n, C.c_void_p(4096), C.c_void_p(vel), C.c_void_p(4096),
+                               C.c_void_p(4096), C.c_void_p(inv_m), C.c_void_p(4096), float(dt),
+                               int(steps), C.c_void_p(energies), C.c_void_p(256), ws_bytes, None)
+
+    assert call(steps=-1) == -1
+    assert call(dt=float("nan")) == -1
+    assert call(dt=float("inf")) == -1
+    assert call(vel=0) == -1
+    assert call(inv_m=0) == -1
+    assert call(inv_m=4098) == -1          # misaligned
+    assert call(energies=4100) == -1       # an FP64 array needs 8-byte alignment
+    assert call(ws_bytes=need - 1) == -3
+    assert call(p=api.Params.from_dict(dict(base, r_switch=13.0))) == -1

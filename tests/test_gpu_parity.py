@@ -259,6 +259,46 @@ def test_compact_multi_pass(gpu, flags):
     _check_fp32(p, pos, t, q, f, e, cnt)
 
 
+def test_cell_beyond_one_sort_chunk(gpu):
+    """1,200 atoms in one cell of a 3x3x3 grid: the in-cell sort ranks them over several
+    LDS chunks of keys (a cell of at most 1,024 atoms takes one), and the pair kernels
+    take a home cell of that size, in both shells and in float64."""
+    _say("case: 1,200 atoms in one cell + 300 elsewhere, 37 A box")
+    import torch
+    rng = np.random.default_rng(21)
+    g = np.arange(11) * 1.1 + 0.3
+    lat = np.array([[x, y, z] for x in g for y in g for z in g])[:1200]
+    rest = rng.uniform(13.0, 36.5, (300, 3))
+    pos = np.vstack([lat, rest]).astype(np.float32).astype(np.float64)
+    n = len(pos)
+    t = rng.integers(0, 2, n).astype(np.int32)
+    q = rng.normal(0, 0.2, n)
+    p = dict(box=(37.0, 37.0, 37.0), r_cut=12.0, r_switch=10.0, coulomb_k=W.COULOMB_K,
+             sigma=np.array([0.8, 0.9]), epsilon=np.array([0.05, 0.1]), flags=0)
+    f, e, ws, cnt = run(p, pos, t, q, gpu, flags=api.DIAG_COUNTERS)
+    _check_fp32(p, pos, t, q, f, e, cnt)
+    lay = api.workspace_layout(p, n)
+    start = ws[lay["cell_start"]: lay["cell_start"] + 4 * (lay["n_cells"] + 1)].view(torch.int32).cpu().numpy()
+    perm = ws[lay["perm"]: lay["perm"] + 4 * n].view(torch.int32).cpu().numpy()
+    big = int(np.argmax(np.diff(start)))
+    seg = perm[start[big]:start[big + 1]]
+    assert len(seg) >= 1200
+    pos64, _ = oracle.canonicalize(pos.astype(np.float32), np.asarray(p["box"]))
+    dims = lay["dims"]
+    cz = big // (dims[0] * dims[1])
+    inv_wz = np.float32(dims[2] / float(np.float32(37.0)))
+    half = ((pos64[seg, 2].astype(np.float32) * inv_wz * np.float32(2)).astype(np.int64) >= 2 * cz + 1)
+    key = list(zip(half.astype(int), pos64[seg, 0], seg))
+    assert key == sorted(key)
+    f2, e2, _, cnt2 = run(p, pos, t, q, gpu, flags=api.PAIR_FULL_SHELL | api.DIAG_COUNTERS)
+    _check_fp32(p, pos, t, q, f2, e2, cnt2)
+    f64, e64, _, cnt64 = run(p, pos, t, q, gpu, double=True, flags=api.DIAG_COUNTERS)
+    r = _ref(p, pos, t, q)
+    err = force_errors(f64, r.force, r.abs_sum)
+    assert err["max_norm"] <= 1e-12 and e64 == pytest.approx(r.energy, rel=1e-12)
+    assert np.array_equal(cnt64, r.count)
+
+
 def test_global_atomic_binning_path(gpu):
     """A 400 A box has 33^3 cells, more than the per-block LDS histogram holds, so the
     binning takes the global-atomic path; atoms sit in dense blobs, one across the
