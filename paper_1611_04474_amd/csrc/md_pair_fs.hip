@@ -61,6 +61,9 @@ constexpr int kLdsBytes = 160 * 1024;
 constexpr float kMargin = 0.05f;    // A^2 added to rc^2 by the expanded-form prefilter
 constexpr float kWin = 1.0e-3f;     // A added to r_cut for the x-window
 constexpr float kBigU = 1.0e30f;    // squared distance given to lanes that must add nothing
+// largest partial force component (kcal/mol/A) the half shell adds into a per-atom sum:
+// 15 partials of at most 2^27 stay inside the 2^31 range of the 64-bit fixed point
+constexpr float kHalfPartialMax = 134217728.f;
 static_assert(kMaxTypes <= 64, "a type must fit the low 6 bits of a staged c_j");
 
 // The 27 neighbour images.
@@ -745,6 +748,10 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
               float* dst = &a.facc[(int64_t)c * a.n + s];
               *dst = P0 == 0 ? r3[c] : *dst + r3[c];
             } else {
+              // the half shell's per-atom sum gathers up to 15 partials (this one, the home
+              // cell's neighbour-side sum, 13 flushes of other workgroups): each stays below
+              // 2^27 kcal/mol/A, so their sum cannot leave the 2^31 range of the fixed point
+              if (kHalf && !(fabsf(r3[c]) < kHalfPartialMax)) st |= MD_STATUS_FIXED_OVERFLOW;
               const long long qv = to_fixed(r3[c], st);
               long long* dst = &a.acc64[(int64_t)c * a.n + s];
               if (kHalf)
@@ -787,9 +794,10 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
           const int64_t src = im.start + e;
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            // units of 2^-24 to the sums' 2^-32; beyond 2^55 the sum would not fit them
+            // units of 2^-24 to the sums' 2^-32, each partial below 2^27 kcal/mol/A (2^51
+            // units), as the home side's
             const long long v = sJ[3 * (dst - P0) + c];
-            if (v >= (1ll << 55) || v < -(1ll << 55)) st |= MD_STATUS_FIXED_OVERFLOW;
+            if (v >= (1ll << 51) || v < -(1ll << 51)) st |= MD_STATUS_FIXED_OVERFLOW;
             else if (v != 0)
               global_add(&a.acc64[(int64_t)c * a.n + src],
                          (long long)((unsigned long long)v << 8));

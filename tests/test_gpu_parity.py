@@ -366,6 +366,11 @@ def test_wrapping_and_status_bits(gpu):
     bt = s.types.copy(); bt[3] = 99
     _, _, ws, _ = run(p, s.pos, bt, s.charges, gpu)
     assert api.read_status(ws) & api.STATUS_BAD_TYPE
+    # two atoms 0.02 A apart: a pair force far beyond the fixed-point range, in either shell
+    close = s.pos.copy(); close[11] = close[10] + np.float32(0.02)
+    for flags in (0, api.PAIR_FULL_SHELL):
+        _, _, ws, _ = run(p, close, s.types, s.charges, gpu, flags=flags)
+        assert api.read_status(ws) & api.STATUS_FIXED_OVERFLOW, flags
     # a clean call on the same workspace clears the sticky word
     run(p, s.pos, s.types, s.charges, gpu, ws=ws)
     assert api.read_status(ws) == 0
