@@ -84,8 +84,7 @@ md_status make_plan(const md_params* p, int64_t n, int real_bytes, Plan* pl) {
   pl->bin_chunk = 0;
   if (n > 0 && cells <= kBinLdsCells) {
     int64_t chunk = (n + kBinMaxBlocks - 1) / kBinMaxBlocks;
-    chunk = (chunk + 1023) / 1024 * 1024;
-    if (chunk < kBinMinChunk) chunk = kBinMinChunk;
+    chunk = (chunk + kBinChunkUnit - 1) / kBinChunkUnit * kBinChunkUnit;
     pl->bin_chunk = chunk;
     pl->bin_blocks = (int)((n + chunk - 1) / chunk);
   }

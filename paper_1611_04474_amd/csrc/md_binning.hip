@@ -11,7 +11,9 @@
 //                return value is the atom's slot among the block's atoms of that cell);
 //                the histogram and the block's status bits go to the workspace, so no
 //                global atomics are needed;
-//   k_bin_scan   one workgroup: per cell, exclusive offsets of the blocks and the total;
+//   k_bin_colscan (grids of more than 1024 cells) per cell, exclusive offsets of the
+//                blocks and the total, one workgroup per 64 cells;
+//   k_bin_scan   one workgroup: (smaller grids) the same per-cell offsets and totals;
 //                exclusive scan of the totals -> cell_start; the cells ordered by
 //                decreasing atom count (the pair kernel starts the largest home cells
 //                first, so the last workgroups to run are short ones); the mixed
@@ -52,17 +54,24 @@ __device__ inline int cell_coord(Real x, Real inv_w, int n) {
   return c > n - 1 ? n - 1 : c;
 }
 
+// Cell of an atom from its raw coordinates and type (which are checked).
 template <typename Real>
-__device__ inline int cell_of(const SysArgs<Real>& a, int64_t i, uint32_t& st) {
-  const Real x = wrap_coord(a.pos_in[3 * i + 0], a.L[0], st);
-  const Real y = wrap_coord(a.pos_in[3 * i + 1], a.L[1], st);
-  const Real z = wrap_coord(a.pos_in[3 * i + 2], a.L[2], st);
-  const int t = a.type_in[i];
+__device__ inline int cell_from(const SysArgs<Real>& a, Real x0, Real y0, Real z0, int t,
+                                uint32_t& st) {
+  const Real x = wrap_coord(x0, a.L[0], st);
+  const Real y = wrap_coord(y0, a.L[1], st);
+  const Real z = wrap_coord(z0, a.L[2], st);
   if (t < 0 || t >= a.n_types) st |= MD_STATUS_BAD_TYPE;
   const int cx = cell_coord(x, a.inv_w[0], a.nx);
   const int cy = cell_coord(y, a.inv_w[1], a.ny);
   const int cz = cell_coord(z, a.inv_w[2], a.nz);
   return (cz * a.ny + cy) * a.nx + cx;
+}
+
+template <typename Real>
+__device__ inline int cell_of(const SysArgs<Real>& a, int64_t i, uint32_t& st) {
+  return cell_from(a, a.pos_in[3 * i + 0], a.pos_in[3 * i + 1], a.pos_in[3 * i + 2],
+                   a.type_in[i], st);
 }
 
 // Clears the per-atom accumulators that the pair kernels add into.
@@ -81,33 +90,60 @@ __device__ inline void clear_atom(const SysArgs<Real>& a, int64_t i) {
   if (a.flags & MD_DIAG_COUNTERS) a.paircount[a.n + i] = 0;
 }
 
+// kBinThreads threads per block; a block's atoms are taken kHistPer per thread at a time,
+// all their loads issued before any of them is binned (the chunk is a multiple of
+// kBinThreads kHistPer atoms).
+constexpr int kHistPer = kBinChunkUnit / kBinThreads;
+
 template <typename Real>
 __device__ inline void bin_hist(const SysArgs<Real>& a, int64_t blk) {
   extern __shared__ int32_t s_h[];   // [n_cells] counts, then the status bits
   const int nc = (int)a.n_cells;
   const int tid = threadIdx.x;
-  for (int c = tid; c <= nc; c += 1024) s_h[c] = 0;
+  for (int c = tid; c <= nc; c += kBinThreads) s_h[c] = 0;
   __syncthreads();
   const int64_t i0 = blk * a.bin_chunk;
   const int64_t i1 = i0 + a.bin_chunk < a.n ? i0 + a.bin_chunk : a.n;
   uint32_t st = 0;
-  for (int64_t i = i0 + tid; i < i1; i += 1024) {
-    const int c = cell_of(a, i, st);
-    a.cell[i] = c;
-    a.rank[i] = atomicAdd(&s_h[c], 1);
-    clear_atom(a, i);
+  for (int64_t r0 = i0; r0 < i1; r0 += kBinThreads * kHistPer) {
+    Real x[kHistPer], y[kHistPer], z[kHistPer];
+    int ty[kHistPer], c[kHistPer];
+#pragma unroll
+    for (int u = 0; u < kHistPer; ++u) {
+      // past the end: a repeat of the block's last atom, whose cell and status bits are
+      // already its own (nothing is stored for it)
+      int64_t i = r0 + u * kBinThreads + tid;
+      i = i < i1 ? i : i1 - 1;
+      x[u] = a.pos_in[3 * i + 0];
+      y[u] = a.pos_in[3 * i + 1];
+      z[u] = a.pos_in[3 * i + 2];
+      ty[u] = a.type_in[i];
+    }
+#pragma unroll
+    for (int u = 0; u < kHistPer; ++u) c[u] = cell_from(a, x[u], y[u], z[u], ty[u], st);
+#pragma unroll
+    for (int u = 0; u < kHistPer; ++u) {
+      const int64_t i = r0 + u * kBinThreads + tid;
+      if (i < i1) {
+        a.cell[i] = c[u];
+        a.rank[i] = atomicAdd(&s_h[c[u]], 1);
+        clear_atom(a, i);
+      }
+    }
   }
   if (st) atomicOr(reinterpret_cast<uint32_t*>(&s_h[nc]), st);
   __syncthreads();
   int32_t* hb = a.bhist + blk * nc;
-  for (int c = tid; c < nc; c += 1024) hb[c] = s_h[c];
+  for (int c = tid; c < nc; c += kBinThreads) hb[c] = s_h[c];
   if (tid == 0) a.bstat[blk] = (uint32_t)s_h[nc];
 }
 
 template <typename Real>
-__global__ __launch_bounds__(1024) void k_bin_hist(SysArgs<Real> a) { bin_hist(a, blockIdx.x); }
+__global__ __launch_bounds__(kBinThreads) void k_bin_hist(SysArgs<Real> a) {
+  bin_hist(a, blockIdx.x);
+}
 
-__global__ __launch_bounds__(1024) void k_bin_hist_batch(Batch<float> b) {
+__global__ __launch_bounds__(kBinThreads) void k_bin_hist_batch(Batch<float> b) {
   int64_t blk;
   const int s = b.pick(blockIdx.x, blk);
   bin_hist(b.sys[s], blk);
@@ -136,10 +172,6 @@ __global__ void k_bin_count(SysArgs<Real> a) {
   if (st) atomicOr(&a.hdr->status, st);
 }
 
-// One workgroup of 1024 threads. With per-block histograms: per cell, the blocks'
-// counts become exclusive offsets (in place) and their total the cell count. Then the
-// exclusive scan of the counts into start[] (start[n_cells] = n), in chunks of 4096
-// with a running carry, the mixed LJ table, and (own_header) the status word.
 // Exclusive prefix sum of one value per thread over a 1024-thread workgroup: a scan
 // within each wave, then the 16 wave totals through LDS. *total gets the sum of all.
 __device__ inline int32_t block_scan_excl(int32_t v, int32_t* s_tot, int32_t* total) {
@@ -164,63 +196,94 @@ __device__ inline int32_t block_scan_excl(int32_t v, int32_t* s_tot, int32_t* to
   return before + x - v;
 }
 
+// Grids of at most kScanFused cells binned with per-block histograms skip the scan
+// kernels: every block of k_scatter_fused scans the histograms itself (one thread per
+// cell). Larger grids go through k_bin_colscan, k_bin_scan and k_scatter.
+constexpr int kScanFused = 1024;
+
 template <typename Real>
-__device__ inline void bin_scan(const SysArgs<Real>& a, const TypeTable& tt, int own_header) {
-  __shared__ int32_t s_tot[16];
-  const int t = threadIdx.x;
+__host__ __device__ inline bool scan_fused(const SysArgs<Real>& a) {
+  return a.bin_blocks > 0 && a.n_cells <= kScanFused;
+}
+
+// Workgroups of k_bin_colscan for one system (0 when the scatter does the scan).
+template <typename Real>
+__host__ __device__ inline int64_t colscan_blocks(const SysArgs<Real>& a) {
+  return a.bin_blocks > 0 && !scan_fused(a) ? (a.n_cells + 63) / 64 : 0;
+}
+
+// Per-block histograms of large grids: workgroup blk (1024 threads) takes cells
+// 64 blk .. 64 blk + 63, one per lane. Wave w sums its share of the blocks' counts of the
+// lane's cell (up to 64 blocks, all loads in flight), the 16 wave sums are scanned through
+// LDS, and the counts become each block's exclusive offset within the cell (in place);
+// their total is the cell count.
+template <typename Real>
+__device__ inline void bin_colscan(const SysArgs<Real>& a, int64_t blk) {
+  static_assert(kBinMaxBlocks <= 16 * 64, "a wave sums at most 64 blocks");
+  __shared__ int32_t s_col[16][64];
+  const int t = threadIdx.x, lane = t & 63;
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);   // uniform: row addresses in SGPRs
   const int64_t nc = a.n_cells;
   const int B = a.bin_blocks;
-  if (B > 0) {
-    for (int64_t c = t; c < nc; c += 1024) {
-      int32_t acc = 0;
-      int b = 0;
-      for (; b + 8 <= B; b += 8) {   // eight independent loads in flight
-        int32_t v[8];
+  const int64_t c = blk * 64 + lane;
+  const bool cv = c < nc;
+  const int per = (B + 15) / 16;   // blocks per wave
+  const int b0 = w * per;
+  int32_t v[64];
+  int32_t sum = 0;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = a.bhist[(int64_t)(b + u) * nc + c];
+  for (int r = 0; r < 64; ++r) {
+    const int b = b0 + r;
+    v[r] = (r < per && b < B && cv) ? a.bhist[(int64_t)b * nc + c] : 0;
+    sum += v[r];
+  }
+  s_col[w][lane] = sum;
+  __syncthreads();
+  int32_t base = 0, tot = 0;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          a.bhist[(int64_t)(b + u) * nc + c] = acc;
-          acc += v[u];
-        }
-      }
-      for (; b < B; ++b) {
-        const int32_t v = a.bhist[(int64_t)b * nc + c];
-        a.bhist[(int64_t)b * nc + c] = acc;
-        acc += v;
-      }
-      a.count[c] = acc;
-    }
+  for (int k = 0; k < 16; ++k) {
+    const int32_t x = s_col[k][lane];
+    base += k < w ? x : 0;
+    tot += x;
   }
-  __syncthreads();   // the counts written above are read by other threads below
-  int32_t carry = 0;
-  for (int64_t base = 0; base < nc; base += 4096) {
-    int32_t v[4];
-    int32_t sum = 0;
-    for (int k = 0; k < 4; ++k) {
-      const int64_t idx = base + 4 * t + k;
-      v[k] = idx < nc ? a.count[idx] : 0;
-      sum += v[k];
-    }
-    int32_t chunk;
-    int32_t run = carry + block_scan_excl(sum, s_tot, &chunk);
-    for (int k = 0; k < 4; ++k) {
-      const int64_t idx = base + 4 * t + k;
-      if (idx < nc) a.start[idx] = run;
-      run += v[k];
-    }
-    carry += chunk;
+#pragma unroll
+  for (int r = 0; r < 64; ++r) {
+    const int b = b0 + r;
+    if (r < per && b < B && cv) a.bhist[(int64_t)b * nc + c] = base;
+    base += v[r];
   }
-  if (t == 0) a.start[nc] = carry;
-  // launch order of the pair kernel: counting sort of the cells by decreasing count
-  // (counts clamped to kOrderBins - 1); the order within a bin is arbitrary, which only
-  // changes which compute unit takes a cell, never a result
+  if (w == 0 && cv) a.count[c] = tot;
+}
+
+template <typename Real>
+__global__ __launch_bounds__(1024) void k_bin_colscan(SysArgs<Real> a) {
+  bin_colscan(a, blockIdx.x);
+}
+
+__global__ __launch_bounds__(1024) void k_bin_colscan_batch(Batch<float> b) {
+  int64_t blk;
+  const int s = b.pick(blockIdx.x, blk);
+  bin_colscan(b.sys[s], blk);
+}
+
+// The cells' launch order for the pair kernel, the mixed LJ table and (own_header) the
+// status word: the end of the scan, by one workgroup of 1024 threads; count(c) gives the
+// atom count of cell c, and st_lane (threads 0 .. 63) the histogram blocks' status bits
+// from block_status.
+template <typename Real, typename Count>
+__device__ inline void scan_tail(const SysArgs<Real>& a, const TypeTable& tt, int own_header,
+                                 int32_t* s_tot, Count count, uint32_t st_lane) {
+  const int t = threadIdx.x;
+  const int64_t nc = a.n_cells;
+  // counting sort of the cells by decreasing count (counts clamped to kOrderBins - 1); the
+  // order within a bin is arbitrary, which only changes which compute unit takes a cell,
+  // never a result
   constexpr int kOrderBins = 1024;
   __shared__ int32_t s_bin[kOrderBins];
   s_bin[t] = 0;
   __syncthreads();
   for (int64_t c = t; c < nc; c += 1024) {
-    const int32_t v = a.count[c];
+    const int32_t v = count(c);
     atomicAdd(&s_bin[kOrderBins - 1 - (v < kOrderBins - 1 ? v : kOrderBins - 1)], 1);
   }
   __syncthreads();
@@ -231,7 +294,7 @@ __device__ inline void bin_scan(const SysArgs<Real>& a, const TypeTable& tt, int
     __syncthreads();
   }
   for (int64_t c = t; c < nc; c += 1024) {
-    const int32_t v = a.count[c];
+    const int32_t v = count(c);
     const int32_t pos = atomicAdd(&s_bin[kOrderBins - 1 - (v < kOrderBins - 1 ? v : kOrderBins - 1)], 1);
     a.order[pos] = (int32_t)c;
   }
@@ -244,14 +307,91 @@ __device__ inline void bin_scan(const SysArgs<Real>& a, const TypeTable& tt, int
     a.lj[2 * e + 0] = (Real)(4.0 * ep * s6 * s6);
     a.lj[2 * e + 1] = (Real)(4.0 * ep * s6);
   }
-  static_assert(kBinMaxBlocks <= 64, "one block's status per lane of wave 0");
   if (own_header && t < 64) {
-    // the blocks' status bits, one block per lane of wave 0
-    uint32_t st = t < B ? a.bstat[t] : 0u;
+    uint32_t st = st_lane;
     for (int o = 32; o > 0; o >>= 1) st |= __shfl_xor(st, o);
     if (t == 0) a.hdr->status = st;
     if (t < 5) a.hdr->diag[t] = 0;
   }
+}
+
+// Status bits of the histogram blocks t, t + 64, ... (threads t < 64 of a workgroup),
+// loaded by block_status and combined by Status::bits where they are needed, so that the
+// loads overlap others.
+struct Status {
+  static_assert(kBinMaxBlocks <= 16 * 64, "16 loads per thread");
+  uint32_t v[16];
+  __device__ uint32_t bits() const {
+    uint32_t st = 0u;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) st |= v[k];
+    return st;
+  }
+};
+
+template <typename Real>
+__device__ inline Status block_status(const SysArgs<Real>& a, bool want) {
+  Status s;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int b = (int)threadIdx.x + 64 * k;
+    s.v[k] = want && threadIdx.x < 64 && b < a.bin_blocks ? a.bstat[b] : 0u;
+  }
+  return s;
+}
+
+// Cell counts of grids of at most kScanLds cells are kept in LDS by the scan kernel.
+constexpr int kScanLds = 8192;
+
+// One workgroup of 1024 threads (grids scanned by k_bin_colscan, or binned with global
+// atomics): the exclusive scan of the cell counts into start[] (start[n_cells] = n), in
+// chunks of 4096 with a running carry, then scan_tail. The counts are read into LDS first
+// when the grid has at most kScanLds cells.
+template <typename Real>
+__device__ inline void bin_scan(const SysArgs<Real>& a, const TypeTable& tt, int own_header) {
+  __shared__ int32_t s_tot[16];
+  __shared__ int32_t s_cnt[kScanLds];
+  const int t = threadIdx.x;
+  const int64_t nc = a.n_cells;
+  const bool in_lds = nc <= kScanLds;
+  const Status st_blocks = block_status(a, own_header != 0);
+  if (in_lds) {
+    for (int c0 = 0; c0 < nc; c0 += 8 * 1024) {
+      int32_t v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int c = c0 + 1024 * k + t;
+        v[k] = c < nc ? a.count[c] : 0;
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int c = c0 + 1024 * k + t;
+        if (c < nc) s_cnt[c] = v[k];
+      }
+    }
+  }
+  __syncthreads();   // the counts staged above are read by other threads below
+  auto count = [&](int64_t c) { return in_lds ? s_cnt[c] : a.count[c]; };
+  int32_t carry = 0;
+  for (int64_t base = 0; base < nc; base += 4096) {
+    int32_t v[4];
+    int32_t sum = 0;
+    for (int k = 0; k < 4; ++k) {
+      const int64_t idx = base + 4 * t + k;
+      v[k] = idx < nc ? count(idx) : 0;
+      sum += v[k];
+    }
+    int32_t chunk;
+    int32_t run = carry + block_scan_excl(sum, s_tot, &chunk);
+    for (int k = 0; k < 4; ++k) {
+      const int64_t idx = base + 4 * t + k;
+      if (idx < nc) a.start[idx] = run;
+      run += v[k];
+    }
+    carry += chunk;
+  }
+  if (t == 0) a.start[nc] = carry;
+  scan_tail(a, tt, own_header, s_tot, count, st_blocks.bits());
 }
 
 template <typename Real>
@@ -282,6 +422,24 @@ __device__ inline unsigned long long sort_key(const SysArgs<Real>& a, int32_t i,
          ((unsigned long long)__builtin_bit_cast(uint32_t, x + 0.f) << 31) | (uint32_t)i;
 }
 
+// Atom i (of cell c) goes to slot `slot` of the unsorted cell-major arrays: its sort key,
+// its wrapped (x, y, z, q) and its type.
+template <typename Real>
+__device__ inline void put_atom(const SysArgs<Real>& a, int64_t i, int c, int32_t slot, Real x,
+                                Real y, Real z, Real q, int t) {
+  const int cz = (int)(c / ((int64_t)a.nx * a.ny));
+  uint32_t st = 0;
+  P4<Real> p;
+  p.x = wrap_coord(x, a.L[0], st);
+  p.y = wrap_coord(y, a.L[1], st);
+  p.z = wrap_coord(z, a.L[2], st);
+  p.w = q;
+  if (t < 0 || t >= a.n_types) t = 0;
+  a.ukey[slot] = sort_key(a, (int32_t)i, (float)p.x, p.z, cz);
+  a.upos[slot] = p;
+  a.unsorted[slot] = t;
+}
+
 // Each atom goes to its cell's range (in arbitrary order) with its sort key, its wrapped
 // (x, y, z, q) and its type, read here in the caller's order (coalesced), so the in-cell
 // sort only touches its own cell's range.
@@ -292,18 +450,69 @@ __device__ inline void scatter(const SysArgs<Real>& a, int64_t blk) {
   const int c = a.cell[i];
   int32_t slot = a.start[c] + a.rank[i];
   if (a.bin_blocks > 0) slot += a.bhist[(i / a.bin_chunk) * a.n_cells + c];
-  const int cz = (int)(c / ((int64_t)a.nx * a.ny));
-  uint32_t st = 0;
-  P4<Real> p;
-  p.x = wrap_coord(a.pos_in[3 * i + 0], a.L[0], st);
-  p.y = wrap_coord(a.pos_in[3 * i + 1], a.L[1], st);
-  p.z = wrap_coord(a.pos_in[3 * i + 2], a.L[2], st);
-  p.w = a.q_in[i];
-  int t = a.type_in[i];
-  if (t < 0 || t >= a.n_types) t = 0;
-  a.ukey[slot] = sort_key(a, (int32_t)i, (float)p.x, p.z, cz);
-  a.upos[slot] = p;
-  a.unsorted[slot] = t;
+  put_atom(a, i, c, slot, a.pos_in[3 * i + 0], a.pos_in[3 * i + 1], a.pos_in[3 * i + 2],
+           a.q_in[i], a.type_in[i]);
+}
+
+// Grids of at most kScanFused cells with per-block histograms: block blk (1024 threads)
+// takes atoms 1024 blk .. 1024 blk + 1023, which lie in histogram block
+// hb = 1024 blk / bin_chunk. Thread c adds up the histogram blocks' counts of cell c, all
+// of them and those of the blocks before hb; the totals are scanned into the cells' starts
+// in LDS, and each atom goes to start[c] + (offset of block hb in cell c) + (its rank
+// within hb). Every block repeats this scan, which replaces a kernel of its own; block 0
+// also writes start[] and runs scan_tail. All loads are issued before the first is used.
+template <typename Real>
+__host__ __device__ inline int64_t fused_blocks(const SysArgs<Real>& a) {
+  return scan_fused(a) ? (a.n + 1023) / 1024 : 0;
+}
+
+template <typename Real>
+__device__ inline void scatter_fused(const SysArgs<Real>& a, const TypeTable& tt, int64_t blk) {
+  static_assert(kScanFused <= 1024, "one cell per thread");
+  static_assert(kBinChunkUnit % 1024 == 0, "a block's atoms lie in one histogram block");
+  __shared__ int32_t s_tot[16];
+  __shared__ int32_t s_start[kScanFused];
+  __shared__ int32_t s_off[kScanFused];
+  __shared__ int32_t s_cnt[kScanFused];
+  const int t = threadIdx.x;
+  const int nc = (int)a.n_cells;
+  const int B = a.bin_blocks;
+  const int64_t i = blk * 1024 + t;
+  const int64_t hb = blk * 1024 / a.bin_chunk;
+  // this thread's atom (a repeat of the last one past the end: nothing is stored for it)
+  const int64_t ic = i < a.n ? i : a.n - 1;
+  const int ci = a.cell[ic], rk = a.rank[ic];
+  const Real x = a.pos_in[3 * ic + 0], y = a.pos_in[3 * ic + 1], z = a.pos_in[3 * ic + 2];
+  const Real q = a.q_in[ic];
+  const int ty = a.type_in[ic];
+  const Status st_blocks = block_status(a, blk == 0);
+  int32_t tot = 0, off = 0;
+  if (t < nc) {
+    for (int b0 = 0; b0 < B; b0 += 64) {
+      int32_t v[64];
+#pragma unroll
+      for (int r = 0; r < 64; ++r) v[r] = b0 + r < B ? a.bhist[(int64_t)(b0 + r) * nc + t] : 0;
+#pragma unroll
+      for (int r = 0; r < 64; ++r) {
+        tot += v[r];
+        off += b0 + r < hb ? v[r] : 0;
+      }
+    }
+  }
+  int32_t all;
+  const int32_t start_c = block_scan_excl(tot, s_tot, &all);
+  if (t < nc) {
+    s_start[t] = start_c;
+    s_off[t] = off;
+    s_cnt[t] = tot;
+  }
+  __syncthreads();
+  if (i < a.n) put_atom(a, i, ci, s_start[ci] + s_off[ci] + rk, x, y, z, q, ty);
+  if (blk == 0) {
+    if (t < nc) a.start[t] = start_c;
+    if (t == 0) a.start[nc] = all;
+    scan_tail(a, tt, 1, s_tot, [&](int64_t cc) { return s_cnt[cc]; }, st_blocks.bits());
+  }
 }
 
 template <typename Real>
@@ -313,6 +522,17 @@ __global__ __launch_bounds__(256) void k_scatter_batch(Batch<float> b) {
   int64_t blk;
   const int s = b.pick(blockIdx.x, blk);
   scatter(b.sys[s], blk);
+}
+
+template <typename Real>
+__global__ __launch_bounds__(1024) void k_scatter_fused(SysArgs<Real> a, TypeTable tt) {
+  scatter_fused(a, tt, blockIdx.x);
+}
+
+__global__ __launch_bounds__(1024) void k_scatter_fused_batch(Batch<float> b, TypeTable tt) {
+  int64_t blk;
+  const int s = b.pick(blockIdx.x, blk);
+  scatter_fused(b.sys[s], tt, blk);
 }
 
 // One workgroup per cell. Each member's position in the cell is the number of members
@@ -452,7 +672,7 @@ hipError_t launch_binning(const SysArgs<Real>& a, const TypeTable& tt, hipStream
   int own_header = 1;
   if (a.n > 0 && a.bin_blocks > 0) {
     const size_t shmem = sizeof(int32_t) * (size_t)(a.n_cells + 1);
-    hipLaunchKernelGGL(k_bin_hist<Real>, dim3((unsigned)a.bin_blocks), dim3(1024), shmem, stream,
+    hipLaunchKernelGGL(k_bin_hist<Real>, dim3((unsigned)a.bin_blocks), dim3(kBinThreads), shmem, stream,
                        a);
   } else if (a.n > 0) {
     int64_t work = a.n_cells > a.n ? a.n_cells : a.n;
@@ -471,10 +691,18 @@ hipError_t launch_binning(const SysArgs<Real>& a, const TypeTable& tt, hipStream
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(k_setup<Real>, dim3((unsigned)blocks), dim3(256), 0, stream, as);
   }
-  hipLaunchKernelGGL(k_bin_scan<Real>, dim3(1), dim3(1024), 0, stream, as, tt, own_header);
-  if (a.n == 0) return hipGetLastError();
-  hipLaunchKernelGGL(k_scatter<Real>, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, stream,
-                     a);
+  if (scan_fused(as)) {
+    hipLaunchKernelGGL(k_scatter_fused<Real>, dim3((unsigned)fused_blocks(as)), dim3(1024), 0,
+                       stream, as, tt);
+  } else {
+    if (colscan_blocks(as) > 0)
+      hipLaunchKernelGGL(k_bin_colscan<Real>, dim3((unsigned)colscan_blocks(as)), dim3(1024), 0,
+                         stream, as);
+    hipLaunchKernelGGL(k_bin_scan<Real>, dim3(1), dim3(1024), 0, stream, as, tt, own_header);
+    if (a.n == 0) return hipGetLastError();
+    hipLaunchKernelGGL(k_scatter<Real>, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, stream,
+                       a);
+  }
   hipLaunchKernelGGL(k_cell_sort<Real>, dim3((unsigned)a.n_cells), dim3(256), 0, stream, a);
   return hipGetLastError();
 }
@@ -495,11 +723,21 @@ hipError_t launch_binning_batch(const Batch<float>& b0, const TypeTable& tt, hip
     shmem = need > shmem ? need : shmem;
   }
   int64_t nb = batch_blocks(b, [](const SysArgs<float>& a) { return (int64_t)a.bin_blocks; });
-  hipLaunchKernelGGL(k_bin_hist_batch, dim3((unsigned)nb), dim3(1024), shmem, stream, b);
-  nb = batch_blocks(b, [](const SysArgs<float>&) { return (int64_t)1; });
-  hipLaunchKernelGGL(k_bin_scan_batch, dim3((unsigned)nb), dim3(1024), 0, stream, b, tt);
-  nb = batch_blocks(b, [](const SysArgs<float>& a) { return (a.n + 255) / 256; });
-  hipLaunchKernelGGL(k_scatter_batch, dim3((unsigned)nb), dim3(256), 0, stream, b);
+  hipLaunchKernelGGL(k_bin_hist_batch, dim3((unsigned)nb), dim3(kBinThreads), shmem, stream, b);
+  // grids of at most kScanFused cells: scan and scatter in one kernel
+  nb = batch_blocks(b, [](const SysArgs<float>& a) { return fused_blocks(a); });
+  if (nb > 0) hipLaunchKernelGGL(k_scatter_fused_batch, dim3((unsigned)nb), dim3(1024), 0, stream, b, tt);
+  // larger grids
+  nb = batch_blocks(b, [](const SysArgs<float>& a) { return colscan_blocks(a); });
+  if (nb > 0) hipLaunchKernelGGL(k_bin_colscan_batch, dim3((unsigned)nb), dim3(1024), 0, stream, b);
+  nb = batch_blocks(b, [](const SysArgs<float>& a) { return scan_fused(a) ? (int64_t)0 : (int64_t)1; });
+  if (nb > 0) {
+    hipLaunchKernelGGL(k_bin_scan_batch, dim3((unsigned)nb), dim3(1024), 0, stream, b, tt);
+    nb = batch_blocks(b, [](const SysArgs<float>& a) {
+      return scan_fused(a) ? (int64_t)0 : (a.n + 255) / 256;
+    });
+    hipLaunchKernelGGL(k_scatter_batch, dim3((unsigned)nb), dim3(256), 0, stream, b);
+  }
   nb = batch_blocks(b, [](const SysArgs<float>& a) { return a.n_cells; });
   hipLaunchKernelGGL(k_cell_sort_batch, dim3((unsigned)nb), dim3(256), 0, stream, b);
   return hipGetLastError();

@@ -18,8 +18,9 @@ constexpr int kFsSplit = 1;          // compacted-kernel workgroups per home cel
 constexpr int64_t kMaxCells = 1 << 24;
 constexpr int64_t kMaxAtoms = (int64_t)1 << 30;
 constexpr int kBinLdsCells = 32768;  // largest grid binned with a per-block LDS histogram
-constexpr int kBinMaxBlocks = 64;    // blocks of that pass
-constexpr int kBinMinChunk = 2048;   // atoms per block at least
+constexpr int kBinMaxBlocks = 1024;  // blocks of that pass
+constexpr int kBinThreads = 512;     // threads per block of that pass
+constexpr int kBinChunkUnit = 2048;  // atoms per block: a multiple of this (4 per thread)
 
 // Workspace header (first 256 bytes).
 // Drain depth selected by MD_PAIR_DRAIN in md_params.flags (2 when the field is 0).
@@ -87,7 +88,8 @@ struct SysArgs {
   Real* lj;                    // [n_types^2][2] (c12, c6)
   int32_t* paircount;          // [2][n]: caller order (after finalize), sorted order (pass)
   long long* acc64;            // [3][n] per-atom fixed-point sums (compacted kernel)
-  int32_t* bhist;              // [bin_blocks][n_cells] per-block cell counts, then offsets
+  int32_t* bhist;              // [bin_blocks][n_cells] per-block cell counts (offsets in place
+                               // after k_bin_colscan, for grids of more than 1024 cells)
   uint32_t* bstat;             // [bin_blocks] per-block status bits
   int32_t* order;              // [n_cells] cells by decreasing atom count (launch order)
   int32_t* zsplit;             // [n_cells] atoms of each cell in its lower z half

@@ -42,6 +42,7 @@ __device__ inline void finalize(const SysArgs<Real>& a, int64_t blk) {
   if (s >= a.n) return;
   const int64_t i = a.perm[s];
   uint32_t st = 0;
+  Real f[3];
   for (int c = 0; c < 3; ++c) {
     Real v;
     if (a.flags & MD_ACCUM_F32_ATOMIC) {
@@ -55,8 +56,13 @@ __device__ inline void finalize(const SysArgs<Real>& a, int64_t blk) {
       for (int slot = 0; slot < kSlots; ++slot) acc += a.part[((int64_t)slot * 3 + c) * a.n + s];
       v = acc;
     }
-    a.force_out[3 * i + c] = v;
+    f[c] = v;
   }
+  // one store of the three components
+  struct alignas(sizeof(Real)) R3 {
+    Real x, y, z;
+  };
+  *reinterpret_cast<R3*>(a.force_out + 3 * i) = R3{f[0], f[1], f[2]};
   if (a.flags & MD_DIAG_COUNTERS) a.paircount[i] = a.paircount[a.n + s];
   if (st) atomicOr(&a.hdr->status, st);
 }
@@ -66,7 +72,18 @@ __device__ inline void energy(const double* epart, int64_t n_tasks, double* out,
   if (halve_diag && threadIdx.x < 5) hdr->diag[threadIdx.x] /= 2;
   __shared__ double s[256];
   double acc = 0.0;
-  for (int64_t t = threadIdx.x; t < n_tasks; t += 256) acc += epart[t];
+  // each thread adds its partials in index order, eight loads in flight at a time
+  for (int64_t t0 = threadIdx.x; t0 < n_tasks; t0 += 8 * 256) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t t = t0 + 256 * u;
+      v[u] = t < n_tasks ? epart[t] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (t0 + 256 * u < n_tasks) acc += v[u];
+  }
   s[threadIdx.x] = acc;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
@@ -86,15 +103,16 @@ __host__ __device__ inline int halve_diag(const SysArgs<Real>& a) {
   return (a.compact && !a.half_shell && (a.flags & MD_DIAG_COUNTERS) && a.n > 0) ? 1 : 0;
 }
 
-// Blocks 0 .. ceil(n/256) - 1 finalize atoms; the block after them sums the energy
-// partials, which the pair kernel has completed, so one launch does both.
+// Block 0 sums the energy partials, which the pair kernel has completed, and blocks
+// 1 .. ceil(n/256) finalize atoms, so one launch does both; the energy block, the longest,
+// is dispatched first.
 template <typename Real>
 __device__ inline void finalize_or_energy(const SysArgs<Real>& a, int64_t blk) {
-  if (blk == (a.n + 255) / 256) {
+  if (blk == 0) {
     energy(a.epart, energy_parts(a), a.energy_out, a.hdr, halve_diag(a));
     return;
   }
-  finalize(a, blk);
+  finalize(a, blk - 1);
 }
 
 template <typename Real>

@@ -102,42 +102,72 @@ def test_fp32_apoa1_full(gpu, flags):
     assert diag[0] == sum_candidates(p, s.pos)
 
 
+def _check_binning(p, pos, ws, n):
+    """The sorted layout in the workspace against the oracle's cells: cell ranges that
+    cover every atom once, each cell ordered by (z half, wrapped x, original index) with
+    the z half in float32 as the kernel computes it, the lower-half counts, and each atom
+    in the oracle's cell unless it sits within 1e-4 A of a cell face."""
+    import torch
+    lay = api.workspace_layout(p, n)
+    nc = lay["n_cells"]
+    start = ws[lay["cell_start"]: lay["cell_start"] + 4 * (nc + 1)].view(torch.int32).cpu().numpy()
+    perm = ws[lay["perm"]: lay["perm"] + 4 * n].view(torch.int32).cpu().numpy().astype(np.int64)
+    zsplit = ws[lay["z_split"]: lay["z_split"] + 4 * nc].view(torch.int32).cpu().numpy()
+    assert start[0] == 0 and start[-1] == n and np.all(np.diff(start) >= 0)
+    assert np.array_equal(np.sort(perm), np.arange(n))
+    box = np.asarray(p["box"], np.float64)
+    pos64, _ = oracle.canonicalize(pos, box)   # wrapped in float32, as the kernels do
+    dims_g = lay["dims"]
+    inv_wz = np.float32(dims_g[2] / float(np.float32(box[2])))
+    scell = np.repeat(np.arange(nc), np.diff(start))          # cell of each sorted slot
+    cz = scell // (dims_g[0] * dims_g[1])
+    zf = pos64[perm, 2].astype(np.float32)
+    half = ((zf * inv_wz * np.float32(2)).astype(np.int64) >= 2 * cz + 1).astype(np.int64)
+    assert np.array_equal(np.bincount(scell[half == 0], minlength=nc), zsplit)
+    x = pos64[perm, 0]
+    same = np.diff(scell) == 0
+    dh, dx, di = np.diff(half), np.diff(x), np.diff(perm)
+    ordered = (dh > 0) | ((dh == 0) & ((dx > 0) | ((dx == 0) & (di > 0))))
+    assert np.all(ordered[same])
+    gcell = np.empty(n, np.int64)
+    gcell[perm] = scell
+    ocell, dims = oracle.bin_atoms(p, pos64)
+    diff = np.nonzero(gcell != ocell)[0]
+    w = box / np.array(dims)
+    frac = pos64[diff] / w
+    assert np.all(np.min(np.abs(frac - np.round(frac)) * w, axis=1) < 1e-4), diff[:10]
+    return lay
+
+
 def test_binning_matches_oracle(gpu):
     _say("case: binning of the 92,224-atom system")
-    import torch
     s = W.apoa1_system()
     p = s.params()
     f, e, ws, _ = run(p, s.pos, s.types, s.charges, gpu)
+    _check_binning(p, s.pos, ws, s.n)
+
+
+def test_binning_many_blocks(gpu):
+    """2,500,000 atoms in a 280 A cube (23^3 cells, more than the fused scan takes): 611
+    histogram blocks of 4,096 atoms (two rounds of 4 atoms per thread), 39 blocks per wave in
+    the column scan, the cell counts of the scan kernel in LDS; sampled forces against the
+    oracle."""
+    _say("case: binning of 2,500,000 atoms, 280 A cube")
+    import torch
+    s = W.gen_system(2_500_000, (280.0, 280.0, 280.0), seed=21)
+    p = s.params()
     lay = api.workspace_layout(p, s.n)
-    nc = lay["n_cells"]
-    start = ws[lay["cell_start"]: lay["cell_start"] + 4 * (nc + 1)].view(torch.int32).cpu().numpy()
-    perm = ws[lay["perm"]: lay["perm"] + 4 * s.n].view(torch.int32).cpu().numpy()
-    assert start[0] == 0 and start[-1] == s.n and np.all(np.diff(start) >= 0)
-    assert np.array_equal(np.sort(perm), np.arange(s.n))
-    pos64, _ = oracle.canonicalize(s.pos, s.box)   # wrapped in float32, as the kernels do
-    dims_g = lay["dims"]
-    inv_wz = np.float32(dims_g[2] / float(np.float32(s.box[2])))
-    zsplit = ws[lay["z_split"]: lay["z_split"] + 4 * nc].view(torch.int32).cpu().numpy()
-    gcell = np.empty(s.n, np.int64)
-    for c in range(nc):
-        seg = perm[start[c]:start[c + 1]]
-        # a cell is ordered by (z half, wrapped x, original index); z half in float32 as
-        # the kernel computes it
-        cz = c // (dims_g[0] * dims_g[1])
-        zf = pos64[seg, 2].astype(np.float32)
-        half = ((zf * inv_wz * np.float32(2)).astype(np.int64) >= 2 * cz + 1).astype(np.int64)
-        assert zsplit[c] == int((half == 0).sum())
-        x = pos64[seg, 0]
-        dh, dx, di = np.diff(half), np.diff(x), np.diff(seg)
-        assert np.all((dh > 0) | ((dh == 0) & ((dx > 0) | ((dx == 0) & (di > 0)))))
-        gcell[seg] = c
-    ocell, dims = oracle.bin_atoms(p, pos64)
-    diff = np.nonzero(gcell != ocell)[0]
-    # an atom may only change cell when it sits within 1e-4 A of a cell face
-    w = s.box / np.array(dims)
-    for i in diff:
-        frac = pos64[i] / w
-        assert np.min(np.abs(frac - np.round(frac)) * w) < 1e-4, (i, pos64[i])
+    assert lay["n_cells"] == 23 ** 3
+    f, e, ws, _ = run(p, s.pos, s.types, s.charges, gpu)
+    assert api.read_status(ws) == 0
+    _check_binning(p, s.pos, ws, s.n)
+    idx = np.sort(np.random.default_rng(3).choice(s.n, 200, replace=False))
+    ref = oracle.forces_subset(p, s.pos, s.types, s.charges, idx)
+    err = force_errors(f[idx], ref.force, ref.abs_sum)
+    _say("sampled", err)
+    assert err["max_norm"] <= 1e-5 and err["rms"] <= 1e-5
+    del ws
+    torch.cuda.empty_cache()
 
 
 @pytest.mark.parametrize("flags", [0, api.PAIR_FULL_SHELL])
