@@ -91,10 +91,10 @@ struct Img {
 
 // A segment: one z half of the images of one (dy, dz) row with one shift class, in x
 // order. Its slab bounds y0..y1, z0..z1 are in the home cell's frame.
-struct Seg {
-  int begin, end;   // neighbour-list positions
+struct alignas(16) Seg {
+  float y0, y1, z0, z1;   // first: one 16-byte load
+  int begin, end;         // neighbour-list positions
   int grp;
-  float y0, y1, z0, z1;
 };
 
 // Workgroup header in LDS.
@@ -432,18 +432,34 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
     if (tid == 0) H.next = 0;
     __syncthreads();
 
-    // segment table in registers: lane s holds segment s, clipped to this slice
+    // segment table in registers, clipped to this slice: lane l holds segment l, or, when
+    // there are at most 32 segments, segment l & 31, so that lanes l and l + 32 can search
+    // the two ends of segment l's x-window at once
+    const bool split = n_seg <= 32;
+    const int sl = split ? (lane & 31) : lane;
     int sb = 0, se = 0, sg = 0;
-    float sy0 = 0.f, sy1 = 0.f, sz0 = 0.f, sz1 = 0.f;
-    if (lane < n_seg) {
-      sb = max(H.seg[lane].begin, P0) - P0;
-      se = max(min(H.seg[lane].end, P1) - P0, sb);
-      sg = H.seg[lane].grp;
-      sy0 = H.seg[lane].y0;
-      sy1 = H.seg[lane].y1;
-      sz0 = H.seg[lane].z0;
-      sz1 = H.seg[lane].z1;
+    if (sl < n_seg) {
+      sb = max(H.seg[sl].begin, P0) - P0;
+      se = max(min(H.seg[sl].end, P1) - P0, sb);
+      sg = H.seg[sl].grp;
     }
+    // first position p in [sb, se) of this lane's segment with x >= key (se if none): a
+    // power-of-two search over byte addresses, 2^iters > se - sb, each probe clamped to
+    // the segment's last atom (a probe past it compares that atom instead, and the result
+    // is clamped to se)
+    const uint32_t f4b = (uint32_t)LL.f4;
+    auto lower_bound = [&](float key) __attribute__((always_inline)) {
+      const float k = se > sb ? key : -INFINITY;     // an empty segment probes nothing
+      uint32_t a = f4b + 16u * (uint32_t)sb - 16u;   // byte address of the last atom < key
+      const uint32_t last = f4b + 16u * (uint32_t)se - 16u;
+      for (int it = iters - 1; it >= 0; --it) {
+        const uint32_t t = a + (16u << it);
+        const float xq = *reinterpret_cast<const __attribute__((address_space(3))) float*>(
+            (uintptr_t)min(t, last));   // LDS byte address (the dynamic block starts at 0)
+        a = xq < k ? t : a;
+      }
+      return min((int)((a + 16u - f4b) >> 4), se);
+    };
 
     while (true) {
       int o = 0;
@@ -495,43 +511,32 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
       float e_lane = 0.f;
       float jmax = 0.f;   // largest |F_j| component, in units of 2^-24, handed to round_to_i64
 
-      // x-window of every segment: lane s finds [lo, hi) of segment s with x in
-      // [min x_i - w, max x_i + w) in the segment's frame (two lower_bound searches), where
-      // w^2 = R^2 - gy^2 - gz^2 and gy, gz are the gaps between the group's bounding box
-      // and the segment's slab (less 1e-3 A for atoms binned at a face by rounding)
+      // x-window of every segment: [lo, hi) of segment s with x in [min x_i - w, max x_i + w)
+      // in the segment's frame (two lower_bound searches, in lanes s and s + 32 when the
+      // segments fit 32 lanes, else both in lane s), where w^2 = R^2 - gy^2 - gz^2 and gy,
+      // gz are the gaps between the group's bounding box and the segment's slab (less
+      // 1e-3 A for atoms binned at a face by rounding)
       int wlo, whi;
       {
-        const float gy = fmaxf(fmaxf(sy0 - ymax, ymin - sy1) - kWin, 0.f);
-        const float gz = fmaxf(fmaxf(sz0 - zmax, zmin - sz1) - kWin, 0.f);
+        // the segment's slab, read again for every group (registers are scarce)
+        const Seg& sgl = H.seg[sl < n_seg ? sl : 0];
+        const float4 slab = make_float4(sgl.y0, sgl.y1, sgl.z0, sgl.z1);
+        const float gy = fmaxf(fmaxf(slab.x - ymax, ymin - slab.y) - kWin, 0.f);
+        const float gz = fmaxf(fmaxf(slab.z - zmax, zmin - slab.w) - kWin, 0.f);
         const float w2 = fmaf(R, R, -fmaf(gz, gz, gy * gy));
         const float hw = w2 > 0.f ? __builtin_sqrtf(w2) : -1.f;
         const float hx = (sg & 1) ? L0 : 0.f;
-        const float xlo = (xmin - hx) - hw;
-        const float xhi = (xmax - hx) + hw;
-        int f0 = sb, c0 = se - sb, f1 = sb, c1 = w2 > 0.f ? se - sb : 0;
-        for (int it = 0; it < iters; ++it) {
-          const int h0 = c0 >> 1, h1 = c1 >> 1;
-          const float x0 = sF[f0 + h0].x;   // f + h <= se <= cap: inside the LDS block
-          const float x1 = sF[f1 + h1].x;
-          if (c0 > 0) {
-            if (x0 < xlo) {
-              f0 += h0 + 1;
-              c0 -= h0 + 1;
-            } else {
-              c0 = h0;
-            }
-          }
-          if (c1 > 0) {
-            if (x1 < xhi) {
-              f1 += h1 + 1;
-              c1 -= h1 + 1;
-            } else {
-              c1 = h1;
-            }
-          }
+        // a segment out of reach gets the empty window [sb, sb)
+        const float xlo = w2 > 0.f ? (xmin - hx) - hw : -INFINITY;
+        const float xhi = w2 > 0.f ? (xmax - hx) + hw : -INFINITY;
+        if (split) {
+          // lane s: start of segment s's window; lane s + 32: its end
+          wlo = lower_bound(lane < 32 ? xlo : xhi);
+          whi = wlo;
+        } else {
+          wlo = lower_bound(xlo);
+          whi = lower_bound(xhi);
         }
-        wlo = f0;
-        whi = max(f1, f0);
       }
 
       float xs[kQ], ys[kQ], zs[kQ], thr[kQ];
@@ -540,18 +545,19 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
         return (int)((fb[k] - fk0) >> 1) - k * kFifo;
       };
       // the force on home atom k from one lane's FIFO entry j: the exact distance in the
-      // current frame, the strict cutoff (u > 0 drops the home atom itself) and the force;
-      // `in` is false for lanes past the FIFO's fill level. The half shell adds -F to
-      // neighbour j's accumulator as well (zero for lanes that add nothing), in units of
-      // 2^-24 kcal/mol/A: -f 2^24 dx is an exact scaling of the float32 product, rounded
-      // once to an integer.
+      // current frame, the strict cutoff and the force; `in` is false for lanes past the
+      // FIFO's fill level. The full shell's u > 0 drops the home atom itself; the half
+      // shell never pairs an atom with itself (j > i in the home image). The half shell
+      // adds -F to neighbour j's accumulator as well (zero for lanes that add nothing), in
+      // units of 2^-24 kcal/mol/A: -f 2^24 dx is an exact scaling of the float32 product,
+      // rounded once to an integer.
       auto pair_lane = [&](int k, int jl, const float4& pj, float qj, const float2& lj,
                            bool in) __attribute__((always_inline)) {
         const float dx = xs[k] - pj.x, dy = ys[k] - pj.y, dz = zs[k] - pj.z;
         float u = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
         float e, f;
         if (kClamp) {
-          u = (in && u > 0.f) ? u : kBigU;
+          u = (in && (kHalf || u > 0.f)) ? u : kBigU;
           f = pair_f<kSwitchCoulomb>(u, lj.x, lj.y, kq[k] * qj, rs2, inv_sw, sw12, e);
           if (diag) cnt[k] += __builtin_popcountll(__builtin_amdgcn_ballot_w64(u < rc2));
           if (kHalf && diag && u < rc2) atomicAdd(&sJn[jl], 1);
@@ -628,7 +634,7 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
       int cur_g = -1;
       for (int s = 0; s < n_seg; ++s) {
         int lo = __builtin_amdgcn_readlane(wlo, s);
-        const int hi = __builtin_amdgcn_readlane(whi, s);
+        const int hi = max(__builtin_amdgcn_readlane(whi, split ? s + 32 : s), lo);
         // half shell, home image (segments 0 and 1, positions = home atom indices): only
         // j > i, so the window starts past the group's first atom, and the first batch
         // drops, for each home atom, the lanes at or before it
