@@ -36,8 +36,8 @@ METRIC = "within-cutoff pair-interactions/s @92k atoms; p50/p99 latency mixed ba
 # HBM bytes per launch of the pair kernel at 92,224 atoms, from the FETCH_SIZE and
 # WRITE_SIZE counters scaled by a copy of known size (profiles/traffic_pair_fs_92k.md);
 # valid only for the kernel code they were taken on (kernel_code_sha256)
-PAIR_TRAFFIC = {"kernel_sha256": "169b743587bef9b2cfb51530095f94fa45d097bd0dfc6bda7ac66297b943bfe7",
-                "bytes": (17831 + 35478) * 1024}
+PAIR_TRAFFIC = {"kernel_sha256": "5f53c1aaabcceb6277fee304c0344fe31a07087ac2b65c40d9b241b725c30564",
+                "bytes": (14803 + 31492) * 1024}
 
 
 def parse():
