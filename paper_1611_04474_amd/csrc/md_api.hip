@@ -91,6 +91,7 @@ md_status make_plan(const md_params* p, int64_t n, int real_bytes, Plan* pl) {
   pl->off_bhist = o;     o = align_up(o + sizeof(int32_t) * (size_t)pl->bin_blocks * cells);
   pl->off_bstat = o;     o = align_up(o + sizeof(uint32_t) * (size_t)(pl->bin_blocks + 1));
   pl->off_order = o;     o = align_up(o + sizeof(int32_t) * cells);
+  pl->off_cost = o;      o = align_up(o + sizeof(uint32_t) * cells);
   pl->off_zsplit = o;    o = align_up(o + sizeof(int32_t) * cells);
   pl->off_ukey = o;      o = align_up(o + sizeof(unsigned long long) * nn);
   pl->off_upos = o;      o = align_up(o + (size_t)4 * real_bytes * nn);
@@ -128,6 +129,7 @@ SysArgs<Real> make_args(const md_params* p, const Plan& pl, int64_t n, const Rea
   a.bhist = (int32_t*)(b + pl.off_bhist);
   a.bstat = (uint32_t*)(b + pl.off_bstat);
   a.order = (int32_t*)(b + pl.off_order);
+  a.cost = (uint32_t*)(b + pl.off_cost);
   a.zsplit = (int32_t*)(b + pl.off_zsplit);
   a.ukey = (unsigned long long*)(b + pl.off_ukey);
   a.upos = (P4<Real>*)(b + pl.off_upos);

@@ -266,26 +266,41 @@ __global__ __launch_bounds__(1024) void k_bin_colscan_batch(Batch<float> b) {
   bin_colscan(b.sys[s], blk);
 }
 
+// Whether cost[] holds the pair kernel's times of the last evaluation on this grid (a
+// workspace fresh from the caller holds anything: then the key rarely matches, and a false
+// match only changes the launch order).
+template <typename Real>
+__device__ inline bool have_costs(const SysArgs<Real>& a) {
+  return a.hdr->cost_key == kCostKey && a.hdr->cost_cells == (uint32_t)a.n_cells;
+}
+
 // The cells' launch order for the pair kernel, the mixed LJ table and (own_header) the
-// status word: the end of the scan, by one workgroup of 1024 threads; count(c) gives the
-// atom count of cell c, and st_lane (threads 0 .. 63) the histogram blocks' status bits
-// from block_status.
-template <typename Real, typename Count>
+// status word: the end of the scan, by one workgroup of 1024 threads. key(c) is cell c's
+// expected cost: its time in the last pair kernel when known, else its atom count;
+// st_lane (threads 0 .. 63) carries the histogram blocks' status bits from block_status.
+template <typename Real, typename Key>
 __device__ inline void scan_tail(const SysArgs<Real>& a, const TypeTable& tt, int own_header,
-                                 int32_t* s_tot, Count count, uint32_t st_lane) {
+                                 int32_t* s_tot, Key key, uint32_t st_lane) {
   const int t = threadIdx.x;
   const int64_t nc = a.n_cells;
-  // counting sort of the cells by decreasing count (counts clamped to kOrderBins - 1); the
-  // order within a bin is arbitrary, which only changes which compute unit takes a cell,
-  // never a result
+  // counting sort of the cells by decreasing key, in kOrderBins bins of 2^sh key units
+  // (sh makes the largest key fit); the order within a bin is arbitrary, which only
+  // changes which compute unit takes a cell, never a result. Longest first lets the
+  // short cells fill the tail.
   constexpr int kOrderBins = 1024;
   __shared__ int32_t s_bin[kOrderBins];
+  __shared__ uint32_t s_max;
   s_bin[t] = 0;
+  if (t == 0) s_max = 0;
   __syncthreads();
-  for (int64_t c = t; c < nc; c += 1024) {
-    const int32_t v = count(c);
-    atomicAdd(&s_bin[kOrderBins - 1 - (v < kOrderBins - 1 ? v : kOrderBins - 1)], 1);
-  }
+  for (int64_t c = t; c < nc; c += 1024) atomicMax(&s_max, key(c));
+  __syncthreads();
+  const int sh = max(0, 32 - __builtin_clz(s_max | 1u) - 10);
+  auto bin = [&](int64_t c) {
+    const uint32_t v = key(c) >> sh;
+    return kOrderBins - 1 - (int)(v < kOrderBins - 1 ? v : kOrderBins - 1);
+  };
+  for (int64_t c = t; c < nc; c += 1024) atomicAdd(&s_bin[bin(c)], 1);
   __syncthreads();
   {
     int32_t all;
@@ -294,8 +309,7 @@ __device__ inline void scan_tail(const SysArgs<Real>& a, const TypeTable& tt, in
     __syncthreads();
   }
   for (int64_t c = t; c < nc; c += 1024) {
-    const int32_t v = count(c);
-    const int32_t pos = atomicAdd(&s_bin[kOrderBins - 1 - (v < kOrderBins - 1 ? v : kOrderBins - 1)], 1);
+    const int32_t pos = atomicAdd(&s_bin[bin(c)], 1);
     a.order[pos] = (int32_t)c;
   }
   const int nt = a.n_types;
@@ -391,7 +405,10 @@ __device__ inline void bin_scan(const SysArgs<Real>& a, const TypeTable& tt, int
     carry += chunk;
   }
   if (t == 0) a.start[nc] = carry;
-  scan_tail(a, tt, own_header, s_tot, count, st_blocks.bits());
+  const bool by_cost = have_costs(a);
+  scan_tail(a, tt, own_header, s_tot,
+            [&](int64_t c) { return by_cost ? a.cost[c] : (uint32_t)count(c); },
+            st_blocks.bits());
 }
 
 template <typename Real>
@@ -486,6 +503,9 @@ __device__ inline void scatter_fused(const SysArgs<Real>& a, const TypeTable& tt
   const Real q = a.q_in[ic];
   const int ty = a.type_in[ic];
   const Status st_blocks = block_status(a, blk == 0);
+  // block 0: this cell's cost in the last pair kernel, when known
+  const bool by_cost = blk == 0 && have_costs(a);
+  const uint32_t cost_t = by_cost && t < nc ? a.cost[t] : 0u;
   int32_t tot = 0, off = 0;
   if (t < nc) {
     for (int b0 = 0; b0 < B; b0 += 64) {
@@ -504,14 +524,14 @@ __device__ inline void scatter_fused(const SysArgs<Real>& a, const TypeTable& tt
   if (t < nc) {
     s_start[t] = start_c;
     s_off[t] = off;
-    s_cnt[t] = tot;
+    s_cnt[t] = by_cost ? (int32_t)cost_t : tot;   // block 0's order key
   }
   __syncthreads();
   if (i < a.n) put_atom(a, i, ci, s_start[ci] + s_off[ci] + rk, x, y, z, q, ty);
   if (blk == 0) {
     if (t < nc) a.start[t] = start_c;
     if (t == 0) a.start[nc] = all;
-    scan_tail(a, tt, 1, s_tot, [&](int64_t cc) { return s_cnt[cc]; }, st_blocks.bits());
+    scan_tail(a, tt, 1, s_tot, [&](int64_t cc) { return (uint32_t)s_cnt[cc]; }, st_blocks.bits());
   }
 }
 

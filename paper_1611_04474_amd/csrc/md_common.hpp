@@ -34,8 +34,11 @@ struct WsHeader {
   uint32_t pad0;
   unsigned long long diag[5];   // candidates, filter passes, cutoff passes, filtered slots,
                                 // force lanes evaluated
-  uint32_t pad1[52];
+  uint32_t cost_key;            // kCostKey when cost[] holds the last pair kernel's times
+  uint32_t cost_cells;          // ... of a grid of this many cells
+  uint32_t pad1[50];
 };
+constexpr uint32_t kCostKey = 0x4d44434fu;
 static_assert(sizeof(WsHeader) == 256, "header size");
 
 template <typename Real>
@@ -53,6 +56,7 @@ struct Plan {
   // byte offsets
   size_t off_count, off_start, off_cell, off_rank, off_unsorted, off_pos, off_type, off_perm,
       off_part, off_facc, off_epart, off_lj, off_paircount, off_bhist, off_bstat, off_order,
+      off_cost,
       off_zsplit, off_ukey, off_upos, off_kpart, total;
   int bin_blocks;               // blocks of the LDS-histogram binning pass (0: global atomics)
   int64_t bin_chunk;            // atoms per such block
@@ -91,7 +95,8 @@ struct SysArgs {
   int32_t* bhist;              // [bin_blocks][n_cells] per-block cell counts (offsets in place
                                // after k_bin_colscan, for grids of more than 1024 cells)
   uint32_t* bstat;             // [bin_blocks] per-block status bits
-  int32_t* order;              // [n_cells] cells by decreasing atom count (launch order)
+  int32_t* order;              // [n_cells] launch order of the home cells, longest first
+  uint32_t* cost;              // [n_cells] each home cell's time in the last pair kernel
   int32_t* zsplit;             // [n_cells] atoms of each cell in its lower z half
   // scalars
   int64_t n, n_cells, n_tasks;

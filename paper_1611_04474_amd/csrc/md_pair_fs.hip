@@ -848,20 +848,42 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
   }
 }
 
+// The workgroup's time for its home cell (constant 100 MHz clock) goes to cost[cell]: the
+// binning of the next evaluation on this grid launches the cells longest first by it
+// (measurement-based load balancing; atom counts stand in on the first evaluation). The
+// first workgroup marks the costs valid for this grid.
+__device__ inline void record_cost(const SysArgs<float>& a, int64_t cell, uint64_t t0,
+                                   bool first) {
+  if (threadIdx.x == 0) {   // after the workgroup's last barrier
+    const uint64_t dt = __builtin_amdgcn_s_memrealtime() - t0;
+    a.cost[cell] = dt < 0xffffffffull ? (uint32_t)dt : 0xffffffffu;
+    if (first) {
+      a.hdr->cost_key = kCostKey;
+      a.hdr->cost_cells = (uint32_t)a.n_cells;
+    }
+  }
+}
+
 template <bool kHalf, bool kSwitchCoulomb, bool kClamp, bool kDiag, int kDrain>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNW / 4, kNW / 4)))
 void k_pair_fs(SysArgs<float> a, int cap) {
-  // home cells in decreasing order of atom count, spread over the XCDs in turn
-  pair_fs<kHalf, kSwitchCoulomb, kClamp, kDiag, kDrain>(a, cap, a.order[blockIdx.x]);
+  // home cells in the order the binning chose (longest first)
+  const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+  const int64_t cell = a.order[blockIdx.x];
+  pair_fs<kHalf, kSwitchCoulomb, kClamp, kDiag, kDrain>(a, cap, cell);
+  record_cost(a, cell, t0, blockIdx.x == 0);
 }
 
 // One launch for a batch: block b is cell order[b - cum[s]] of system s.
 template <bool kHalf, bool kSwitchCoulomb, bool kClamp, bool kDiag, int kDrain>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNW / 4, kNW / 4)))
 void k_pair_fs_batch(Batch<float> b, int cap) {
+  const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
   int64_t unit;
   const int s = b.pick(blockIdx.x, unit);
-  pair_fs<kHalf, kSwitchCoulomb, kClamp, kDiag, kDrain>(b.sys[s], cap, b.sys[s].order[unit]);
+  const int64_t cell = b.sys[s].order[unit];
+  pair_fs<kHalf, kSwitchCoulomb, kClamp, kDiag, kDrain>(b.sys[s], cap, cell);
+  record_cost(b.sys[s], cell, t0, unit == 0);
 }
 
 template <bool H, bool S, bool C, bool D, int R>

@@ -436,17 +436,22 @@ def test_stmv_sampled(gpu):
 
 def test_batched_matches_alone(gpu):
     """Serving form: systems of different sizes in one batched call give bitwise the
-    results of evaluating each alone. 13 systems exceed one launch batch, one predicated
+    results of evaluating each alone. 14 systems exceed one launch batch, one predicated
     system is evaluated on its own inside the call, and two full-shell systems split
-    the batches by kind."""
-    _say("case: 13 serving requests, batched vs alone")
+    the batches by kind. The last system has 1,728 cells, so its binning takes the path
+    for grids of more than 1024 cells while the others scan inside the scatter."""
+    _say("case: 13 serving requests and one 150,000-atom cube, batched vs alone")
     import torch
     from _gpu import to_dev
     reqs, table = W.serving_trace(n_req=64)
-    picks = [0, 1, 2, 3, 5, 8, 13, 21, 34, 40, 50, 55, 63]
+    picks = [0, 1, 2, 3, 5, 8, 13, 21, 34, 40, 50, 55, 63, None]
     systems, alone = [], []
     for k, r in enumerate(picks):
-        s = W.request_system(reqs[r], table)
+        if r is None:
+            s = W.gen_system(150_000, (150.0, 150.0, 150.0), seed=31)
+            assert api.workspace_layout(s.params(), s.n)["n_cells"] == 12 ** 3
+        else:
+            s = W.request_system(reqs[r], table)
         flags = api.PAIR_PREDICATED if k == 6 else api.PAIR_FULL_SHELL if k in (3, 4) else 0
         p = api.Params.from_dict(s.params(), flags)
         d = to_dev((s.pos, s.types, s.charges), gpu)
