@@ -109,7 +109,10 @@ typedef struct {
  * md_forces_f64 (double_precision = 1) for n_atoms atoms with p->flags (the flags
  * choose the pair kernel, whose per-atom buffers differ in size). Returns 0 when the
  * parameters are invalid. The workspace must be 256-byte aligned; its contents
- * need no initialisation and are scratch between calls. */
+ * need no initialisation. Between calls they are scratch, except that the float32
+ * compacted kernel leaves each home cell's measured time there: the next call on the
+ * same workspace and cell grid launches the cells longest first by those times. They
+ * only steer scheduling, never a result, so any contents are valid. */
 size_t md_workspace_bytes(const md_params* p, int64_t n_atoms, int double_precision);
 
 /*
