@@ -111,8 +111,9 @@ typedef struct {
  * parameters are invalid. The workspace must be 256-byte aligned; its contents
  * need no initialisation. Between calls they are scratch, except that the float32
  * compacted kernel leaves each home cell's measured time there: the next call on the
- * same workspace and cell grid launches the cells longest first by those times. They
- * only steer scheduling, never a result, so any contents are valid. */
+ * same workspace and cell grid (of at most 1024 cells) launches the cells longest first
+ * by those times. They only steer scheduling, never a result, so any contents are
+ * valid. */
 size_t md_workspace_bytes(const md_params* p, int64_t n_atoms, int double_precision);
 
 /*

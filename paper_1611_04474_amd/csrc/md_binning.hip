@@ -274,30 +274,30 @@ __device__ inline bool have_costs(const SysArgs<Real>& a) {
   return a.hdr->cost_key == kCostKey && a.hdr->cost_cells == (uint32_t)a.n_cells;
 }
 
+// Launch-order key of a cell from its time in units of the 100 MHz clock: bins of 160 ns,
+// so the 1024 bins of the order's counting sort span 164 us per cell (longer ones share
+// the first bin).
+__device__ inline uint32_t cost_key(uint32_t ticks) { return ticks >> 4; }
+
 // The cells' launch order for the pair kernel, the mixed LJ table and (own_header) the
 // status word: the end of the scan, by one workgroup of 1024 threads. key(c) is cell c's
-// expected cost: its time in the last pair kernel when known, else its atom count;
-// st_lane (threads 0 .. 63) carries the histogram blocks' status bits from block_status.
+// expected cost: its atom count, or (grids of at most kScanFused cells) its time in the
+// last pair kernel when known; st_lane (threads 0 .. 63) carries the histogram blocks'
+// status bits from block_status.
 template <typename Real, typename Key>
 __device__ inline void scan_tail(const SysArgs<Real>& a, const TypeTable& tt, int own_header,
                                  int32_t* s_tot, Key key, uint32_t st_lane) {
   const int t = threadIdx.x;
   const int64_t nc = a.n_cells;
-  // counting sort of the cells by decreasing key, in kOrderBins bins of 2^sh key units
-  // (sh makes the largest key fit); the order within a bin is arbitrary, which only
-  // changes which compute unit takes a cell, never a result. Longest first lets the
-  // short cells fill the tail.
+  // counting sort of the cells by decreasing key (keys clamped to kOrderBins - 1); the
+  // order within a bin is arbitrary, which only changes which compute unit takes a cell,
+  // never a result. Longest first lets the short cells fill the tail.
   constexpr int kOrderBins = 1024;
   __shared__ int32_t s_bin[kOrderBins];
-  __shared__ uint32_t s_max;
   s_bin[t] = 0;
-  if (t == 0) s_max = 0;
   __syncthreads();
-  for (int64_t c = t; c < nc; c += 1024) atomicMax(&s_max, key(c));
-  __syncthreads();
-  const int sh = max(0, 32 - __builtin_clz(s_max | 1u) - 10);
   auto bin = [&](int64_t c) {
-    const uint32_t v = key(c) >> sh;
+    const uint32_t v = key(c);
     return kOrderBins - 1 - (int)(v < kOrderBins - 1 ? v : kOrderBins - 1);
   };
   for (int64_t c = t; c < nc; c += 1024) atomicAdd(&s_bin[bin(c)], 1);
@@ -405,9 +405,9 @@ __device__ inline void bin_scan(const SysArgs<Real>& a, const TypeTable& tt, int
     carry += chunk;
   }
   if (t == 0) a.start[nc] = carry;
-  const bool by_cost = have_costs(a);
-  scan_tail(a, tt, own_header, s_tot,
-            [&](int64_t c) { return by_cost ? a.cost[c] : (uint32_t)count(c); },
+  // launch order by atom count: with more than 1024 cells there are several workgroups
+  // per compute unit, and the short cells already fill the tail
+  scan_tail(a, tt, own_header, s_tot, [&](int64_t c) { return (uint32_t)count(c); },
             st_blocks.bits());
 }
 
@@ -503,9 +503,10 @@ __device__ inline void scatter_fused(const SysArgs<Real>& a, const TypeTable& tt
   const Real q = a.q_in[ic];
   const int ty = a.type_in[ic];
   const Status st_blocks = block_status(a, blk == 0);
-  // block 0: this cell's cost in the last pair kernel, when known
+  // block 0: this cell's cost in the last pair kernel (loaded before it is known whether
+  // the costs are valid, so that both loads are in flight together)
+  const uint32_t cost_t = blk == 0 && t < nc ? a.cost[t] : 0u;
   const bool by_cost = blk == 0 && have_costs(a);
-  const uint32_t cost_t = by_cost && t < nc ? a.cost[t] : 0u;
   int32_t tot = 0, off = 0;
   if (t < nc) {
     for (int b0 = 0; b0 < B; b0 += 64) {
@@ -524,7 +525,7 @@ __device__ inline void scatter_fused(const SysArgs<Real>& a, const TypeTable& tt
   if (t < nc) {
     s_start[t] = start_c;
     s_off[t] = off;
-    s_cnt[t] = by_cost ? (int32_t)cost_t : tot;   // block 0's order key
+    s_cnt[t] = by_cost ? (int32_t)cost_key(cost_t) : tot;   // block 0's order key
   }
   __syncthreads();
   if (i < a.n) put_atom(a, i, ci, s_start[ci] + s_off[ci] + rk, x, y, z, q, ty);

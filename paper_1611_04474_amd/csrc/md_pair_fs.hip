@@ -849,9 +849,10 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
 }
 
 // The workgroup's time for its home cell (constant 100 MHz clock) goes to cost[cell]: the
-// binning of the next evaluation on this grid launches the cells longest first by it
-// (measurement-based load balancing; atom counts stand in on the first evaluation). The
-// first workgroup marks the costs valid for this grid.
+// binning of the next evaluation on this grid (of at most 1024 cells) launches the cells
+// longest first by it (measurement-based load balancing; atom counts stand in on the
+// first evaluation and on larger grids). The first workgroup marks the costs valid for
+// this grid.
 __device__ inline void record_cost(const SysArgs<float>& a, int64_t cell, uint64_t t0,
                                    bool first) {
   if (threadIdx.x == 0) {   // after the workgroup's last barrier
