@@ -4,29 +4,35 @@
 // arrays (first transformation of Section 2.2): float4/double4 (x, y, z, q), the
 // type and the permutation back to the caller's order.
 //
-// Kernels, in launch order. When the grid fits in LDS (the usual case):
-//   k_bin_hist   each block takes a contiguous range of atoms, wraps each coordinate
-//                into [0, L] (one add/subtract of L in the input precision), checks it,
-//                computes the cell and counts it in an LDS histogram (the LDS atomic's
-//                return value is the atom's slot among the block's atoms of that cell);
-//                the histogram and the block's status bits go to the workspace, so no
-//                global atomics are needed;
-//   k_bin_colscan (grids of more than 1024 cells) per cell, exclusive offsets of the
-//                blocks and the total, one workgroup per 64 cells;
-//   k_bin_scan   one workgroup: (smaller grids) the same per-cell offsets and totals;
-//                exclusive scan of the totals -> cell_start; the cells ordered by
-//                decreasing atom count (the pair kernel starts the largest home cells
-//                first, so the last workgroups to run are short ones); the mixed
-//                Lennard-Jones table (Lorentz-Berthelot); the status word;
-// otherwise k_setup (clears the counters) and k_bin_count (one global atomic per atom)
-// take the place of k_bin_hist, and k_bin_scan only scans. Then:
-//   k_scatter    writes each atom's index into its cell's range (arbitrary order);
-//   k_cell_sort  one workgroup per cell: orders the cell's atoms by (z half of the cell,
-//                wrapped x, original index) -- a total order, so every later sum runs in
-//                a reproducible order, and each half of a row of cells along x is sorted in
-//                x, which lets the pair kernel bound the candidates of a group of home
-//                atoms by an x-window per half-row -- writes the sorted arrays and the
-//                number of atoms in the lower z half.
+// Kernels, in launch order. When the grid fits in an LDS histogram (up to 32,768 cells):
+//   k_bin_hist       each block takes a contiguous range of atoms, wraps each coordinate
+//                    into [0, L] (one add/subtract of L in the input precision), checks it,
+//                    computes the cell and counts it in an LDS histogram (the LDS atomic's
+//                    return value is the atom's slot among the block's atoms of that cell);
+//                    the histogram and the block's status bits go to the workspace, so no
+//                    global atomics are needed;
+// then, for grids of at most 1024 cells,
+//   k_scatter_fused  every block derives the cells' starts and its own offset within each
+//                    cell from the histograms and scatters its atoms; block 0 also writes
+//                    cell_start, the launch order, the mixed Lennard-Jones table
+//                    (Lorentz-Berthelot) and the status word;
+// and for larger grids
+//   k_bin_colscan    per cell, the blocks' exclusive offsets and the total (64 cells per
+//                    workgroup);
+//   k_bin_scan       one workgroup: exclusive scan of the totals -> cell_start, the launch
+//                    order, the LJ table and the status word;
+//   k_scatter        each atom to its cell's range.
+// Beyond 32,768 cells, k_setup (clears the counters) and k_bin_count (one global atomic per
+// atom) take the place of k_bin_hist, and k_bin_scan and k_scatter follow. Last:
+//   k_cell_sort      one workgroup per cell: orders the cell's atoms by (z half of the cell,
+//                    wrapped x, original index) -- a total order, so every later sum runs
+//                    in a reproducible order, and each half of a row of cells along x is
+//                    sorted in x, which lets the pair kernel bound the candidates of a group
+//                    of home atoms by an x-window per half-row -- writes the sorted arrays
+//                    and the number of atoms in the lower z half.
+// The scatter puts atoms in arbitrary order within a cell's range (the LDS atomics' order);
+// the launch order puts the cells longest first (atom counts, or the last pair kernel's
+// measured times on small grids), so that the last workgroups to run are short ones.
 #include "md_common.hpp"
 
 namespace md {
