@@ -566,6 +566,13 @@ __global__ __launch_bounds__(1024) void k_scatter_fused_batch(Batch<float> b, Ty
 // with a smaller key (keys are distinct: they hold the atom index), counted over LDS
 // chunks of the cell's keys, so any cell occupancy is handled; the member's data then
 // move to that position.
+// Adds to *s_low the number of lanes of this wave with `low` set: one LDS atomic per wave
+// (called by every lane of the wave).
+__device__ inline void count_low(int32_t* s_low, bool low) {
+  const unsigned long long b = __builtin_amdgcn_ballot_w64(low);
+  if ((threadIdx.x & 63) == 0 && b != 0ull) atomicAdd(s_low, (int32_t)__builtin_popcountll(b));
+}
+
 template <typename Real>
 __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
   constexpr int kChunk = 1024;
@@ -620,9 +627,10 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
       const int32_t e = (int32_t)threadIdx.x + 256 * k;
-      if (!(k < kk && e < m)) continue;
+      const bool in = k < kk && e < m;
+      count_low(&s_low, in && !(my_key[k] >> 63));
+      if (!in) continue;
       const int32_t d = s0 + my_rank[k];
-      if (!(my_key[k] >> 63)) atomicAdd(&s_low, 1);
       P4<Real> p;
       p.x = px[k];
       p.y = py[k];
@@ -662,9 +670,10 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
     }
     for (int k = 0; k < kPer; ++k) {
       const int32_t e = a0 + (int32_t)threadIdx.x + 256 * k;
-      if (!(k < kk && e < m)) continue;
+      const bool in = k < kk && e < m;
+      count_low(&s_low, in && !(my_key[k] >> 63));
+      if (!in) continue;
       const int32_t d = s0 + my_rank[k];
-      if (!(my_key[k] >> 63)) atomicAdd(&s_low, 1);
       a.pos[d] = a.upos[s0 + e];
       a.type[d] = a.unsorted[s0 + e];
       a.perm[d] = (int32_t)(my_key[k] & 0x7fffffffull);
