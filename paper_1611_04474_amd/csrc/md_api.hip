@@ -66,7 +66,6 @@ md_status make_plan(const md_params* p, int64_t n, int real_bytes, Plan* pl) {
   pl->off_start = o;     o = align_up(o + sizeof(int32_t) * (cells + 1));
   pl->off_cell = o;      o = align_up(o + sizeof(int32_t) * nn);
   pl->off_rank = o;      o = align_up(o + sizeof(int32_t) * nn);
-  pl->off_unsorted = o;  o = align_up(o + sizeof(int32_t) * nn);
   pl->off_pos = o;       o = align_up(o + (size_t)4 * real_bytes * nn);
   pl->off_type = o;      o = align_up(o + sizeof(int32_t) * nn);
   pl->off_perm = o;      o = align_up(o + sizeof(int32_t) * nn);
@@ -93,7 +92,7 @@ md_status make_plan(const md_params* p, int64_t n, int real_bytes, Plan* pl) {
   pl->off_order = o;     o = align_up(o + sizeof(int32_t) * cells);
   pl->off_cost = o;      o = align_up(o + sizeof(uint32_t) * cells);
   pl->off_zsplit = o;    o = align_up(o + sizeof(int32_t) * cells);
-  pl->off_ukey = o;      o = align_up(o + sizeof(unsigned long long) * nn);
+  pl->off_ukey = o;      o = align_up(o + sizeof(UKey) * nn);
   pl->off_upos = o;      o = align_up(o + (size_t)4 * real_bytes * nn);
   pl->off_kpart = o;     o = align_up(o + sizeof(double) * (size_t)ke_blocks(n));
   pl->total = o;
@@ -116,7 +115,6 @@ SysArgs<Real> make_args(const md_params* p, const Plan& pl, int64_t n, const Rea
   a.start = (int32_t*)(b + pl.off_start);
   a.cell = (int32_t*)(b + pl.off_cell);
   a.rank = (int32_t*)(b + pl.off_rank);
-  a.unsorted = (int32_t*)(b + pl.off_unsorted);
   a.pos = (P4<Real>*)(b + pl.off_pos);
   a.type = (int32_t*)(b + pl.off_type);
   a.perm = (int32_t*)(b + pl.off_perm);
@@ -131,7 +129,7 @@ SysArgs<Real> make_args(const md_params* p, const Plan& pl, int64_t n, const Rea
   a.order = (int32_t*)(b + pl.off_order);
   a.cost = (uint32_t*)(b + pl.off_cost);
   a.zsplit = (int32_t*)(b + pl.off_zsplit);
-  a.ukey = (unsigned long long*)(b + pl.off_ukey);
+  a.ukey = (UKey*)(b + pl.off_ukey);
   a.upos = (P4<Real>*)(b + pl.off_upos);
   a.bin_blocks = pl.bin_blocks;
   a.bin_chunk = pl.bin_chunk;

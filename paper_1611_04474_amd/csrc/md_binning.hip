@@ -445,8 +445,8 @@ __device__ inline unsigned long long sort_key(const SysArgs<Real>& a, int32_t i,
          ((unsigned long long)__builtin_bit_cast(uint32_t, x + 0.f) << 31) | (uint32_t)i;
 }
 
-// Atom i (of cell c) goes to slot `slot` of the unsorted cell-major arrays: its sort key,
-// its wrapped (x, y, z, q) and its type.
+// Atom i (of cell c) goes to slot `slot` of the cell-major arrays that precede the in-cell
+// sort: its sort key and type as one 16-byte record, and its wrapped (x, y, z, q).
 template <typename Real>
 __device__ inline void put_atom(const SysArgs<Real>& a, int64_t i, int c, int32_t slot, Real x,
                                 Real y, Real z, Real q, int t) {
@@ -458,9 +458,8 @@ __device__ inline void put_atom(const SysArgs<Real>& a, int64_t i, int c, int32_
   p.z = wrap_coord(z, a.L[2], st);
   p.w = q;
   if (t < 0 || t >= a.n_types) t = 0;
-  a.ukey[slot] = sort_key(a, (int32_t)i, (float)p.x, p.z, cz);
+  a.ukey[slot] = UKey{sort_key(a, (int32_t)i, (float)p.x, p.z, cz), t, 0};
   a.upos[slot] = p;
-  a.unsorted[slot] = t;
 }
 
 // Each atom goes to its cell's range (in arbitrary order) with its sort key, its wrapped
@@ -598,13 +597,14 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
       const int32_t e = (int32_t)threadIdx.x + 256 * k;
       const bool in = k < kk && e < m;
       const int32_t src = s0 + (in ? e : 0);   // m >= 1 here: a valid member
-      my_key[k] = in ? a.ukey[src] : ~0ull;
+      const UKey u = a.ukey[src];
+      my_key[k] = in ? u.key : ~0ull;
       const P4<Real> p = a.upos[src];
       px[k] = p.x;
       py[k] = p.y;
       pz[k] = p.z;
       pq[k] = p.w;
-      my_t[k] = a.unsorted[src];
+      my_t[k] = u.type;
       my_rank[k] = 0;
     }
     // slots m .. 256 kk - 1 (a multiple of 8) hold ~0, which is below no key
@@ -650,13 +650,13 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
     int32_t my_rank[kPer];
     for (int k = 0; k < kPer; ++k) {
       const int32_t e = a0 + (int32_t)threadIdx.x + 256 * k;
-      my_key[k] = (k < kk && e < m) ? a.ukey[s0 + e] : ~0ull;
+      my_key[k] = (k < kk && e < m) ? a.ukey[s0 + e].key : ~0ull;
       my_rank[k] = 0;
     }
     for (int32_t b0 = 0; b0 < m; b0 += kChunk) {
       const int32_t mb = min(kChunk, m - b0);
       __syncthreads();
-      for (int32_t e = threadIdx.x; e < mb; e += 256) s_key[e] = a.ukey[s0 + b0 + e];
+      for (int32_t e = threadIdx.x; e < mb; e += 256) s_key[e] = a.ukey[s0 + b0 + e].key;
       for (int32_t e = mb + (int32_t)threadIdx.x; e < ((mb + 3) & ~3); e += 256) s_key[e] = ~0ull;
       __syncthreads();
       for (int32_t e = 0; e < mb; e += 4) {
@@ -675,7 +675,7 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
       if (!in) continue;
       const int32_t d = s0 + my_rank[k];
       a.pos[d] = a.upos[s0 + e];
-      a.type[d] = a.unsorted[s0 + e];
+      a.type[d] = a.ukey[s0 + e].type;
       a.perm[d] = (int32_t)(my_key[k] & 0x7fffffffull);
     }
   }

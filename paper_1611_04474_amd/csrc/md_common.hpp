@@ -41,6 +41,13 @@ struct WsHeader {
 constexpr uint32_t kCostKey = 0x4d44434fu;
 static_assert(sizeof(WsHeader) == 256, "header size");
 
+// An atom's in-cell sort key and type, written by the scatter with one 16-byte store.
+struct alignas(16) UKey {
+  unsigned long long key;
+  int32_t type;
+  int32_t pad;
+};
+
 template <typename Real>
 struct alignas(4 * sizeof(Real)) P4 {
   Real x, y, z, w;
@@ -54,7 +61,7 @@ struct Plan {
   int64_t n;
   int real_bytes;               // 4 or 8
   // byte offsets
-  size_t off_count, off_start, off_cell, off_rank, off_unsorted, off_pos, off_type, off_perm,
+  size_t off_count, off_start, off_cell, off_rank, off_pos, off_type, off_perm,
       off_part, off_facc, off_epart, off_lj, off_paircount, off_bhist, off_bstat, off_order,
       off_cost,
       off_zsplit, off_ukey, off_upos, off_kpart, total;
@@ -80,8 +87,8 @@ struct SysArgs {
   int32_t* start;              // [n_cells+1]
   int32_t* cell;               // [n]
   int32_t* rank;               // [n]
-  int32_t* unsorted;           // [n] types, in cell order before the in-cell sort
-  unsigned long long* ukey;    // [n] in-cell sort keys, same order
+  UKey* ukey;                  // [n] in-cell sort keys and types, in cell order before the
+                               // in-cell sort
   P4<Real>* upos;              // [n] wrapped (x, y, z, q), same order
   P4<Real>* pos;               // [n] sorted (x,y,z,q)
   int32_t* type;               // [n] sorted
