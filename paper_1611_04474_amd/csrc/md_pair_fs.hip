@@ -728,19 +728,26 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
         r[3 * k + 1] = fy[k];
         r[3 * k + 2] = fz[k];
       }
+      // Both exchanges are register swaps between lane groups (v_permlane32_swap: lanes
+      // 32-63 of the first operand with lanes 0-31 of the second; v_permlane16_swap: the
+      // odd 16-lane rows of the first with the even rows of the second). After the swap
+      // the first operand holds the lane's kept value in the lower group and the partner's
+      // in the upper one, the second operand the reverse, so their sum is the same two
+      // terms as keep + partner's give (float addition commutes exactly). The results are
+      // read by value: a bit cast applied to an element of the returned vector reads
+      // element 0 for both with this compiler.
       float r6[6], r3[3];
-      const bool up32 = lane >= 32, up16 = (lane & 16) != 0;
 #pragma unroll
       for (int i = 0; i < 6; ++i) {
-        const float keep = up32 ? r[i + 6] : r[i];
-        const float give = up32 ? r[i] : r[i + 6];
-        r6[i] = keep + __shfl_xor(give, 32);
+        const auto sw =
+            __builtin_amdgcn_permlane32_swap(__float_as_uint(r[i]), __float_as_uint(r[i + 6]), false, false);
+        r6[i] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
       }
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        const float keep = up16 ? r6[i + 3] : r6[i];
-        const float give = up16 ? r6[i] : r6[i + 3];
-        r3[i] = keep + __shfl_xor(give, 16);
+        const auto sw =
+            __builtin_amdgcn_permlane16_swap(__float_as_uint(r6[i]), __float_as_uint(r6[i + 3]), false, false);
+        r3[i] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
       }
 #pragma unroll
       for (int i = 0; i < 3; ++i) r3[i] = rowsum16(r3[i]);
