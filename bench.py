@@ -36,8 +36,8 @@ METRIC = "within-cutoff pair-interactions/s @92k atoms; p50/p99 latency mixed ba
 # HBM bytes per launch of the pair kernel at 92,224 atoms, from the FETCH_SIZE and
 # WRITE_SIZE counters scaled by a copy of known size (profiles/traffic_pair_fs_92k.md);
 # valid only for the kernel code they were taken on (kernel_code_sha256)
-PAIR_TRAFFIC = {"kernel_sha256": "7ac961e465ee339923bde2e9c41ee3c7c13d493700030dfd69a11e8bcc392c4b",
-                "bytes": (14638 + 31512) * 1024}
+PAIR_TRAFFIC = {"kernel_sha256": "fa77b6880d902de67bd92a20687c1d6f7fde9dabd2f2b37d54ab4752b1c4fbf5",
+                "bytes": (13718 + 30421) * 1024}
 
 
 def parse():
