@@ -9,7 +9,9 @@ and energy) on inputs already resident in HBM.
 
 Prints ONE JSON line: within-cutoff pair interactions per second, the roofline of the
 pair kernel (algorithmic float32 FLOPs per launch / launch time measured with HIP
-events on the launch stream), the FP64 oracle timed on the host cores, and two more
+events on the launch stream, against the published peak and against that peak scaled
+to the shader clock the kernel's workgroups counted), the FP64 oracle timed on the host
+cores, and two more
 forms of the same path:
   serving  -- 512 requests of 2k-200k atoms (cubes at 0.1 atoms/A^3, Poisson arrivals
               at 200 req/s), continuous batching against the plain one-at-a-time path,
@@ -29,6 +31,7 @@ import time
 import numpy as np
 
 PEAK_FP32_TFLOPS = 157.3       # MI355X published float32 vector peak
+CLOCK_NOMINAL_GHZ = 2.4        # the clock that peak is quoted at
 FLOP_PER_CANDIDATE = 8         # filter: 3 sub, 1 mul, 2 fma (fma = 2)
 FLOP_PER_PAIR = 40             # force, switch, accumulation
 BIN_BYTES_PER_ATOM = 20 + 24 + 24
@@ -36,8 +39,8 @@ METRIC = "within-cutoff pair-interactions/s @92k atoms; p50/p99 latency mixed ba
 # HBM bytes per launch of the pair kernel at 92,224 atoms, from the FETCH_SIZE and
 # WRITE_SIZE counters scaled by a copy of known size (profiles/traffic_pair_fs_92k.md);
 # valid only for the kernel code they were taken on (kernel_code_sha256)
-PAIR_TRAFFIC = {"kernel_sha256": "fa77b6880d902de67bd92a20687c1d6f7fde9dabd2f2b37d54ab4752b1c4fbf5",
-                "bytes": (13718 + 30421) * 1024}
+PAIR_TRAFFIC = {"kernel_sha256": "9e62758b00009c557c6b1e15075a49d5704e8e915d7385e505f92029ecda6982",
+                "bytes": (13870 + 30452) * 1024}
 
 
 def parse():
@@ -163,6 +166,8 @@ def main():
     wall = time.perf_counter() - t0
     if api.read_status(ws) != 0:
         raise SystemExit(f"device status {api.read_status(ws):#x}")
+    # shader clock of the last timed pair launch, counted by its own workgroups
+    clock_ghz = api.read_clock(ws)
     bin_ms = [e[0].elapsed_time(e[1]) for e in events]
     pair_ms = [e[1].elapsed_time(e[2]) for e in events]
     fin_ms = [e[2].elapsed_time(e[3]) for e in events]
@@ -218,6 +223,12 @@ def main():
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
+            "clock_GHz_nominal": CLOCK_NOMINAL_GHZ,
+            "clock_GHz_under_load": clock_ghz or None,
+            "peak_at_clock_under_load": (PEAK_FP32_TFLOPS * clock_ghz / CLOCK_NOMINAL_GHZ
+                                         if clock_ghz else None),
+            "frac_at_clock_under_load": (achieved * CLOCK_NOMINAL_GHZ / (PEAK_FP32_TFLOPS * clock_ghz)
+                                         if clock_ghz else None),
             "flop_per_launch": flop_per_launch,
             "traffic": pair_traffic(args),
         },

@@ -213,6 +213,14 @@ md_status md_read_device_status(const void* d_ws, void* stream, uint32_t* bits);
  * [4] are half of its per-atom counts. Synchronises `stream`. */
 md_status md_read_diag(const void* d_ws, void* stream, uint64_t counters[5]);
 
+/* The shader clock, in GHz, at which the compacted pair kernel of the last call on this
+ * workspace ran: each of its workgroups counts shader-clock cycles and ticks of the
+ * constant 100 MHz counter over its run, and *ghz is the ratio of the two sums times
+ * 0.1, i.e. the clock averaged over workgroup time. It measures the roofline's peak at
+ * the clock under load. *ghz is 0 when no compacted pair kernel has run since the last
+ * binning (the predicated kernel does not count). Synchronises `stream`. */
+md_status md_read_clock(const void* d_ws, void* stream, double* ghz);
+
 /* Layout of the workspace, for inspection of intermediate results. Offsets are in
  * bytes from the workspace start.
  *   cell_start: int32 [n_cells+1], first sorted index of each cell

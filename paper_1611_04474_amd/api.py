@@ -99,6 +99,8 @@ def lib():
         L.md_read_device_status.restype = C.c_int
         L.md_read_diag.argtypes = [vp, vp, C.POINTER(C.c_uint64)]
         L.md_read_diag.restype = C.c_int
+        L.md_read_clock.argtypes = [vp, vp, C.POINTER(C.c_double)]
+        L.md_read_clock.restype = C.c_int
         L.md_status_string.argtypes = [C.c_int]
         L.md_status_string.restype = C.c_char_p
         _lib = L
@@ -107,7 +109,8 @@ def lib():
 
 EXPORTED = ("md_workspace_bytes", "md_forces_f32", "md_forces_f32_stages", "md_forces_f64",
             "md_forces_batched", "md_run_vv_f32",
-            "md_read_device_status", "md_read_diag", "md_workspace_layout", "md_status_string")
+            "md_read_device_status", "md_read_diag", "md_read_clock", "md_workspace_layout",
+            "md_status_string")
 
 
 class Params:
@@ -332,6 +335,15 @@ def read_diag(workspace, stream=None):
     if rc != MD_OK:
         raise MDError(rc, "md_read_diag")
     return [int(x) for x in v]
+
+
+def read_clock(workspace, stream=None):
+    """Shader clock (GHz) of the last compacted pair kernel on this workspace, 0.0 if none."""
+    v = C.c_double(0.0)
+    rc = lib().md_read_clock(C.c_void_p(workspace.data_ptr()), _stream_ptr(stream), C.byref(v))
+    if rc != MD_OK:
+        raise MDError(rc, "md_read_clock")
+    return float(v.value)
 
 
 def status_string(code):

@@ -363,6 +363,17 @@ md_status md_read_diag(const void* d_ws, void* stream, uint64_t counters[5]) {
   return MD_OK;
 }
 
+md_status md_read_clock(const void* d_ws, void* stream, double* ghz) {
+  if (!d_ws || !ghz) return MD_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  md::WsHeader h;
+  if (hipMemcpyAsync(&h, d_ws, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess)
+    return MD_ERR_HIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return MD_ERR_HIP;
+  *ghz = h.clock[1] ? 0.1 * (double)h.clock[0] / (double)h.clock[1] : 0.0;
+  return MD_OK;
+}
+
 const char* md_status_string(md_status s) {
   switch (s) {
     case MD_OK: return "ok";

@@ -164,6 +164,7 @@ __global__ void k_setup(SysArgs<Real> a) {
   if (tid == 0) {
     a.hdr->status = 0;
     for (int k = 0; k < 5; ++k) a.hdr->diag[k] = 0;
+    a.hdr->clock[0] = a.hdr->clock[1] = 0;
   }
 }
 
@@ -332,6 +333,7 @@ __device__ inline void scan_tail(const SysArgs<Real>& a, const TypeTable& tt, in
     for (int o = 32; o > 0; o >>= 1) st |= __shfl_xor(st, o);
     if (t == 0) a.hdr->status = st;
     if (t < 5) a.hdr->diag[t] = 0;
+    if (t < 2) a.hdr->clock[t] = 0;
   }
 }
 

@@ -34,9 +34,11 @@ struct WsHeader {
   uint32_t pad0;
   unsigned long long diag[5];   // candidates, filter passes, cutoff passes, filtered slots,
                                 // force lanes evaluated
+  unsigned long long clock[2];  // compacted pair kernel since the last binning, summed over
+                                // its workgroups: shader-clock cycles, 100 MHz ticks
   uint32_t cost_key;            // kCostKey when cost[] holds the last pair kernel's times
   uint32_t cost_cells;          // ... of a grid of this many cells
-  uint32_t pad1[50];
+  uint32_t pad1[46];
 };
 constexpr uint32_t kCostKey = 0x4d44434fu;
 static_assert(sizeof(WsHeader) == 256, "header size");

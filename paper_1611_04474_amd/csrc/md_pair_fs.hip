@@ -860,11 +860,17 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
 // longest first by it (measurement-based load balancing; atom counts stand in on the
 // first evaluation and on larger grids). The first workgroup marks the costs valid for
 // this grid.
+// The same workgroup also adds its shader-clock cycles (s_memtime) and its 100 MHz ticks
+// to the header's two clock sums: their ratio is the clock the kernel ran at, weighted by
+// workgroup time.
 __device__ inline void record_cost(const SysArgs<float>& a, int64_t cell, uint64_t t0,
-                                   bool first) {
+                                   uint64_t c0, bool first) {
   if (threadIdx.x == 0) {   // after the workgroup's last barrier
+    const uint64_t dc = __builtin_amdgcn_s_memtime() - c0;
     const uint64_t dt = __builtin_amdgcn_s_memrealtime() - t0;
     a.cost[cell] = dt < 0xffffffffull ? (uint32_t)dt : 0xffffffffu;
+    atomicAdd(&a.hdr->clock[0], (unsigned long long)dc);
+    atomicAdd(&a.hdr->clock[1], (unsigned long long)dt);
     if (first) {
       a.hdr->cost_key = kCostKey;
       a.hdr->cost_cells = (uint32_t)a.n_cells;
@@ -877,9 +883,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNW / 
 void k_pair_fs(SysArgs<float> a, int cap) {
   // home cells in the order the binning chose (longest first)
   const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+  const uint64_t c0 = __builtin_amdgcn_s_memtime();
   const int64_t cell = a.order[blockIdx.x];
   pair_fs<kHalf, kSwitchCoulomb, kClamp, kDiag, kDrain>(a, cap, cell);
-  record_cost(a, cell, t0, blockIdx.x == 0);
+  record_cost(a, cell, t0, c0, blockIdx.x == 0);
 }
 
 // One launch for a batch: block b is cell order[b - cum[s]] of system s.
@@ -887,11 +894,12 @@ template <bool kHalf, bool kSwitchCoulomb, bool kClamp, bool kDiag, int kDrain>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNW / 4, kNW / 4)))
 void k_pair_fs_batch(Batch<float> b, int cap) {
   const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+  const uint64_t c0 = __builtin_amdgcn_s_memtime();
   int64_t unit;
   const int s = b.pick(blockIdx.x, unit);
   const int64_t cell = b.sys[s].order[unit];
   pair_fs<kHalf, kSwitchCoulomb, kClamp, kDiag, kDrain>(b.sys[s], cap, cell);
-  record_cost(b.sys[s], cell, t0, unit == 0);
+  record_cost(b.sys[s], cell, t0, c0, unit == 0);
 }
 
 template <bool H, bool S, bool C, bool D, int R>

@@ -30,6 +30,15 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(api.EXPORTED)
 
 
+def test_read_calls_reject_null_workspace():
+    """The read calls check their pointers before any device call."""
+    v = C.c_double(1.0)
+    assert api.lib().md_read_clock(None, None, C.byref(v)) == -1
+    assert v.value == 1.0
+    w = (C.c_uint64 * 5)()
+    assert api.lib().md_read_diag(None, None, w) == -1
+
+
 def test_status_strings():
     assert api.status_string(0) == "ok"
     assert "workspace" in api.status_string(-3)

@@ -191,6 +191,27 @@ def test_fixed64_bitwise_reproducible(gpu, flags):
         assert torch.equal(f1, f0) and torch.equal(e1, e0), k
 
 
+def test_clock_under_load(gpu):
+    """The pair kernel's own clock reading: a shader clock between 0.5 GHz and the
+    2.4 GHz maximum after the compacted kernel (the roofline's peak at the clock under
+    load comes from it), 0 after the predicated kernel, which does not record one."""
+    _say("case: 92,224 atoms, clock of the compacted and of the predicated pair kernel")
+    from _gpu import to_dev
+    s = W.apoa1_system()
+    d = to_dev((s.pos, s.types, s.charges), gpu)
+    for flags in (0, api.PAIR_PREDICATED):
+        p = api.Params.from_dict(s.params(), flags)
+        ws = api.alloc_workspace(p, s.n, gpu)
+        ws.fill_(0xAB)
+        api.forces(p, *d, workspace=ws)
+        ghz = api.read_clock(ws)
+        _say("flags", flags, "clock GHz", ghz)
+        if flags == 0:
+            assert 0.5 < ghz < 2.45, ghz
+        else:
+            assert ghz == 0.0
+
+
 def test_f32_atomic_mode(gpu):
     _say("case: 92,224 atoms, float32 atomic accumulation")
     s = W.apoa1_system()
