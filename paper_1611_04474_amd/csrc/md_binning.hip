@@ -467,6 +467,16 @@ __device__ inline void put_atom(const SysArgs<Real>& a, int64_t i, int c, int32_
 // Each atom goes to its cell's range (in arbitrary order) with its sort key, its wrapped
 // (x, y, z, q) and its type, read here in the caller's order (coalesced), so the in-cell
 // sort only touches its own cell's range.
+// Workgroups are dealt to the 8 XCDs in turn, each with its own L2. Block bid is renumbered
+// so that every XCD takes one contiguous range of the nblk blocks (the first nblk % 8 XCDs
+// one block more): a bijection on 0..nblk-1, so only the placement changes. The scatter's
+// consecutive blocks share a histogram row (bhist[i / bin_chunk]); numbered this way a row
+// is fetched into one L2 instead of into up to eight.
+__device__ inline int64_t xcd_contiguous(int64_t bid, int64_t nblk) {
+  const int64_t x = bid % 8, k = bid / 8, q = nblk / 8, r = nblk % 8;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+}
+
 template <typename Real>
 __device__ inline void scatter(const SysArgs<Real>& a, int64_t blk) {
   const int64_t i = blk * 256 + threadIdx.x;
@@ -544,7 +554,9 @@ __device__ inline void scatter_fused(const SysArgs<Real>& a, const TypeTable& tt
 }
 
 template <typename Real>
-__global__ __launch_bounds__(256) void k_scatter(SysArgs<Real> a) { scatter(a, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_scatter(SysArgs<Real> a) {
+  scatter(a, xcd_contiguous(blockIdx.x, gridDim.x));
+}
 
 __global__ __launch_bounds__(256) void k_scatter_batch(Batch<float> b) {
   int64_t blk;
