@@ -216,9 +216,11 @@ md_status md_read_diag(const void* d_ws, void* stream, uint64_t counters[5]);
 /* The shader clock, in GHz, at which the compacted pair kernel of the last call on this
  * workspace ran: each of its workgroups counts shader-clock cycles and ticks of the
  * constant 100 MHz counter over its run, and *ghz is the ratio of the two sums times
- * 0.1, i.e. the clock averaged over workgroup time. It measures the roofline's peak at
- * the clock under load. *ghz is 0 when no compacted pair kernel has run since the last
- * binning (the predicated kernel does not count). Synchronises `stream`. */
+ * 0.1, i.e. the clock averaged over workgroup time. Scaling a peak rate quoted at the
+ * nominal clock by *ghz / nominal gives the peak at the clock the kernel really ran at.
+ * *ghz is 0 when no compacted pair kernel has run since the last binning (the predicated
+ * and the float64 kernels do not count). Errors: MD_ERR_INVALID_ARG for a null pointer,
+ * MD_ERR_HIP if the copy fails. Synchronises `stream`. */
 md_status md_read_clock(const void* d_ws, void* stream, double* ghz);
 
 /* Layout of the workspace, for inspection of intermediate results. Offsets are in
