@@ -109,8 +109,9 @@ def pct(v, q):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU decomposition is described in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: "
+              "the path runs on one GPU, and a large system would shard by spatial "
+              "decomposition of the cell grid with halo exchange", file=sys.stderr)
         sys.exit(2)
 
     import torch
