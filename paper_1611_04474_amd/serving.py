@@ -125,6 +125,42 @@ def run_policy(items, arrivals, backend, budget_bytes, max_batch=32, max_infligh
                  busy_s=busy, peak_bytes=peak)
 
 
+_HIP = None
+
+
+def copy_async(dst, src, stream):
+    """Stream-ordered copy between a pinned host tensor and a device tensor of the same
+    byte size, through hipMemcpyAsync itself. torch's non-blocking copy also records an
+    event on the pinned host block for each copy; the serving buffers live for the whole
+    run, so those events pile up, and now and then recording one held the host for 7-10 ms,
+    which showed as the batched tail at high request rates."""
+    global _HIP
+    import ctypes as C
+    if _HIP is None:
+        lib = C.CDLL("libamdhip64.so")
+        lib.hipMemcpyAsync.restype = C.c_int
+        lib.hipMemcpyAsync.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p]
+        _HIP = lib
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("copy_async: sizes differ")
+    host = src if dst.is_cuda else dst
+    if host.is_cuda or not host.is_pinned() or not (src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("copy_async: needs one pinned host and one device tensor, contiguous")
+    kind = 1 if dst.is_cuda else 2          # hipMemcpyHostToDevice, hipMemcpyDeviceToHost
+    rc = _HIP.hipMemcpyAsync(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), nbytes, kind,
+                             C.c_void_p(stream.cuda_stream))
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpyAsync failed with code {rc}")
+
+
+def _to_device(t, device, stream):
+    import torch
+    d = torch.empty(t.shape, dtype=t.dtype, device=device)
+    copy_async(d, t, stream)
+    return d
+
+
 class GpuBackend:
     """Backend of run_policy on one HIP device: device tensors per admitted request,
     host-to-device copies on a copy stream, batched force calls and device-to-host
@@ -142,9 +178,9 @@ class GpuBackend:
         torch = self.torch
         with torch.cuda.stream(self.copy):
             h = dict(item=it,
-                     pos=it.pos.to(self.device, non_blocking=True),
-                     types=it.types.to(self.device, non_blocking=True),
-                     charges=it.charges.to(self.device, non_blocking=True),
+                     pos=_to_device(it.pos, self.device, self.copy),
+                     types=_to_device(it.types, self.device, self.copy),
+                     charges=_to_device(it.charges, self.device, self.copy),
                      force=torch.empty((it.n, 3), dtype=torch.float32, device=self.device),
                      energy=torch.empty(1, dtype=torch.float64, device=self.device),
                      workspace=api.alloc_workspace(it.params, it.n, self.device))
@@ -163,10 +199,9 @@ class GpuBackend:
                                  charges=h["charges"], force=h["force"], energy=h["energy"],
                                  workspace=h["workspace"]) for h in handles],
                            stream=self.compute)
-        with torch.cuda.stream(self.compute):
-            for h in handles:
-                h["item"].force_out.copy_(h["force"], non_blocking=True)
-                h["item"].energy_out.copy_(h["energy"], non_blocking=True)
+        for h in handles:
+            copy_async(h["item"].force_out, h["force"], self.compute)
+            copy_async(h["item"].energy_out, h["energy"], self.compute)
         end.record(self.compute)
         return (start, end)
 
@@ -198,12 +233,12 @@ def replay_plain(items, arrivals, device, clock=time.perf_counter):
         with torch.cuda.stream(stream):
             start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             start.record(stream)
-            pos = it.pos.to(device, non_blocking=True)
-            types = it.types.to(device, non_blocking=True)
-            q = it.charges.to(device, non_blocking=True)
+            pos = _to_device(it.pos, device, stream)
+            types = _to_device(it.types, device, stream)
+            q = _to_device(it.charges, device, stream)
             f, e = api.forces(it.params, pos, types, q, stream=stream)
-            it.force_out.copy_(f, non_blocking=True)
-            it.energy_out.copy_(e, non_blocking=True)
+            copy_async(it.force_out, f, stream)
+            copy_async(it.energy_out, e, stream)
             end.record(stream)
         end.synchronize()
         done_s[k] = clock() - t0

@@ -502,6 +502,37 @@ def test_batched_matches_alone(gpu):
     assert err["max_norm"] <= 1e-5 and err["rms"] <= 1e-5, err
 
 
+def test_serving_loop_outputs(gpu):
+    """The serving loop's results equal the plain call's on the same requests, bit for bit:
+    inputs copied in and forces copied out with copy_async (hipMemcpyAsync between pinned
+    host and device memory), batched launches of up to 4 requests; and so do the results
+    of the one-at-a-time replay."""
+    _say("case: serving loop and plain replay, 12 trace requests, against direct calls")
+    import torch
+    from paper_1611_04474_amd import serving as S
+    from _gpu import to_dev
+    reqs, table = W.serving_trace(n_req=12)
+    systems = [W.request_system(r, table) for r in reqs]
+    items = S.prepare(systems, gpu)
+    for it in items:
+        it.force_out.fill_(float("nan"))
+        it.energy_out.fill_(float("nan"))
+    st = S.run_policy(items, np.zeros(len(items)), S.GpuBackend(gpu), 64 << 30, 4, 2)
+    assert max(st.batches) > 1
+    torch.cuda.synchronize()
+    got = [(it.force_out.clone(), it.energy_out.clone()) for it in items]
+    for it in items:
+        it.force_out.fill_(float("nan"))
+        it.energy_out.fill_(float("nan"))
+    S.replay_plain(items, np.zeros(len(items)), gpu)
+    for k, (it, s) in enumerate(zip(items, systems)):
+        d = to_dev((s.pos, s.types, s.charges), gpu)
+        f, e = api.forces(it.params, *d)
+        f, e = f.cpu(), e.cpu()
+        assert torch.equal(got[k][0], f) and torch.equal(got[k][1], e), ("batched", k)
+        assert torch.equal(it.force_out, f) and torch.equal(it.energy_out, e), ("plain", k)
+
+
 def test_precision_form_report(gpu):
     """Precision form on the 92,224-atom system: float32 pair arithmetic with 64-bit
     fixed-point per-atom sums against float32-atomic sums, each against the FP64 oracle
