@@ -380,3 +380,121 @@ def test_small_config_golden():
     assert r.n_pairs == g["n_pairs"] == 1201501
     assert r.energy == pytest.approx(g["energy"], rel=1e-12)
     np.testing.assert_allclose(r.force[g["atoms"]], np.array(g["forces"]), rtol=1e-10, atol=1e-6)
+
+
+# ------------------------------------------------- parity scaffolding ----
+# Two oracle outputs decide how strict the GPU parity bars are: the per-atom sum of
+# pair-force magnitudes (the denominator of the normalised force error) and the atoms
+# with a partner in the float32/float64 cutoff band (excused from the exact partner-count
+# check). Both are pinned here to closed forms and to an independent enumeration.
+
+def _eq12_magnitude(s, e, qi, qj, r):
+    """|F| of one pair from Eq. 1 and Eq. 2 (inside the switching radius): LJ with
+    A = 48 eps s^12, B = 24 eps s^6, plus Coulomb k qi qj / r^2."""
+    A = 48 * e * s ** 12
+    B = 24 * e * s ** 6
+    return abs(A / r ** 13 - B / r ** 7 + K * qi * qj / r ** 2)
+
+
+@pytest.mark.parametrize("r", [2.9, 3.3, 6.0, 9.9])
+@pytest.mark.parametrize("method", ["bruteforce", "celllist"])
+def test_abs_sum_two_atoms_equals_force_magnitude(r, method):
+    """With one partner the sum of pair-force magnitudes is |F_i| itself, and |F_i| is
+    the Eq. 1 + Eq. 2 magnitude (|f| u in place of |f| sqrt(u) would miss by a factor r)."""
+    s, e = 3.1, 0.12
+    p = params(sigma=(s,), eps=(e,))
+    pos, t, q = two_atoms(r, qi=0.4, qj=-0.3, axis=1)
+    res = oracle.forces(p, pos, t, q, method)
+    mag = _eq12_magnitude(s, e, 0.4, -0.3, r)
+    assert res.abs_sum[0] == pytest.approx(mag, rel=1e-12)
+    assert res.abs_sum[1] == pytest.approx(mag, rel=1e-12)
+    assert np.linalg.norm(res.force[0]) == pytest.approx(mag, rel=1e-12)
+    sub = oracle.forces_subset(p, pos, t, q, [1])
+    assert sub.abs_sum[0] == pytest.approx(mag, rel=1e-12)
+
+
+@pytest.mark.parametrize("method", ["bruteforce", "celllist"])
+def test_abs_sum_three_collinear_atoms(method):
+    """Three atoms on a line, 3.4 A apart, the middle one with two equal partners: its
+    force cancels exactly while its magnitude sum is twice the pair magnitude; an end
+    atom sums its near partner (3.4 A) and its far one (6.8 A)."""
+    s, e, d = 3.0, 0.1, 3.4
+    p = params(sigma=(s,), eps=(e,))
+    pos = np.full((3, 3), 9.0)
+    pos[:, 0] = [4.0, 4.0 + d, 4.0 + 2 * d]
+    t = np.zeros(3, np.int32)
+    q = np.array([0.25, 0.5, 0.25])
+    res = oracle.forces(p, pos, t, q, method)
+    near = _eq12_magnitude(s, e, 0.25, 0.5, d)
+    far = _eq12_magnitude(s, e, 0.25, 0.25, 2 * d)
+    assert np.linalg.norm(res.force[1]) < 1e-12 * near
+    assert res.abs_sum[1] == pytest.approx(2 * near, rel=1e-12)
+    assert res.abs_sum[0] == pytest.approx(near + far, rel=1e-12)
+    assert res.abs_sum[2] == pytest.approx(near + far, rel=1e-12)
+    assert list(res.count) == [2, 2, 2]
+
+
+def _band_enumeration(p, pos, band):
+    """Independent count of partners with |u - rc^2| <= band, every pair by minimum image
+    in numpy (no cells): per atom, and unique pairs."""
+    L = np.asarray(p["box"], float)
+    x = np.asarray(pos, float)
+    d = x[:, None, :] - x[None, :, :]
+    d -= L * np.round(d / L)
+    u = (d * d).sum(axis=2)
+    inb = np.abs(u - p["r_cut"] ** 2) <= band
+    np.fill_diagonal(inb, False)
+    return inb.sum(axis=1), int(np.triu(inb, 1).sum())
+
+
+@pytest.mark.parametrize("box,seed", [((24.5, 24.5, 24.5), 21), ((24.5, 37.0, 50.0), 22)])
+def test_band_atoms_match_enumeration(box, seed):
+    """The band finder against a plain enumeration, on a 2x2x2 and a mixed 2x3x4 grid, with
+    a wide band (so that many pairs fall in it, also across every periodic face) and with
+    the 8-ulp float32 band around rc^2 = 144."""
+    pos, t, q, p = _random_system(260, box, seed)
+    for band in (3.0, 0.4, 8 * 2.0 ** (7 - 23)):
+        per, tot = oracle.band_atoms(p, pos, band)
+        eper, etot = _band_enumeration(p, pos, band)
+        assert np.array_equal(per, eper), band
+        assert tot == etot
+    per, tot = oracle.band_atoms(p, pos, 3.0)
+    assert tot > 50 and per.sum() == 2 * tot
+
+
+def test_band_atoms_constructed_pairs():
+    """Pairs placed a few float32 ulps of rc^2 from the cutoff are in the band, pairs
+    beyond it are not; across a periodic face as inside the box."""
+    ulp = 2.0 ** (7 - 23)                       # float32 ulp of 144
+    band = 8 * ulp
+    p = params(box=(40.0, 40.0, 40.0))
+    rows = []
+    # (x_i, distance^2 - rc^2): inside the box, and through the x face at 0 / 40
+    for k, (x0, du) in enumerate([(3.0, 2 * ulp), (3.0, -2 * ulp), (3.0, 7.5 * ulp),
+                                  (3.0, 30 * ulp), (34.0, -3 * ulp), (34.0, 40 * ulp)]):
+        r = math.sqrt(144.0 + du)
+        y = 2.0 + 4.5 * k
+        rows.append(((x0, y, 5.0), ((x0 + r) % 40.0, y, 5.0)))
+    pos = np.array([a for pr in rows for a in pr])
+    expect_in = [True, True, True, False, True, False]
+    per, tot = oracle.band_atoms(p, pos, band)
+    eper, etot = _band_enumeration(p, pos, band)
+    assert np.array_equal(per, eper)
+    for k, want in enumerate(expect_in):
+        assert per[2 * k] == per[2 * k + 1] == int(want), k
+    assert tot == sum(expect_in)
+
+
+def test_canonicalize_float64_wrap_branches():
+    """float64 inputs: [-L, 0) gets +L, [L, 2L) gets -L, both exactly; outside, NaN flagged."""
+    box = np.array([30.0, 20.0, 10.0])
+    pos = np.array([[-29.5, 20.0, 19.25], [-1e-9, 39.0, 0.0]])
+    out, st = oracle.canonicalize(pos, box)
+    assert st == 0
+    np.testing.assert_array_equal(out, [[0.5, 0.0, 9.25], [-1e-9 + 30.0, 19.0, 0.0]])
+    _, st = oracle.canonicalize(np.array([[-30.0001, 0.0, 0.0]]), box)
+    assert st == oracle.STATUS_OUT_OF_BOX
+    _, st = oracle.canonicalize(np.array([[0.0, 40.0, 0.0]]), box)
+    assert st == oracle.STATUS_OUT_OF_BOX
+    _, st = oracle.canonicalize(np.array([[0.0, 0.0, np.nan]]), box)
+    assert st == oracle.STATUS_NAN
