@@ -61,9 +61,15 @@ constexpr int kLdsBytes = 160 * 1024;
 constexpr float kMargin = 0.05f;    // A^2 added to rc^2 by the expanded-form prefilter
 constexpr float kWin = 1.0e-3f;     // A added to r_cut for the x-window
 constexpr float kBigU = 1.0e30f;    // squared distance given to lanes that must add nothing
-// largest partial force component (kcal/mol/A) the half shell adds into a per-atom sum:
-// 15 partials of at most 2^27 stay inside the 2^31 range of the 64-bit fixed point
-constexpr float kHalfPartialMax = 134217728.f;
+// Range of the per-atom 64-bit fixed-point sums (2^31 kcal/mol/A). In the half shell an
+// atom's sum gathers one neighbour-side partial from each of the 14 images that stage it
+// (its home image and the 13 workgroups that have its cell ahead), each below 2^27
+// (kNbrPartialMax), and one home-side partial per LDS slice of its home cell's neighbour
+// list, S of them, each below 2^28 / S: 14 * 2^27 + 2^28 = 2^31. In the full shell an
+// atom's S home-side partials are each below 2^31 / S.
+constexpr float kNbrPartialMax = 134217728.f;      // 2^27
+constexpr float kHalfHomeBudget = 268435456.f;     // 2^28
+constexpr float kFullHomeBudget = 2147483648.f;    // 2^31
 static_assert(kMaxTypes <= 64, "a type must fit the low 6 bits of a staged c_j");
 
 // The 27 neighbour images.
@@ -374,6 +380,8 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
   const int n_seg = H.n_seg;
   const int iters = H.iters;
   const int n_grp_q = (nA + kQ - 1) / kQ;
+  // largest home-side partial of one slice (see kHalfHomeBudget)
+  const float home_max = (kHalf ? kHalfHomeBudget : kFullHomeBudget) / (float)max(1, (total + cap - 1) / cap);
   const float R = __builtin_sqrtf(rc2) + kWin;
   long long e_fix = 0;   // energy in units of 2^-24 kcal/mol: exact, order-independent sums
   unsigned long long pass_count = 0, filt_count = 0, slot_count = 0, lane_count = 0;
@@ -761,10 +769,9 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
               float* dst = &a.facc[(int64_t)c * a.n + s];
               *dst = P0 == 0 ? r3[c] : *dst + r3[c];
             } else {
-              // the half shell's per-atom sum gathers up to 15 partials (this one, the home
-              // cell's neighbour-side sum, 13 flushes of other workgroups): each stays below
-              // 2^27 kcal/mol/A, so their sum cannot leave the 2^31 range of the fixed point
-              if (kHalf && !(fabsf(r3[c]) < kHalfPartialMax)) st |= MD_STATUS_FIXED_OVERFLOW;
+              // one of the slice count's home-side partials of this atom: within its share
+              // of the fixed point's range (kHalfHomeBudget, kFullHomeBudget)
+              if (!(fabsf(r3[c]) < home_max)) st |= MD_STATUS_FIXED_OVERFLOW;
               const long long qv = to_fixed(r3[c], st);
               long long* dst = &a.acc64[(int64_t)c * a.n + s];
               if (kHalf)
@@ -808,7 +815,7 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             // units of 2^-24 to the sums' 2^-32, each partial below 2^27 kcal/mol/A (2^51
-            // units), as the home side's
+            // units, kNbrPartialMax)
             const long long v = sJ[3 * (dst - P0) + c];
             if (v >= (1ll << 51) || v < -(1ll << 51)) st |= MD_STATUS_FIXED_OVERFLOW;
             else if (v != 0)

@@ -630,3 +630,109 @@ def test_fp32_kernel_variants(gpu, case, shell):
     assert ok.all()
     if nb == 0:
         assert e == pytest.approx(r.energy, rel=1e-6, abs=1e-6)
+
+
+_TINY = [((24.5, 24.5, 24.5), 150, 1), ((36.5, 36.5, 36.5), 300, 2), ((24.5, 37.0, 50.0), 260, 3),
+         ((40.0, 26.0, 31.0), 5, 4)]
+_COMPACT_FORMS = [(0, "half shell, 2 batches per drain"),
+                  (api.PAIR_DRAIN(1), "half shell, 1 batch per drain"),
+                  (api.PAIR_FULL_SHELL, "full shell")]
+
+
+@pytest.mark.parametrize("box,n,seed", _TINY)
+@pytest.mark.parametrize("form", range(len(_COMPACT_FORMS)))
+def test_fp32_compacted_tiny_grids(gpu, box, n, seed, form):
+    """The float32 compacted kernel on the grids the oracle's cell list is pinned on:
+    2x2x2 and 3x3x3 cells, a mixed 2x3x4 grid (two images of one cell on some axes only,
+    the n_d = 2 case of the 27-cell stencil) and a 5-atom system on a 3x2x2 grid."""
+    flags, what = _COMPACT_FORMS[form]
+    _say("case: float32 compacted kernel, tiny system", box, n, seed, what)
+    pos, t, q, p = _random_system(n, box, seed)
+    f, e, ws, cnt = run(p, pos, t, q, gpu, flags=flags | api.DIAG_COUNTERS)
+    r, err = _check_fp32(p, pos, t, q, f, e, cnt)
+    band, nb = oracle.band_atoms(p, pos, BAND)
+    assert abs(api.read_diag(ws)[2] - r.n_pairs) <= nb
+    assert api.read_status(ws) == 0
+
+
+def _cutoff_pairs():
+    """Four pairs in a 40 A box, each atom at least 20 A from every atom of another pair:
+    exactly r_cut apart inside the box and through the x face (both excluded by the strict
+    test u < rc^2), and one float32 step closer than r_cut, inside and through the face
+    (both included). Every coordinate and every displacement is exact in float32."""
+    x_in = float(np.nextafter(np.float32(15.0), np.float32(0.0)))
+    x_face = float(np.nextafter(np.float32(28.5), np.float32(40.0)))
+    pos = np.array([[3.0, 5.0, 5.0], [15.0, 5.0, 5.0],          # 12 A exactly
+                    [3.0, 25.0, 5.0], [x_in, 25.0, 5.0],         # just inside
+                    [0.5, 5.0, 25.0], [28.5, 5.0, 25.0],         # 12 A through the face
+                    [0.5, 25.0, 25.0], [x_face, 25.0, 25.0]])    # just inside, through it
+    t = np.array([0, 1, 0, 1, 1, 0, 1, 0], np.int32)
+    q = np.array([0.5, -0.4, 0.3, 0.6, -0.2, 0.5, 0.4, 0.4])
+    return pos, t, q
+
+
+@pytest.mark.parametrize("switch", [10.0, 12.0])
+def test_exact_cutoff_pairs(gpu, switch):
+    """Algorithm 1's strict cutoff on pairs exactly r_cut apart and one float32 step
+    inside, with the switch on and off, in both shells of the float32 kernel and in
+    float64: partner counts 0 / 1 exactly, zero force on the excluded pairs."""
+    _say("case: pairs at and just inside r_cut, r_switch", switch)
+    pos, t, q = _cutoff_pairs()
+    p = dict(box=(40.0, 40.0, 40.0), r_cut=12.0, r_switch=switch, coulomb_k=W.COULOMB_K,
+             sigma=np.array([2.5, 3.0]), epsilon=np.array([0.05, 0.1]), flags=0)
+    r = oracle.forces(p, pos, t, q, "bruteforce")
+    scale = oracle.forces(dict(p, r_switch=12.0), pos, t, q, "bruteforce")
+    assert list(r.count) == [0, 0, 1, 1, 0, 0, 1, 1]
+    for flags, double in ((0, False), (api.PAIR_FULL_SHELL, False), (0, True)):
+        f, e, ws, cnt = run(p, pos, t, q, gpu, double=double, flags=flags | api.DIAG_COUNTERS)
+        _say("flags", flags, "double", double, "counts", cnt.tolist())
+        assert list(cnt) == [0, 0, 1, 1, 0, 0, 1, 1], (flags, double)
+        assert np.all(f[[0, 1, 4, 5]] == 0.0), (flags, double)
+        # errors on the scale of the unswitched pair (the switch is near 0 at r_cut)
+        tol = 1e-12 if double else 1e-5
+        for i in (2, 3, 6, 7):
+            assert np.linalg.norm(f[i] - r.force[i]) <= tol * np.linalg.norm(scale.force[i]), (i, flags)
+        assert abs(e - r.energy) <= tol * abs(scale.energy), (flags, double)
+        assert api.read_diag(ws)[2] == 2
+
+
+def test_overflow_bound_follows_slices(gpu):
+    """The half shell bounds an atom's home-side partials by 2^28 / S kcal/mol/A, S being
+    the LDS slices of its home cell's neighbour list, so its 14 neighbour-side partials
+    (each below 2^27) and S home-side ones cannot wrap the 2^31 fixed-point range. A pair
+    force of 1.1e8 along x lies between 2^28 / 3 and 2^27: it sets the overflow bit in a
+    system whose neighbour lists take three slices, and not in one that takes one."""
+    _say("case: 1.1e8 kcal/mol/A pair force, three slices and one slice")
+    p_of = lambda L: dict(box=(L, L, L), r_cut=12.0, r_switch=10.0, coulomb_k=W.COULOMB_K,
+                          sigma=np.array([1.0, 1.2]), epsilon=np.array([0.05, 0.1]), flags=0)
+    target = 1.1e8
+    lo, hi = 0.1, 0.6                  # |F| of a type-0 pair falls with r on [0.1, 0.6] A
+    for _ in range(80):
+        mid = 0.5 * (lo + hi)
+        f = oracle.pair_terms(p_of(24.5), 0, 0, 0.0, 0.0, mid * mid)[1] * mid
+        lo, hi = (mid, hi) if f > target else (lo, mid)
+    r = np.float32(lo)
+    rng = np.random.default_rng(31)
+    # 4,096 atoms on a 16^3 lattice in a 24.5 A box (2x2x2 cells): 14 x 512 atoms in each
+    # home cell's half-shell list, three LDS slices
+    dense = np.mod(_lattice_blob(rng, np.full(3, 0.4), 16, 1.53, 0.05), 24.5)
+    # 60 atoms in a 40 A box (3x3x3 cells): one slice
+    sparse = np.mod(_lattice_blob(rng, np.full(3, 1.0), 4, 9.5, 0.5), 40.0)[:60]
+    for pos, L, want in ((dense, 24.5, True), (sparse, 40.0, False)):
+        pos = pos.astype(np.float32)
+        pos[1] = pos[0] + np.array([r, 0, 0], np.float32)   # the close pair, along x
+        n = len(pos)
+        t = np.zeros(n, np.int32)
+        q = np.zeros(n)
+        p = p_of(L)
+        f, e, ws, _ = run(p, pos.astype(np.float64), t, q, gpu)
+        st = api.read_status(ws)
+        _say("box", L, "atoms", n, "status", st, "force on the pair", f[0, 0], f[1, 0])
+        assert abs(f[0, 0]) > 2 ** 28 / 3 and abs(f[0, 0]) < 2 ** 27
+        assert bool(st & api.STATUS_FIXED_OVERFLOW) == want, (L, st)
+        if not want:
+            # the pair's own forces (the other atoms carry ~1e-6 kcal/mol/A, below the
+            # 2^-24 rounding of the neighbour-side sums)
+            ref = oracle.forces(p, pos, t, q, "bruteforce")
+            err = force_errors(f[:2], ref.force[:2], ref.abs_sum[:2])
+            assert err["max_norm"] <= 1e-5 and err["rms"] <= 1e-5, err
