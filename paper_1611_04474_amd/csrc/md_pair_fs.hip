@@ -817,7 +817,8 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
             // units of 2^-24 to the sums' 2^-32, each partial below 2^27 kcal/mol/A (2^51
             // units, kNbrPartialMax)
             const long long v = sJ[3 * (dst - P0) + c];
-            if (v >= (1ll << 51) || v < -(1ll << 51)) st |= MD_STATUS_FIXED_OVERFLOW;
+            constexpr long long kLim = (long long)kNbrPartialMax << 24;
+            if (v >= kLim || v < -kLim) st |= MD_STATUS_FIXED_OVERFLOW;
             else if (v != 0)
               global_add(&a.acc64[(int64_t)c * a.n + src],
                          (long long)((unsigned long long)v << 8));
