@@ -26,7 +26,8 @@
  *     the sigma/epsilon arrays inside md_params, are host pointers.
  *   - The caller owns every buffer, including the workspace; the library allocates
  *     no device memory and keeps no global state, so calls with distinct
- *     workspaces may run concurrently.
+ *     workspaces may run concurrently. The one exception is md_forces_f32_noalloc,
+ *     which uses a workspace of the library's own, one per device.
  *   - Argument checks are synchronous and return an md_status; nothing is enqueued
  *     when a check fails. Work is enqueued on `stream` (a hipStream_t, or NULL for
  *     the default stream) and outputs are valid once the stream reaches the call.
@@ -146,6 +147,28 @@ md_status md_forces_f32_stages(const md_params* p, int64_t n_atoms, const float*
                                const int32_t* d_type, const float* d_charge, float* d_force,
                                double* d_energy, void* d_ws, size_t ws_bytes,
                                uint32_t stages, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): md_forces_f32 with the library's own
+ * workspace instead of a caller-owned one, so the call allocates nothing.
+ *   - The workspace is a static device array of MD_NOALLOC_MAX_WORKSPACE_BYTES (32 MiB)
+ *     per device, created when the library's code is first used on that device and held
+ *     until the process ends. Its device address is looked up once per device, on the
+ *     first call with that device current.
+ *   - Systems whose md_workspace_bytes(p, n_atoms, 0) exceeds that size are rejected with
+ *     MD_ERR_CAPACITY before anything is enqueued (at 8 atom types about 280,000 atoms
+ *     of the 0.1 atoms/A^3 systems). Other argument errors as for md_forces_f32.
+ *   - Every call on one device uses that device's one array: calls that overlap on one
+ *     device (other streams, other host threads) race and give undefined results;
+ *     serialise them. Each call starts from whatever the previous one left, which is
+ *     valid: nothing in the workspace needs initialisation.
+ *   - d_status, if not NULL, is caller-owned device memory (4 bytes, 4-byte aligned) that
+ *     receives the call's device status word (MD_STATUS_* bits) in stream order.
+ * Other arguments, outputs and the asynchrony as for md_forces_f32. */
+#define MD_NOALLOC_MAX_WORKSPACE_BYTES (32u << 20)
+md_status md_forces_f32_noalloc(const md_params* p, int64_t n_atoms, const float* d_pos,
+                                const int32_t* d_type, const float* d_charge, float* d_force,
+                                double* d_energy, uint32_t* d_status, void* stream);
 
 /* Same as md_forces_f32 with float64 positions, charges, forces and pair
  * arithmetic throughout (per-atom sums in float64, fixed order). */

@@ -92,6 +92,8 @@ def lib():
         L.md_forces_f32_stages.restype = C.c_int
         L.md_forces_batched.argtypes = [C.POINTER(_System), C.c_int32, vp]
         L.md_forces_batched.restype = C.c_int
+        L.md_forces_f32_noalloc.argtypes = [pp, C.c_int64, vp, vp, vp, vp, vp, vp, vp]
+        L.md_forces_f32_noalloc.restype = C.c_int
         L.md_run_vv_f32.argtypes = [pp, C.c_int64, vp, vp, vp, vp, vp, vp, C.c_double, C.c_int32,
                                     vp, vp, C.c_size_t, vp]
         L.md_run_vv_f32.restype = C.c_int
@@ -108,7 +110,7 @@ def lib():
 
 
 EXPORTED = ("md_workspace_bytes", "md_forces_f32", "md_forces_f32_stages", "md_forces_f64",
-            "md_forces_batched", "md_run_vv_f32",
+            "md_forces_batched", "md_forces_f32_noalloc", "md_run_vv_f32",
             "md_read_device_status", "md_read_diag", "md_read_clock", "md_workspace_layout",
             "md_status_string")
 
@@ -240,6 +242,24 @@ def forces(params, pos, types, charges, *, flags=None, force=None, energy=None, 
     if rc != MD_OK:
         raise MDError(rc, "md_forces_f64" if dp else "md_forces_f32")
     return force, energy
+
+
+NOALLOC_MAX_WORKSPACE_BYTES = 32 << 20
+
+
+def forces_noalloc(params, pos, types, charges, force, energy, status=None, stream=None):
+    """md_forces_f32_noalloc: one float32 evaluation in the library's own per-device
+    workspace, allocating nothing. pos, types, charges, force [n,3] float32, energy [1]
+    float64 and the optional status (int32 [1]) are caller-allocated device tensors."""
+    p = _as_params(params)
+    n = int(pos.shape[0])
+    rc = lib().md_forces_f32_noalloc(p.ref(), n, C.c_void_p(pos.data_ptr()),
+                                     C.c_void_p(types.data_ptr()), C.c_void_p(charges.data_ptr()),
+                                     C.c_void_p(force.data_ptr()), C.c_void_p(energy.data_ptr()),
+                                     C.c_void_p(status.data_ptr() if status is not None else 0),
+                                     _stream_ptr(stream))
+    if rc != MD_OK:
+        raise MDError(rc, "md_forces_f32_noalloc")
 
 
 STAGE_BIN, STAGE_PAIR, STAGE_FINALIZE, STAGE_ALL = 1, 2, 4, 7

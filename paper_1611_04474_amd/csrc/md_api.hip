@@ -3,9 +3,44 @@
 #include <math.h>
 #include <string.h>
 
+#include <atomic>
+#include <mutex>
+
 #include "md_common.hpp"
 
 namespace md {
+
+// Workspace of md_forces_f32_noalloc: one per device, held from the library's first use
+// on that device until the process ends. Host code reaches it only through the device
+// address that hipGetSymbolAddress returns for the current device (noalloc_scratch).
+constexpr size_t kScratchBytes = (size_t)MD_NOALLOC_MAX_WORKSPACE_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::atomic<void*> g_scratch[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+// Device address of the current device's scratch array, looked up once per device.
+static md_status noalloc_scratch(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return MD_ERR_HIP;
+  if (dev < 0 || dev >= kMaxDevices) return MD_ERR_CAPACITY;
+  void* ptr = g_scratch[dev].load(std::memory_order_acquire);
+  if (!ptr) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    ptr = g_scratch[dev].load(std::memory_order_relaxed);
+    if (!ptr) {
+      if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+        return MD_ERR_HIP;
+      g_scratch[dev].store(ptr, std::memory_order_release);
+    }
+  }
+  *out = ptr;
+  return MD_OK;
+}
+
+// Copies the status word of a workspace to caller memory, in stream order.
+__global__ void k_copy_status(const WsHeader* hdr, uint32_t* out) { *out = hdr->status; }
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -268,6 +303,31 @@ md_status md_forces_f64(const md_params* p, int64_t n_atoms, const double* d_pos
                         double* d_energy, void* d_ws, size_t ws_bytes, void* stream) {
   return md::forces_impl<double>(p, n_atoms, d_pos, d_type, d_charge, d_force, d_energy, d_ws,
                                  ws_bytes, stream);
+}
+
+md_status md_forces_f32_noalloc(const md_params* p, int64_t n_atoms, const float* d_pos,
+                                const int32_t* d_type, const float* d_charge, float* d_force,
+                                double* d_energy, uint32_t* d_status, void* stream) {
+  md::Plan pl;
+  // every argument check, the size limit included, before any HIP call
+  md_status s = md::make_plan(p, n_atoms, 4, &pl);
+  if (s != MD_OK) return s;
+  if (pl.total > md::kScratchBytes) return MD_ERR_CAPACITY;
+  if (d_status && ((uintptr_t)d_status & 3)) return MD_ERR_INVALID_ARG;
+  // pointer checks of md_forces_f32 (the workspace is checked against a stand-in with the
+  // scratch array's size and alignment)
+  s = md::check_call<float>(p, n_atoms, d_pos, d_type, d_charge, d_force, d_energy,
+                            (const void*)(uintptr_t)256, md::kScratchBytes, &pl);
+  if (s != MD_OK) return s;
+  void* ws = nullptr;
+  s = md::noalloc_scratch(&ws);
+  if (s != MD_OK) return s;
+  s = md::forces_impl<float>(p, n_atoms, d_pos, d_type, d_charge, d_force, d_energy, ws,
+                             md::kScratchBytes, stream);
+  if (s != MD_OK || !d_status) return s;
+  hipLaunchKernelGGL(md::k_copy_status, dim3(1), dim3(1), 0, (hipStream_t)stream,
+                     (const md::WsHeader*)ws, d_status);
+  return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
 }
 
 md_status md_run_vv_f32(const md_params* p, int64_t n_atoms, float* d_pos, float* d_vel,

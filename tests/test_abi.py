@@ -158,3 +158,25 @@ def test_motion_update_argument_errors_are_synchronous():
     assert call(energies=4100) == -1       # an FP64 array needs 8-byte alignment
     assert call(ws_bytes=need - 1) == -3
     assert call(p=api.Params.from_dict(dict(base, r_switch=13.0))) == -1
+
+
+def test_noalloc_rejects_before_any_device_call():
+    """md_forces_f32_noalloc checks every argument, and the size of the system against its
+    32 MiB per-device workspace, before it touches the device (these calls run without one)."""
+    L = api.lib()
+    base = W.small_system().params()
+    p = api.Params.from_dict(base)
+    f = L.md_forces_f32_noalloc
+    ptr = C.c_void_p(4096)
+    # n large enough that the workspace exceeds the array: MD_ERR_CAPACITY
+    n_big = 400_000
+    big = api.Params.from_dict(dict(base, box=(160.0, 160.0, 160.0)))
+    assert api.workspace_bytes(big, n_big) > api.NOALLOC_MAX_WORKSPACE_BYTES
+    assert f(big.ref(), n_big, ptr, ptr, ptr, ptr, ptr, None, None) == -6
+    # ordinary argument errors as for md_forces_f32
+    assert f(p.ref(), -1, ptr, ptr, ptr, ptr, ptr, None, None) == -1
+    assert f(p.ref(), 10, ptr, ptr, ptr, None, ptr, None, None) == -1
+    assert f(p.ref(), 10, ptr, ptr, ptr, ptr, C.c_void_p(4100), None, None) == -1   # energy alignment
+    assert f(p.ref(), 10, ptr, ptr, ptr, ptr, ptr, C.c_void_p(4098), None) == -1    # status alignment
+    bad = api.Params.from_dict(dict(base, box=(20.0, 30.0, 30.0)))
+    assert f(bad.ref(), 10, ptr, ptr, ptr, ptr, ptr, None, None) == -2
