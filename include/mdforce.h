@@ -110,7 +110,7 @@ typedef struct {
  * md_forces_f64 (double_precision = 1) for n_atoms atoms with p->flags (the flags
  * choose the pair kernel, whose per-atom buffers differ in size). Returns 0 when the
  * parameters are invalid. The workspace must be 256-byte aligned; its contents
- * need no initialisation. Between calls they are scratch, except that the float32
+ * need no initialisation. Between calls they are scratch, except that the
  * compacted kernel leaves each home cell's measured time there: the next call on the
  * same workspace and cell grid (of at most 1024 cells) launches the cells longest first
  * by those times. They only steer scheduling, never a result, so any contents are
@@ -170,8 +170,14 @@ md_status md_forces_f32_noalloc(const md_params* p, int64_t n_atoms, const float
                                 const int32_t* d_type, const float* d_charge, float* d_force,
                                 double* d_energy, uint32_t* d_status, void* stream);
 
-/* Same as md_forces_f32 with float64 positions, charges, forces and pair
- * arithmetic throughout (per-atom sums in float64, fixed order). */
+/* Same as md_forces_f32 with float64 positions, charges, forces and pair arithmetic
+ * throughout (the FP64-everywhere form of Section 2.1's computation): the same compacted
+ * kernel, instantiated for float64, with the cutoff test on a plain float64 evaluation of
+ * dx^2 + dy^2 + dz^2. Per-atom sums and the energy are exact integer sums of a two-word
+ * fixed point (hi 2^-20 + lo 2^-72 kcal/mol/A), so results are the same bits on every run;
+ * MD_PAIR_FULL_SHELL selects the full shell as in float32. With MD_PAIR_PREDICATED (or
+ * MD_ACCUM_F32_ATOMIC) the predicated kernel runs instead, its per-atom partials added in
+ * float64 in a fixed slot order (float32 atomics with MD_ACCUM_F32_ATOMIC). */
 md_status md_forces_f64(const md_params* p, int64_t n_atoms, const double* d_pos,
                         const int32_t* d_type, const double* d_charge, double* d_force,
                         double* d_energy, void* d_ws, size_t ws_bytes, void* stream);
@@ -241,8 +247,8 @@ md_status md_read_diag(const void* d_ws, void* stream, uint64_t counters[5]);
  * constant 100 MHz counter over its run, and *ghz is the ratio of the two sums times
  * 0.1, i.e. the clock averaged over workgroup time. Scaling a peak rate quoted at the
  * nominal clock by *ghz / nominal gives the peak at the clock the kernel really ran at.
- * *ghz is 0 when no compacted pair kernel has run since the last binning (the predicated
- * and the float64 kernels do not count). Errors: MD_ERR_INVALID_ARG for a null pointer,
+ * *ghz is 0 when no compacted pair kernel (float32 or float64) has run since the last
+ * binning (the predicated kernel does not count). Errors: MD_ERR_INVALID_ARG for a null pointer,
  * MD_ERR_HIP if the copy fails. Synchronises `stream`. */
 md_status md_read_clock(const void* d_ws, void* stream, double* ghz);
 

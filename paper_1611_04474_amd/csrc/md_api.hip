@@ -71,6 +71,13 @@ static md_status check_params(const md_params* p) {
   return MD_OK;
 }
 
+// The compacted pair kernel serves every call except MD_PAIR_PREDICATED and float64 with
+// float32 atomics, which take the predicated kernel.
+static bool uses_compact(const md_params* p, int real_bytes) {
+  return !(p->flags & MD_PAIR_PREDICATED) &&
+         !(real_bytes == 8 && (p->flags & MD_ACCUM_F32_ATOMIC));
+}
+
 // Grid rule: n_d = floor(L_d / r_cut), one cell fewer when L_d/n_d exceeds r_cut by
 // less than 1e-3 A (so rounding of a coordinate at a cell face never hides a pair),
 // and at least 2 cells per axis (L >= 2 r_cut keeps the minimum image unique).
@@ -105,10 +112,12 @@ md_status make_plan(const md_params* p, int64_t n, int real_bytes, Plan* pl) {
   pl->off_type = o;      o = align_up(o + sizeof(int32_t) * nn);
   pl->off_perm = o;      o = align_up(o + sizeof(int32_t) * nn);
   // per-atom partials: 27 slots x 3 components for the predicated kernel, or three
-  // 64-bit fixed-point sums for the float32 compacted kernel
-  const bool compact = real_bytes == 4 && !(p->flags & MD_PAIR_PREDICATED);
+  // 64-bit fixed-point sums (float32) or three two-word ones (float64) for the compacted
+  // kernel
+  const bool compact = uses_compact(p, real_bytes);
   pl->off_part = o;
-  o = align_up(o + (compact ? sizeof(long long) * 3 * nn : (size_t)real_bytes * kSlots * 3 * nn));
+  o = align_up(o + (compact ? sizeof(long long) * 3 * (real_bytes / 4) * nn
+                            : (size_t)real_bytes * kSlots * 3 * nn));
   pl->off_facc = o;      o = align_up(o + sizeof(float) * 3 * nn);
   pl->off_epart = o;     o = align_up(o + sizeof(double) * pl->n_tasks);
   pl->off_lj = o;        o = align_up(o + (size_t)real_bytes * 2 * kMaxTypes * kMaxTypes);
@@ -185,7 +194,7 @@ SysArgs<Real> make_args(const md_params* p, const Plan& pl, int64_t n, const Rea
   a.inv_sw = p->r_switch < p->r_cut ? (Real)(1.0 / (rc2 - rs2)) : Real(0);
   a.coulomb_k = (Real)p->coulomb_k;
   a.flags = p->flags;
-  a.compact = (sizeof(Real) == 4 && !(p->flags & MD_PAIR_PREDICATED)) ? 1 : 0;
+  a.compact = uses_compact(p, (int)sizeof(Real)) ? 1 : 0;
   a.half_shell =
       (a.compact && !(p->flags & (MD_ACCUM_F32_ATOMIC | MD_PAIR_FULL_SHELL))) ? 1 : 0;
   return a;
@@ -276,8 +285,7 @@ md_status md_workspace_layout(const md_params* p, int64_t n_atoms, int double_pr
   out->pair_count = pl.off_paircount;
   out->energy_partials = pl.off_epart;
   out->n_energy_partials =
-      (!double_precision && !(p->flags & MD_PAIR_PREDICATED)) ? pl.n_cells * md::kFsSplit
-                                                             : pl.n_tasks;
+      md::uses_compact(p, double_precision ? 8 : 4) ? pl.n_cells * md::kFsSplit : pl.n_tasks;
   out->z_split = pl.off_zsplit;
   out->total_bytes = pl.total;
   return MD_OK;

@@ -89,9 +89,8 @@ __device__ inline void clear_atom(const SysArgs<Real>& a, int64_t i) {
     a.facc[2 * a.n + i] = 0.f;
   }
   if (a.half_shell) {
-    a.acc64[i] = 0;
-    a.acc64[a.n + i] = 0;
-    a.acc64[2 * a.n + i] = 0;
+    // three sums, of one 64-bit word each in float32 and two in float64
+    for (int c = 0; c < (sizeof(Real) == 8 ? 6 : 3); ++c) a.acc64[c * a.n + i] = 0;
   }
   if (a.flags & MD_DIAG_COUNTERS) a.paircount[a.n + i] = 0;
 }

@@ -100,7 +100,9 @@ struct SysArgs {
   double* epart;               // [n_tasks]
   Real* lj;                    // [n_types^2][2] (c12, c6)
   int32_t* paircount;          // [2][n]: caller order (after finalize), sorted order (pass)
-  long long* acc64;            // [3][n] per-atom fixed-point sums (compacted kernel)
+  long long* acc64;            // per-atom fixed-point sums of the compacted kernel: float32
+                               // [3][n] (2^-32 kcal/mol/A); float64 [2][3][n], the high
+                               // words (2^-20) then the low words (2^-72)
   int32_t* bhist;              // [bin_blocks][n_cells] per-block cell counts (offsets in place
                                // after k_bin_colscan, for grids of more than 1024 cells)
   uint32_t* bstat;             // [bin_blocks] per-block status bits
@@ -118,7 +120,7 @@ struct SysArgs {
   Real coulomb_k;
   uint32_t flags;
   int compact;                 // 1: per-atom sums come from the compacted pair kernel (acc64,
-                               //    or facc with MD_ACCUM_F32_ATOMIC)
+                               //    or, float32 only, facc with MD_ACCUM_F32_ATOMIC)
   int half_shell;              // 1: the compacted kernel visits each pair once and adds
                                //    into acc64 with integer atomics (acc64 starts at zero)
 };
@@ -161,7 +163,8 @@ template <typename Real>
 hipError_t launch_pair(const SysArgs<Real>& a, hipStream_t stream);
 template <typename Real>
 hipError_t launch_finalize(const SysArgs<Real>& a, hipStream_t stream);
-hipError_t launch_pair_fs(const SysArgs<float>& a, hipStream_t stream);
+template <typename Real>
+hipError_t launch_pair_fs(const SysArgs<Real>& a, hipStream_t stream);
 
 // Batched float32 launchers. Every system of the batch has n > 0, uses the LDS-histogram
 // binning (bin_blocks > 0), the compacted kernel, and the same flags and

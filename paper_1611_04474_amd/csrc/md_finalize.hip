@@ -1,11 +1,13 @@
 // Finalize: per-atom force sums and the total energy.
 //
-// k_finalize adds the 27 partial forces of each sorted atom (14 as a home atom, 13
-// as a neighbour) and writes the result in the caller's atom order. On the float32
-// path the partials are converted to 64-bit fixed point (one unit = 2^-32 kcal/mol/A,
-// round to nearest even) and summed as integers, so the per-atom total does not
-// depend on any summation order; an out-of-range value sets MD_STATUS_FIXED_OVERFLOW.
-// On the float64 path the partials are added in slot order.
+// k_finalize writes each sorted atom's force in the caller's atom order. After the
+// compacted kernel it converts the per-atom fixed-point sums to float: float32 from one
+// 64-bit word (2^-32 kcal/mol/A), float64 from two (hi 2^-20 + lo 2^-72). After the
+// predicated kernel it adds the 27 partial forces of the atom (14 as a home atom, 13 as a
+// neighbour): in float32 converted to 64-bit fixed point (one unit = 2^-32 kcal/mol/A,
+// round to nearest even) and summed as integers, so the per-atom total does not depend on
+// any summation order (an out-of-range value sets MD_STATUS_FIXED_OVERFLOW); in float64
+// in slot order.
 //
 // The energy block adds the per-workgroup float64 energy partials in a fixed tree order;
 // it is one more block of the same launch.
@@ -47,8 +49,13 @@ __device__ inline void finalize(const SysArgs<Real>& a, int64_t blk) {
     Real v;
     if (a.flags & MD_ACCUM_F32_ATOMIC) {
       v = (Real)a.facc[(int64_t)c * a.n + s];
-    } else if (a.compact) {
+    } else if (a.compact && sizeof(Real) == 4) {
       v = (Real)(__ll2float_rn(a.acc64[(int64_t)c * a.n + s]) * 2.3283064365386963e-10f);
+    } else if (a.compact) {
+      // two-word sum: hi 2^-20 + lo 2^-72 (hi exact in float64, one rounding of lo, one of
+      // the sum)
+      v = (Real)((double)a.acc64[(int64_t)c * a.n + s] * 9.5367431640625e-07 +
+                 (double)a.acc64[(int64_t)(3 + c) * a.n + s] * 2.117582368135751e-22);
     } else if (sizeof(Real) == 4) {
       v = (Real)fixed_sum(reinterpret_cast<const float*>(a.part), a.n, c, s, st);
     } else {

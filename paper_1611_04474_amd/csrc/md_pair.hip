@@ -20,8 +20,8 @@
 // neighbour tile and evaluates the force under the cutoff predicate, so lanes whose
 // candidate fails idle through the force arithmetic -- the conditional data flow that
 // leaves the force unit of the HLS design underused (Section 5.1). It serves the
-// float64 path (bit-for-bit the oracle's predicate) and, in float32, the
-// MD_PAIR_PREDICATED comparison with the compacted kernel.
+// MD_PAIR_PREDICATED comparison with the compacted kernel, in float32 and in float64, and
+// float64 with per-atom float32 atomics (MD_ACCUM_F32_ATOMIC).
 #include "md_common.hpp"
 
 namespace md {
@@ -315,9 +315,7 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_predicated(SysArgs<Real> 
 template <typename Real>
 hipError_t launch_pair(const SysArgs<Real>& a, hipStream_t stream) {
   if (a.n == 0) return hipSuccess;
-  if constexpr (sizeof(Real) == 4) {
-    if (a.compact) return launch_pair_fs(a, stream);
-  }
+  if (a.compact) return launch_pair_fs<Real>(a, stream);
   const int64_t blocks = 8 * ((a.n_tasks + 7) / 8);
   const size_t shmem = sizeof(Real) * 2 * a.n_types * a.n_types;
   const bool swc = !(a.flags & MD_COULOMB_TRUNCATED);

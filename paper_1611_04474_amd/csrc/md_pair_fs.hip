@@ -22,10 +22,10 @@
 //              u < rc^2, and the force summed on the home atom in registers.
 // Each home atom is owned by one wave and its sum runs in a fixed order: the 64 lane
 // partials are added in one fixed order (wave halves and rows exchanging partial sums,
-// then a DPP butterfly within a row) and the total converted exactly to 64-bit fixed
-// point (2^-32 kcal/mol/A); lane energies are summed in 64-bit fixed point
-// (2^-24 kcal/mol), so the energy does not depend on how groups of home atoms were
-// spread over the waves either.
+// then a butterfly within a row) and the total converted exactly to 64-bit fixed point
+// (2^-32 kcal/mol/A); lane energies are summed in 64-bit fixed point (2^-24 kcal/mol),
+// so the energy does not depend on how groups of home atoms were spread over the waves
+// either.
 //
 // Two shells:
 //   full (kHalf = false) -- every pair is evaluated from both of its atoms, as in
@@ -38,6 +38,17 @@
 //              does not depend on the order of the adds), and the accumulators go to the
 //              per-atom sums with 64-bit global integer atomics when the workgroup is
 //              done. Integer addition is associative: the same bits on every run.
+//
+// Two precisions, one template (Real):
+//   float  -- the hot path. The staged c_j carries the atom type in its low mantissa bits;
+//             the neighbour-side force is rounded to 2^-24 units in one 64-bit integer.
+//   double -- float64 throughout: the same staging, segments, windows, filter, FIFOs and
+//             force passes, with the squared distance rounded term by term as a plain
+//             float64 evaluation of dx^2 + dy^2 + dz^2 (so the cutoff decides like the
+//             definition). Per-atom sums and energies use a two-word fixed point,
+//             v = hi 2^-20 + lo 2^-72 (both int64), exact for every float64 partial above
+//             2^-20 kcal/mol/A, so they too are the same bits on every run; types live in
+//             an LDS array of their own.
 #include <type_traits>
 
 #include "md_common.hpp"
@@ -71,6 +82,41 @@ constexpr float kNbrPartialMax = 134217728.f;      // 2^27
 constexpr float kHalfHomeBudget = 268435456.f;     // 2^28
 constexpr float kFullHomeBudget = 2147483648.f;    // 2^31
 static_assert(kMaxTypes <= 64, "a type must fit the low 6 bits of a staged c_j");
+
+// Staged atom (x, y, z, c_j) and LJ (c12, c6) vector types of each precision.
+template <typename Real>
+using V4 = std::conditional_t<sizeof(Real) == 4, float4, double4>;
+template <typename Real>
+using V2 = std::conditional_t<sizeof(Real) == 4, float2, double2>;
+// 64-bit words per component of a per-atom fixed-point sum: 1 (float), 2 (double: hi, lo)
+template <typename Real>
+constexpr int kAccWords = sizeof(Real) == 8 ? 2 : 1;
+
+__device__ inline float mad(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ inline double mad(double a, double b, double c) { return fma(a, b, c); }
+__device__ inline float vmin(float a, float b) { return fminf(a, b); }
+__device__ inline double vmin(double a, double b) { return fmin(a, b); }
+__device__ inline float vmax(float a, float b) { return fmaxf(a, b); }
+__device__ inline double vmax(double a, double b) { return fmax(a, b); }
+__device__ inline float vsqrt(float a) { return __builtin_sqrtf(a); }
+__device__ inline double vsqrt(double a) { return sqrt(a); }
+__device__ inline float4 mk4(float x, float y, float z, float w) { return make_float4(x, y, z, w); }
+__device__ inline double4 mk4(double x, double y, double z, double w) {
+  return make_double4(x, y, z, w);
+}
+template <typename Real>
+__device__ inline V2<Real> mk2(Real x, Real y) {
+  if constexpr (sizeof(Real) == 4) return make_float2(x, y); else return make_double2(x, y);
+}
+
+// Squared distance. float: fused, as the filter's test. double: each product and sum
+// rounded on its own, in the order ((dx^2 + dy^2) + dz^2) of a plain float64 evaluation.
+__device__ inline float dist2(float dx, float dy, float dz) {
+  return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+}
+__device__ inline double dist2(double dx, double dy, double dz) {
+  return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+}
 
 // The 27 neighbour images.
 __constant__ int8_t c_img[27][3] = {
@@ -113,29 +159,36 @@ struct Hdr {
   int next;         // next group of home atoms to hand out
 };
 
-// LDS layout in bytes: header | FIFOs | LJ (c12, c6) [nt^2] | (x, y, z, |r - o_g|^2 with
-// the type in its low bits) [cap] | q [cap], and for the half shell the neighbour-side
-// accumulators (x, y, z) int64 [cap] and, with counters, partner counts int32 [cap]
+// LDS layout in bytes: header | FIFOs | LJ (c12, c6) [nt^2] | (x, y, z, |r - o_g|^2, in
+// float32 with the type in its low bits) [cap] | q [cap] | (float64) type [cap], and for
+// the half shell the neighbour-side accumulators (x, y, z) x kAccWords int64 [cap] and,
+// with counters, partner counts int32 [cap]
 struct Lds {
-  int hdr, fifo, lj, f4, q, jacc, jcnt, total;
+  int hdr, fifo, lj, f4, q, typ, jacc, jcnt, total;
 };
 
 __host__ __device__ constexpr int align_up(int v, int a) { return (v + a - 1) / a * a; }
 
+template <typename Real>
 __host__ __device__ inline int slot_bytes(bool half, bool diag) {
-  return 20 + (half ? 24 + (diag ? 4 : 0) : 0);
+  constexpr int R = (int)sizeof(Real);
+  return 5 * R + (R == 8 ? 4 : 0) + (half ? 24 * kAccWords<Real> + (diag ? 4 : 0) : 0);
 }
 
+template <typename Real>
 __host__ __device__ inline Lds lds_layout(int cap, int n_types, bool half, bool diag, int drain) {
+  constexpr int R = (int)sizeof(Real);
   Lds L;
   L.hdr = 0;
   L.fifo = align_up(L.hdr + (int)sizeof(Hdr), 16);
   L.lj = align_up(L.fifo + 2 * kNW * kQ * fifo_entries(drain), 16);
-  L.f4 = align_up(L.lj + 8 * n_types * n_types, 16);
-  L.q = L.f4 + 16 * cap;
-  L.jacc = align_up(L.q + 4 * cap, 16);
-  L.jcnt = L.jacc + (half ? 24 * cap : 0);
-  L.total = half ? L.jcnt + (diag ? 4 * cap : 0) : L.q + 4 * cap;
+  L.f4 = align_up(L.lj + 2 * R * n_types * n_types, 4 * R);
+  L.q = L.f4 + 4 * R * cap;
+  L.typ = L.q + R * cap;
+  const int end = L.typ + (R == 8 ? 4 * cap : 0);
+  L.jacc = align_up(end, 16);
+  L.jcnt = L.jacc + (half ? 24 * kAccWords<Real> * cap : 0);
+  L.total = half ? L.jcnt + (diag ? 4 * cap : 0) : end;
   return L;
 }
 
@@ -171,6 +224,30 @@ __device__ inline long long round_to_i64(float x) {
   return __builtin_bit_cast(long long, t) - 0x4338000000000000ll;
 }
 
+// Two-word fixed point of the float64 path: v = hi 2^-20 + lo 2^-72 with hi = round(v 2^20)
+// and lo = round((v 2^20 - hi) 2^52), for |v| < 2^31. Both roundings go through the
+// 1.5 * 2^52 add of round_to_i64; v 2^20 - hi is exact (Sterbenz, or hi = 0), so the pair
+// holds v exactly whenever |v| >= 2^-20, and to 2^-73 otherwise.
+struct Fix2 {
+  long long hi, lo;
+};
+__device__ inline Fix2 to_fix2(double v) {
+  const double M = 6755399441055744.0;
+  const double s = v * 1048576.0;                       // 2^20, exact
+  const double t = s + M;                               // s rounded to an integer
+  const double r = (s - (t - M)) * 4503599627370496.0;  // remainder (|r| <= 0.5) times 2^52
+  const double t2 = r + M;
+  return Fix2{__builtin_bit_cast(long long, t) - 0x4338000000000000ll,
+              __builtin_bit_cast(long long, t2) - 0x4338000000000000ll};
+}
+// hi 2^-20 + lo 2^-72 with lo reduced into [0, 2^52) and its carry moved to hi.
+__device__ inline Fix2 normalize2(long long hi, long long lo) {
+  return Fix2{hi + (lo >> 52), lo & ((1ll << 52) - 1)};
+}
+__device__ inline double from_fix2(long long hi, long long lo) {
+  return (double)hi * 9.5367431640625e-07 + (double)lo * 2.117582368135751e-22;   // 2^-20, 2^-72
+}
+
 __device__ inline void lds_add(long long* p, long long v) {
   __hip_atomic_fetch_add(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v,
                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -186,27 +263,33 @@ __device__ inline void global_add(long long* p, long long v) {
 // The switch t = clamp((u - rs^2)/(rc^2 - rs^2), 0, 1), S = (1-t)^2 (1+2t), and
 // g = 12 t (1-t) / (rc^2 - rs^2) = -2 dS/du. With kSwitchCoulomb the whole energy is
 // switched, so at t = 1 both f and e are exactly zero.
-template <bool kSwitchCoulomb>
-__device__ inline float pair_f(float u, float c12, float c6, float qq, float rs2, float inv_sw,
-                               float sw12, float& e) {
-  const float rinv = __builtin_amdgcn_rsqf(u);
-  const float r2 = rinv * rinv;
-  const float r6 = r2 * r2 * r2;
-  const float c6r6 = c6 * r6;
-  const float elj = fmaf(c12 * r6, r6, -c6r6);      // c12/r^12 - c6/r^6
-  const float x6 = fmaf(2.f, elj, c6r6);            // (12 c12/r^12 - 6 c6/r^6) / 6
-  const float ec = qq * rinv;
-  const float t = __builtin_amdgcn_fmed3f((u - rs2) * inv_sw, 0.f, 1.f);
-  const float t2 = t * t;
-  const float S = fmaf(t2, fmaf(2.f, t, -3.f), 1.f);   // (1-t)^2 (1+2t)
-  const float g = (t - t2) * sw12;
-  if (kSwitchCoulomb) {
-    const float et = elj + ec;
-    e = S * et;
-    return fmaf(g, et, S * fmaf(6.f, x6, ec) * r2);
+template <bool kSwitchCoulomb, typename Real>
+__device__ inline Real pair_f(Real u, Real c12, Real c6, Real qq, Real rs2, Real inv_sw,
+                              Real sw12, Real& e) {
+  Real rinv, t;
+  if constexpr (sizeof(Real) == 4) {
+    rinv = __builtin_amdgcn_rsqf(u);
+    t = __builtin_amdgcn_fmed3f((u - rs2) * inv_sw, 0.f, 1.f);
+  } else {
+    rinv = 1.0 / sqrt(u);
+    t = fmin(fmax((u - rs2) * inv_sw, 0.0), 1.0);
   }
-  e = fmaf(S, elj, ec);
-  return fmaf(g, elj, fmaf(6.f * S, x6, ec) * r2);
+  const Real r2 = rinv * rinv;
+  const Real r6 = r2 * r2 * r2;
+  const Real c6r6 = c6 * r6;
+  const Real elj = mad(c12 * r6, r6, -c6r6);        // c12/r^12 - c6/r^6
+  const Real x6 = mad(Real(2), elj, c6r6);          // (12 c12/r^12 - 6 c6/r^6) / 6
+  const Real ec = qq * rinv;
+  const Real t2 = t * t;
+  const Real S = mad(t2, mad(Real(2), t, Real(-3)), Real(1));   // (1-t)^2 (1+2t)
+  const Real g = (t - t2) * sw12;
+  if (kSwitchCoulomb) {
+    const Real et = elj + ec;
+    e = S * et;
+    return mad(g, et, S * mad(Real(6), x6, ec) * r2);
+  }
+  e = mad(S, elj, ec);
+  return mad(g, elj, mad(Real(6) * S, x6, ec) * r2);
 }
 
 // Four 16-bit LDS stores of v, store i by the lanes set in m_i only, to byte addresses
@@ -247,40 +330,47 @@ __device__ inline void lds_store_u16_lanes4(uint32_t a0, uint32_t a1, uint32_t a
 // and e, and pairs beyond the cutoff need no test (t clamps to 1).
 // kDiag: count filter passes, cutoff passes and filtered slots (MD_DIAG_COUNTERS).
 // kHalf: the half shell (64-bit fixed-point sums only). kDrain: force batches per drain.
-template <bool kHalf, bool kSwitchCoulomb, bool kClamp, bool kDiag, int kDrain>
-__device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<float>& a, int cap,
+template <typename Real, bool kHalf, bool kSwitchCoulomb, bool kClamp, bool kDiag, int kDrain>
+__device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<Real>& a, int cap,
                                                               int64_t cellA) {
   extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
+  constexpr bool kF32 = sizeof(Real) == 4;
   constexpr int kImg = kHalf ? 14 : 27;   // neighbour images
   constexpr int kFifo = fifo_entries(kDrain);
   constexpr int kWaveFifo = kQ * kFifo;
-  const Lds LL = lds_layout(cap, a.n_types, kHalf, kDiag, kDrain);
+  constexpr uint32_t kS = sizeof(V4<Real>);   // bytes per staged atom record
+  constexpr int kAW = kAccWords<Real>;
+  using R4 = V4<Real>;
+  using R2 = V2<Real>;
+  const Lds LL = lds_layout<Real>(cap, a.n_types, kHalf, kDiag, kDrain);
   Hdr& H = *reinterpret_cast<Hdr*>(s_dyn + LL.hdr);
   uint16_t* sFifo = reinterpret_cast<uint16_t*>(s_dyn + LL.fifo);
-  float2* sLJ = reinterpret_cast<float2*>(s_dyn + LL.lj);
-  float4* sF = reinterpret_cast<float4*>(s_dyn + LL.f4);
-  float* sQ = reinterpret_cast<float*>(s_dyn + LL.q);
-  long long* sJ = reinterpret_cast<long long*>(s_dyn + LL.jacc);   // [cap][3], half shell
+  R2* sLJ = reinterpret_cast<R2*>(s_dyn + LL.lj);
+  R4* sF = reinterpret_cast<R4*>(s_dyn + LL.f4);
+  Real* sQ = reinterpret_cast<Real*>(s_dyn + LL.q);
+  [[maybe_unused]] int* sT = reinterpret_cast<int*>(s_dyn + LL.typ);   // float64: types
+  long long* sJ = reinterpret_cast<long long*>(s_dyn + LL.jacc);   // [cap][3][kAW], half
   int* sJn = reinterpret_cast<int*>(s_dyn + LL.jcnt);               // [cap], half + counters
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int nt = a.n_types;
-  // low bits of a staged c_j that carry the atom's type
-  const uint32_t tmask = nt > 1 ? (2u << (31 - __builtin_clz((unsigned)(nt - 1)))) - 1u : 0u;
+  // float32: low bits of a staged c_j that carry the atom's type
+  [[maybe_unused]] const uint32_t tmask =
+      nt > 1 ? (2u << (31 - __builtin_clz((unsigned)(nt - 1)))) - 1u : 0u;
   constexpr bool diag = kDiag;
-  const bool f32 = !kHalf && (a.flags & MD_ACCUM_F32_ATOMIC) != 0;
-  const float rc2 = a.rc2, rs2 = a.rs2, inv_sw = a.inv_sw, sw12 = 12.f * a.inv_sw;
-  const float kc = a.coulomb_k;
-  const float L0 = a.L[0], L1 = a.L[1], L2 = a.L[2];
+  const bool f32 = kF32 && !kHalf && (a.flags & MD_ACCUM_F32_ATOMIC) != 0;
+  const Real rc2 = a.rc2, rs2 = a.rs2, inv_sw = a.inv_sw, sw12 = Real(12) * a.inv_sw;
+  const Real kc = a.coulomb_k;
+  const Real L0 = a.L[0], L1 = a.L[1], L2 = a.L[2];
   const int ac0 = (int)(cellA % a.nx), ac1 = (int)((cellA / a.nx) % a.ny),
             ac2 = (int)(cellA / ((int64_t)a.nx * a.ny));
   // origin o of the prefilter: the home cell's centre (any nearby point would do)
-  const float O0 = ((float)ac0 + 0.5f) * (L0 / (float)a.nx);
-  const float O1 = ((float)ac1 + 0.5f) * (L1 / (float)a.ny);
-  const float O2 = ((float)ac2 + 0.5f) * (L2 / (float)a.nz);
+  const Real O0 = ((Real)ac0 + Real(0.5)) * (L0 / (Real)a.nx);
+  const Real O1 = ((Real)ac1 + Real(0.5)) * (L1 / (Real)a.ny);
+  const Real O2 = ((Real)ac2 + Real(0.5)) * (L2 / (Real)a.nz);
 
-  for (int e = tid; e < nt * nt; e += kThreads) sLJ[e] = make_float2(a.lj[2 * e], a.lj[2 * e + 1]);
+  for (int e = tid; e < nt * nt; e += kThreads) sLJ[e] = mk2<Real>(a.lj[2 * e], a.lj[2 * e + 1]);
   // FIFO entries past a FIFO's fill level are read by partial force passes (and then
   // ignored): start them as valid indices
   for (int e = tid; e < kNW * kWaveFifo / 2; e += kThreads)
@@ -353,7 +443,7 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
         H.img[m].jsh = jsh;
       }
       if (head) {
-        const float wy = L1 / (float)a.ny, wz = L2 / (float)a.nz;
+        const float wy = (float)L1 / (float)a.ny, wz = (float)L2 / (float)a.nz;
         Seg& sg_ = H.seg[seg_idx];
         sg_.begin = off;
         sg_.end = off + seg_len;
@@ -382,8 +472,11 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
   const int n_grp_q = (nA + kQ - 1) / kQ;
   // largest home-side partial of one slice (see kHalfHomeBudget)
   const float home_max = (kHalf ? kHalfHomeBudget : kFullHomeBudget) / (float)max(1, (total + cap - 1) / cap);
-  const float R = __builtin_sqrtf(rc2) + kWin;
-  long long e_fix = 0;   // energy in units of 2^-24 kcal/mol: exact, order-independent sums
+  const Real R = vsqrt(rc2) + Real(kWin);
+  // energy: float32 in units of 2^-24 kcal/mol; float64 two-word (e_fix, e_lo): exact,
+  // order-independent sums
+  long long e_fix = 0;
+  [[maybe_unused]] long long e_lo = 0;
   unsigned long long pass_count = 0, filt_count = 0, slot_count = 0, lane_count = 0;
   uint32_t st = 0;
   uint16_t* fifo = sFifo + w * kWaveFifo;
@@ -398,11 +491,11 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
     for (int m = w; m < kImg; m += kNW) {
       const Img im = H.img[m];
       // o_g = o - h: the origin in this image's frame
-      const float og0 = O0 - ((im.grp & 1) ? L0 : 0.f);
-      const float og1 = O1 - ((im.grp & 2) ? L1 : 0.f);
-      const float og2 = O2 - ((im.grp & 4) ? L2 : 0.f);
+      const Real og0 = O0 - ((im.grp & 1) ? L0 : Real(0));
+      const Real og1 = O1 - ((im.grp & 2) ? L1 : Real(0));
+      const Real og2 = O2 - ((im.grp & 4) ? L2 : Real(0));
       for (int e0 = 0; e0 < im.count; e0 += 4 * 64) {
-        P4<float> v[4];
+        P4<Real> v[4];
         int tv[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -416,21 +509,25 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
           const int e = e0 + 64 * r + lane;
           const int dst = e < im.n0 ? im.off[0] + e : im.off[1] + (e - im.n0);
           if (e < im.count && dst >= P0 && dst < P1) {
-            const float x = (im.jsh & 1) ? v[r].x - L0 : v[r].x;
-            const float y = (im.jsh & 2) ? v[r].y - L1 : v[r].y;
-            const float z = (im.jsh & 4) ? v[r].z - L2 : v[r].z;
-            const float rx = x - og0, ry = y - og1, rz = z - og2;
-            // c_j with its low mantissa bits (as many as the types need, at most 6)
-            // replaced by the type: under 64 ulps of c_j, at most 1.6e-2 A^2 for the
-            // largest cells (18 A), well inside the prefilter's margin
-            const float cj = fmaf(rz, rz, fmaf(ry, ry, rx * rx));
-            const uint32_t w4 = (__float_as_uint(cj) & ~tmask) | (uint32_t)tv[r];
-            sF[dst - P0] = make_float4(x, y, z, __uint_as_float(w4));
+            const Real x = (im.jsh & 1) ? v[r].x - L0 : v[r].x;
+            const Real y = (im.jsh & 2) ? v[r].y - L1 : v[r].y;
+            const Real z = (im.jsh & 4) ? v[r].z - L2 : v[r].z;
+            const Real rx = x - og0, ry = y - og1, rz = z - og2;
+            const Real cj = mad(rz, rz, mad(ry, ry, rx * rx));
+            if constexpr (kF32) {
+              // c_j with its low mantissa bits (as many as the types need, at most 6)
+              // replaced by the type: under 64 ulps of c_j, at most 1.6e-2 A^2 for the
+              // largest cells (18 A), well inside the prefilter's margin
+              const uint32_t w4 = (__float_as_uint(cj) & ~tmask) | (uint32_t)tv[r];
+              sF[dst - P0] = mk4(x, y, z, __uint_as_float(w4));
+            } else {
+              sF[dst - P0] = mk4(x, y, z, cj);
+              sT[dst - P0] = tv[r];
+            }
             sQ[dst - P0] = v[r].w;
             if (kHalf) {
-              sJ[3 * (dst - P0)] = 0;
-              sJ[3 * (dst - P0) + 1] = 0;
-              sJ[3 * (dst - P0) + 2] = 0;
+#pragma unroll
+              for (int c = 0; c < 3 * kAW; ++c) sJ[3 * kAW * (dst - P0) + c] = 0;
               if (kDiag) sJn[dst - P0] = 0;
             }
           }
@@ -456,17 +553,17 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
     // the segment's last atom (a probe past it compares that atom instead, and the result
     // is clamped to se)
     const uint32_t f4b = (uint32_t)LL.f4;
-    auto lower_bound = [&](float key) __attribute__((always_inline)) {
-      const float k = se > sb ? key : -INFINITY;     // an empty segment probes nothing
-      uint32_t a = f4b + 16u * (uint32_t)sb - 16u;   // byte address of the last atom < key
-      const uint32_t last = f4b + 16u * (uint32_t)se - 16u;
+    auto lower_bound = [&](Real key) __attribute__((always_inline)) {
+      const Real k = se > sb ? key : Real(-INFINITY);   // an empty segment probes nothing
+      uint32_t a = f4b + kS * (uint32_t)sb - kS;          // byte address of the last atom < key
+      const uint32_t last = f4b + kS * (uint32_t)se - kS;
       for (int it = iters - 1; it >= 0; --it) {
-        const uint32_t t = a + (16u << it);
-        const float xq = *reinterpret_cast<const __attribute__((address_space(3))) float*>(
+        const uint32_t t = a + (kS << it);
+        const Real xq = *reinterpret_cast<const __attribute__((address_space(3))) Real*>(
             (uintptr_t)min(t, last));   // LDS byte address (the dynamic block starts at 0)
         a = xq < k ? t : a;
       }
-      return min((int)((a + 16u - f4b) >> 4), se);
+      return min((int)((a + kS - f4b) / kS), se);
     };
 
     while (true) {
@@ -477,47 +574,48 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
       const int ib = kQ * o;
       const int nv = min(kQ, nA - ib);   // home atoms present in this group
 
-      float xi[kQ], yi[kQ], zi[kQ], kq[kQ], fx[kQ], fy[kQ], fz[kQ];
-      float ax[kQ], ay[kQ], az[kQ], thb[kQ];
+      Real xi[kQ], yi[kQ], zi[kQ], kq[kQ], fx[kQ], fy[kQ], fz[kQ];
+      Real ax[kQ], ay[kQ], az[kQ], thb[kQ];
       int row[kQ];
       uint32_t fb[kQ];   // byte address of the next free slot of FIFO k
       uint32_t fl[kQ];   // fb[k] at which FIFO k holds a full drain
       unsigned cnt[kQ];
-      float xmin = 0.f, xmax = 0.f, ymin = 0.f, ymax = 0.f, zmin = 0.f, zmax = 0.f;
+      Real xmin = 0, xmax = 0, ymin = 0, ymax = 0, zmin = 0, zmax = 0;
 #pragma unroll
       for (int k = 0; k < kQ; ++k) {
         const bool v = k < nv;
         const int s = sA + ib + (v ? k : 0);
-        const P4<float> p = a.pos[s];
+        const P4<Real> p = a.pos[s];
         xi[k] = p.x;
         yi[k] = p.y;
         zi[k] = p.z;
         kq[k] = kc * p.w;
         row[k] = a.type[s] * nt;
-        xmin = k == 0 ? p.x : fminf(xmin, p.x);
-        xmax = k == 0 ? p.x : fmaxf(xmax, p.x);
-        ymin = k == 0 ? p.y : fminf(ymin, p.y);
-        ymax = k == 0 ? p.y : fmaxf(ymax, p.y);
-        zmin = k == 0 ? p.z : fminf(zmin, p.z);
-        zmax = k == 0 ? p.z : fmaxf(zmax, p.z);
+        xmin = k == 0 ? p.x : vmin(xmin, p.x);
+        xmax = k == 0 ? p.x : vmax(xmax, p.x);
+        ymin = k == 0 ? p.y : vmin(ymin, p.y);
+        ymax = k == 0 ? p.y : vmax(ymax, p.y);
+        zmin = k == 0 ? p.z : vmin(zmin, p.z);
+        zmax = k == 0 ? p.z : vmax(zmax, p.z);
         // prefilter in the frame of group g, with a = r_i - o (the same in every frame):
         // |r_j - r_i|^2 = c_j - 2 a.(r_j - o_g) + |a|^2, c_j = |r_j - o_g|^2, so the test
         // c_j + ax.r_j < rc^2 + margin - |a|^2 + ax.o_g with ax = -2a
-        const float rx = p.x - O0, ry = p.y - O1, rz = p.z - O2;
-        ax[k] = v ? -2.f * rx : 0.f;
-        ay[k] = v ? -2.f * ry : 0.f;
-        az[k] = v ? -2.f * rz : 0.f;
+        const Real rx = p.x - O0, ry = p.y - O1, rz = p.z - O2;
+        ax[k] = v ? Real(-2) * rx : Real(0);
+        ay[k] = v ? Real(-2) * ry : Real(0);
+        az[k] = v ? Real(-2) * rz : Real(0);
         // an absent atom gets -1, which c_j >= 0 never passes
-        thb[k] = v ? (rc2 + kMargin) - fmaf(rz, rz, fmaf(ry, ry, rx * rx)) +
+        thb[k] = v ? (rc2 + Real(kMargin)) - mad(rz, rz, mad(ry, ry, rx * rx)) +
                          (ax[k] * O0 + ay[k] * O1 + az[k] * O2)
-                   : -1.f;
-        fx[k] = fy[k] = fz[k] = 0.f;
+                   : Real(-1);
+        fx[k] = fy[k] = fz[k] = Real(0);
         fb[k] = fk0 + 2u * (uint32_t)(k * kFifo);
         fl[k] = fb[k] + 2u * (uint32_t)(64 * kDrain);
         cnt[k] = 0;
       }
-      float e_lane = 0.f;
-      float jmax = 0.f;   // largest |F_j| component, in units of 2^-24, handed to round_to_i64
+      Real e_lane = 0;
+      Real jmax = 0;   // largest |F_j| component handed to the neighbour side (float32: in
+                       // units of 2^-24, as given to round_to_i64)
 
       // x-window of every segment: [lo, hi) of segment s with x in [min x_i - w, max x_i + w)
       // in the segment's frame (two lower_bound searches, in lanes s and s + 32 when the
@@ -529,14 +627,14 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
         // the segment's slab, read again for every group (registers are scarce)
         const Seg& sgl = H.seg[sl < n_seg ? sl : 0];
         const float4 slab = make_float4(sgl.y0, sgl.y1, sgl.z0, sgl.z1);
-        const float gy = fmaxf(fmaxf(slab.x - ymax, ymin - slab.y) - kWin, 0.f);
-        const float gz = fmaxf(fmaxf(slab.z - zmax, zmin - slab.w) - kWin, 0.f);
-        const float w2 = fmaf(R, R, -fmaf(gz, gz, gy * gy));
-        const float hw = w2 > 0.f ? __builtin_sqrtf(w2) : -1.f;
-        const float hx = (sg & 1) ? L0 : 0.f;
+        const Real gy = vmax(vmax((Real)slab.x - ymax, ymin - (Real)slab.y) - Real(kWin), Real(0));
+        const Real gz = vmax(vmax((Real)slab.z - zmax, zmin - (Real)slab.w) - Real(kWin), Real(0));
+        const Real w2 = mad(R, R, -mad(gz, gz, gy * gy));
+        const Real hw = w2 > Real(0) ? vsqrt(w2) : Real(-1);
+        const Real hx = (sg & 1) ? L0 : Real(0);
         // a segment out of reach gets the empty window [sb, sb)
-        const float xlo = w2 > 0.f ? (xmin - hx) - hw : -INFINITY;
-        const float xhi = w2 > 0.f ? (xmax - hx) + hw : -INFINITY;
+        const Real xlo = w2 > Real(0) ? (xmin - hx) - hw : Real(-INFINITY);
+        const Real xhi = w2 > Real(0) ? (xmax - hx) + hw : Real(-INFINITY);
         if (split) {
           // lane s: start of segment s's window; lane s + 32: its end
           wlo = lower_bound(lane < 32 ? xlo : xhi);
@@ -547,48 +645,64 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
         }
       }
 
-      float xs[kQ], ys[kQ], zs[kQ], thr[kQ];
+      Real xs[kQ], ys[kQ], zs[kQ], thr[kQ];
       // entries in FIFO k
       auto fill = [&](int k) __attribute__((always_inline)) {
         return (int)((fb[k] - fk0) >> 1) - k * kFifo;
+      };
+      // type of a staged atom
+      auto type_of = [&](int jl, const R4& pj) __attribute__((always_inline)) {
+        if constexpr (kF32) return (int)(__float_as_uint(pj.w) & tmask); else return sT[jl];
       };
       // the force on home atom k from one lane's FIFO entry j: the exact distance in the
       // current frame, the strict cutoff and the force; `in` is false for lanes past the
       // FIFO's fill level. The full shell's u > 0 drops the home atom itself; the half
       // shell never pairs an atom with itself (j > i in the home image). The half shell
-      // adds -F to neighbour j's accumulator as well (zero for lanes that add nothing), in
-      // units of 2^-24 kcal/mol/A: -f 2^24 dx is an exact scaling of the float32 product,
-      // rounded once to an integer.
-      auto pair_lane = [&](int k, int jl, const float4& pj, float qj, const float2& lj,
+      // adds -F to neighbour j's accumulator as well (zero for lanes that add nothing):
+      // float32 in units of 2^-24 kcal/mol/A (-f 2^24 dx is an exact scaling of the float32
+      // product, rounded once to an integer), float64 as a two-word fixed-point value.
+      auto pair_lane = [&](int k, int jl, const R4& pj, Real qj, const R2& lj,
                            bool in) __attribute__((always_inline)) {
-        const float dx = xs[k] - pj.x, dy = ys[k] - pj.y, dz = zs[k] - pj.z;
-        float u = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        float e, f;
+        const Real dx = xs[k] - pj.x, dy = ys[k] - pj.y, dz = zs[k] - pj.z;
+        Real u = dist2(dx, dy, dz);
+        Real e, f;
         if (kClamp) {
-          u = (in && (kHalf || u > 0.f)) ? u : kBigU;
+          u = (in && (kHalf || u > Real(0))) ? u : Real(kBigU);
           f = pair_f<kSwitchCoulomb>(u, lj.x, lj.y, kq[k] * qj, rs2, inv_sw, sw12, e);
           if (diag) cnt[k] += __builtin_popcountll(__builtin_amdgcn_ballot_w64(u < rc2));
           if (kHalf && diag && u < rc2) atomicAdd(&sJn[jl], 1);
         } else {
-          const bool lv = in && u < rc2 && u > 0.f;
+          const bool lv = in && u < rc2 && u > Real(0);
           f = pair_f<kSwitchCoulomb>(u, lj.x, lj.y, kq[k] * qj, rs2, inv_sw, sw12, e);
-          f = lv ? f : 0.f;
-          e = lv ? e : 0.f;
+          f = lv ? f : Real(0);
+          e = lv ? e : Real(0);
           if (diag) cnt[k] += __builtin_popcountll(__builtin_amdgcn_ballot_w64(lv));
           if (kHalf && diag && lv) atomicAdd(&sJn[jl], 1);
         }
-        fx[k] = fmaf(f, dx, fx[k]);
-        fy[k] = fmaf(f, dy, fy[k]);
-        fz[k] = fmaf(f, dz, fz[k]);
+        fx[k] = mad(f, dx, fx[k]);
+        fy[k] = mad(f, dy, fy[k]);
+        fz[k] = mad(f, dz, fz[k]);
         e_lane += e;
         if (kHalf) {
-          const float g24 = f * -16777216.f;
-          const float px = g24 * dx, py = g24 * dy, pz = g24 * dz;
-          jmax = fmaxf(jmax, fmaxf(fabsf(px), fmaxf(fabsf(py), fabsf(pz))));
-          long long* d = sJ + 3 * jl;
-          lds_add(d, round_to_i64(px));
-          lds_add(d + 1, round_to_i64(py));
-          lds_add(d + 2, round_to_i64(pz));
+          if constexpr (kF32) {
+            const float g24 = f * -16777216.f;
+            const float px = g24 * dx, py = g24 * dy, pz = g24 * dz;
+            jmax = fmaxf(jmax, fmaxf(fabsf(px), fmaxf(fabsf(py), fabsf(pz))));
+            long long* d = sJ + 3 * jl;
+            lds_add(d, round_to_i64(px));
+            lds_add(d + 1, round_to_i64(py));
+            lds_add(d + 2, round_to_i64(pz));
+          } else {
+            const double p3[3] = {-f * dx, -f * dy, -f * dz};
+            long long* d = sJ + 6 * jl;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              jmax = fmax(jmax, fabs(p3[c]));
+              const Fix2 q2 = to_fix2(fmin(fmax(p3[c], -1.0e9), 1.0e9));
+              lds_add(d + 2 * c, q2.hi);
+              lds_add(d + 2 * c + 1, q2.lo);
+            }
+          }
         }
       };
       // dense force passes over the first 64 kDrain entries of FIFO k, every lane busy; all
@@ -596,9 +710,9 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
       // 64 entries) moves to the front.
       auto force = [&](int k) __attribute__((always_inline)) {
         int jj[kDrain], tj[kDrain];
-        float4 pj[kDrain];
-        float qj[kDrain];
-        float2 lj[kDrain];
+        R4 pj[kDrain];
+        Real qj[kDrain];
+        R2 lj[kDrain];
 #pragma unroll
         for (int b = 0; b < kDrain; ++b) jj[b] = fifo[k * kFifo + 64 * b + lane];
         if (diag) lane_count += 64 * kDrain;
@@ -606,7 +720,7 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
         for (int b = 0; b < kDrain; ++b) {
           pj[b] = sF[jj[b]];
           qj[b] = sQ[jj[b]];
-          tj[b] = (int)(__float_as_uint(pj[b].w) & tmask);
+          tj[b] = type_of(jj[b], pj[b]);
         }
 #pragma unroll
         for (int b = 0; b < kDrain; ++b) lj[b] = sLJ[row[k] + tj[b]];
@@ -630,9 +744,9 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
           for (int off = 0; off < n; off += 64) {
             const int jj = fifo[k * kFifo + off + lane];   // entries past n: valid indices
             if (diag) lane_count += 64;
-            const float4 pj = sF[jj];
-            const float qj = sQ[jj];
-            const float2 lj = sLJ[row[k] + (int)(__float_as_uint(pj.w) & tmask)];
+            const R4 pj = sF[jj];
+            const Real qj = sQ[jj];
+            const R2 lj = sLJ[row[k] + type_of(jj, pj)];
             pair_lane(k, jj, pj, qj, lj, off + lane < n);
           }
           fb[k] = fk0 + 2u * (uint32_t)(k * kFifo);
@@ -653,7 +767,8 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
         if (g != cur_g) {
           if (cur_g >= 0) flush();   // the home side changes frame
           cur_g = g;
-          const float hx = (g & 1) ? L0 : 0.f, hy = (g & 2) ? L1 : 0.f, hz = (g & 4) ? L2 : 0.f;
+          const Real hx = (g & 1) ? L0 : Real(0), hy = (g & 2) ? L1 : Real(0),
+                     hz = (g & 4) ? L2 : Real(0);
 #pragma unroll
           for (int k = 0; k < kQ; ++k) {
             xs[k] = xi[k] - hx;   // exact: such home atoms lie in the last cell of the axis
@@ -671,14 +786,14 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
         const int se_s = __builtin_amdgcn_readlane(se, s);
         for (int jb = lo; jb < hi; jb += 64) {
           const int j = jb + lane;
-          const float4 pj = sF[j];
-          float t[kQ];
+          const R4 pj = sF[j];
+          Real t[kQ];
 #pragma unroll
-          for (int k = 0; k < kQ; ++k) t[k] = fmaf(ax[k], pj.x, pj.w);
+          for (int k = 0; k < kQ; ++k) t[k] = mad(ax[k], pj.x, pj.w);
 #pragma unroll
-          for (int k = 0; k < kQ; ++k) t[k] = fmaf(ay[k], pj.y, t[k]);
+          for (int k = 0; k < kQ; ++k) t[k] = mad(ay[k], pj.y, t[k]);
 #pragma unroll
-          for (int k = 0; k < kQ; ++k) t[k] = fmaf(az[k], pj.z, t[k]);
+          for (int k = 0; k < kQ; ++k) t[k] = mad(az[k], pj.z, t[k]);
           unsigned long long m[kQ];
 #pragma unroll
           for (int k = 0; k < kQ; ++k) m[k] = __builtin_amdgcn_ballot_w64(t[k] < thr[k]);
@@ -729,36 +844,59 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
       // totals to its 64-bit fixed-point sum (exact conversion; with an integer atomic in
       // the half shell, where other workgroups add to the same atom) or float32 sum.
       static_assert(kQ == 4, "one 16-lane row per home atom");
-      float r[3 * kQ];
+      Real r[3 * kQ];
 #pragma unroll
       for (int k = 0; k < kQ; ++k) {
         r[3 * k] = fx[k];
         r[3 * k + 1] = fy[k];
         r[3 * k + 2] = fz[k];
       }
-      // Both exchanges are register swaps between lane groups (v_permlane32_swap: lanes
-      // 32-63 of the first operand with lanes 0-31 of the second; v_permlane16_swap: the
-      // odd 16-lane rows of the first with the even rows of the second). After the swap
-      // the first operand holds the lane's kept value in the lower group and the partner's
-      // in the upper one, the second operand the reverse, so their sum is the same two
-      // terms as keep + partner's give (float addition commutes exactly). The results are
-      // read by value: a bit cast applied to an element of the returned vector reads
-      // element 0 for both with this compiler.
-      float r6[6], r3[3];
+      Real r3[3];
+      if constexpr (kF32) {
+        // Both exchanges are register swaps between lane groups (v_permlane32_swap: lanes
+        // 32-63 of the first operand with lanes 0-31 of the second; v_permlane16_swap: the
+        // odd 16-lane rows of the first with the even rows of the second). After the swap
+        // the first operand holds the lane's kept value in the lower group and the
+        // partner's in the upper one, the second operand the reverse, so their sum is the
+        // same two terms as keep + partner's give (float addition commutes exactly). The
+        // results are read by value: a bit cast applied to an element of the returned
+        // vector reads element 0 for both with this compiler.
+        float r6[6];
 #pragma unroll
-      for (int i = 0; i < 6; ++i) {
-        const auto sw =
-            __builtin_amdgcn_permlane32_swap(__float_as_uint(r[i]), __float_as_uint(r[i + 6]), false, false);
-        r6[i] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
+        for (int i = 0; i < 6; ++i) {
+          const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(r[i]),
+                                                           __float_as_uint(r[i + 6]), false, false);
+          r6[i] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(r6[i]),
+                                                           __float_as_uint(r6[i + 3]), false, false);
+          r3[i] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) r3[i] = rowsum16(r3[i]);
+      } else {
+        // the same order with lane shuffles: own + partner's term at each step
+        const bool upper = lane >= 32, odd_row = (lane & 16) != 0;
+        double r6[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+          const double keep = upper ? r[i + 6] : r[i];
+          const double give = upper ? r[i] : r[i + 6];
+          r6[i] = keep + __shfl_xor(give, 32);
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          const double keep = odd_row ? r6[i + 3] : r6[i];
+          const double give = odd_row ? r6[i] : r6[i + 3];
+          r3[i] = keep + __shfl_xor(give, 16);
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int sft = 1; sft < 16; sft <<= 1) r3[i] += __shfl_xor(r3[i], sft);
       }
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const auto sw =
-            __builtin_amdgcn_permlane16_swap(__float_as_uint(r6[i]), __float_as_uint(r6[i + 3]), false, false);
-        r3[i] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
-      }
-#pragma unroll
-      for (int i = 0; i < 3; ++i) r3[i] = rowsum16(r3[i]);
       {
         const int kr = lane >> 4;   // this row's home atom
         if ((lane & 15) == 0 && kr < nv) {
@@ -767,17 +905,30 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
           for (int c = 0; c < 3; ++c) {
             if (f32) {
               float* dst = &a.facc[(int64_t)c * a.n + s];
-              *dst = P0 == 0 ? r3[c] : *dst + r3[c];
+              *dst = P0 == 0 ? (float)r3[c] : *dst + (float)r3[c];
             } else {
               // one of the slice count's home-side partials of this atom: within its share
               // of the fixed point's range (kHalfHomeBudget, kFullHomeBudget)
-              if (!(fabsf(r3[c]) < home_max)) st |= MD_STATUS_FIXED_OVERFLOW;
-              const long long qv = to_fixed(r3[c], st);
-              long long* dst = &a.acc64[(int64_t)c * a.n + s];
-              if (kHalf)
-                global_add(dst, qv);
-              else
-                *dst = P0 == 0 ? qv : *dst + qv;
+              if (!(fabs(r3[c]) < (Real)home_max)) st |= MD_STATUS_FIXED_OVERFLOW;
+              if constexpr (kF32) {
+                const long long qv = to_fixed(r3[c], st);
+                long long* dst = &a.acc64[(int64_t)c * a.n + s];
+                if (kHalf)
+                  global_add(dst, qv);
+                else
+                  *dst = P0 == 0 ? qv : *dst + qv;
+              } else {
+                const Fix2 q2 = to_fix2(fmin(fmax(r3[c], -1.0e10), 1.0e10));
+                long long* dh = &a.acc64[(int64_t)c * a.n + s];
+                long long* dl = &a.acc64[(int64_t)(3 + c) * a.n + s];
+                if (kHalf) {
+                  global_add(dh, q2.hi);
+                  global_add(dl, q2.lo);
+                } else {
+                  *dh = P0 == 0 ? q2.hi : *dh + q2.hi;
+                  *dl = P0 == 0 ? q2.lo : *dl + q2.lo;
+                }
+              }
             }
           }
           if (diag) {
@@ -794,14 +945,23 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
       }
 #pragma unroll
       for (int k = 0; k < kQ; ++k) pass_count += k < nv ? cnt[k] : 0u;
-      {
+      if constexpr (kF32) {
         // the group's lane energy in 64-bit fixed point (exact scaling by 2^24, then one
         // rounding), so the workgroup total does not depend on which wave took which group
         const float v = e_lane * 16777216.0f;
         if (!(fabsf(v) < 4.6116860184273879e18f)) st |= MD_STATUS_FIXED_OVERFLOW;
         else e_fix += __float2ll_rn(v);
+        if (kHalf && !(jmax < 2251799813685248.f)) st |= MD_STATUS_FIXED_OVERFLOW;   // 2^51
+      } else {
+        if (!(fabs(e_lane) < 1.0e9)) {
+          st |= MD_STATUS_FIXED_OVERFLOW;
+        } else {
+          const Fix2 q2 = to_fix2(e_lane);
+          e_fix += q2.hi;
+          e_lo += q2.lo;
+        }
+        if (kHalf && !(jmax < (double)kNbrPartialMax)) st |= MD_STATUS_FIXED_OVERFLOW;
       }
-      if (kHalf && !(jmax < 2251799813685248.f)) st |= MD_STATUS_FIXED_OVERFLOW;   // 2^51
     }
     __syncthreads();
     if (kHalf) {
@@ -814,14 +974,27 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
           const int64_t src = im.start + e;
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            // units of 2^-24 to the sums' 2^-32, each partial below 2^27 kcal/mol/A (2^51
-            // units, kNbrPartialMax)
-            const long long v = sJ[3 * (dst - P0) + c];
-            constexpr long long kLim = (long long)kNbrPartialMax << 24;
-            if (v >= kLim || v < -kLim) st |= MD_STATUS_FIXED_OVERFLOW;
-            else if (v != 0)
-              global_add(&a.acc64[(int64_t)c * a.n + src],
-                         (long long)((unsigned long long)v << 8));
+            if constexpr (kF32) {
+              // units of 2^-24 to the sums' 2^-32, each partial below 2^27 kcal/mol/A (2^51
+              // units, kNbrPartialMax)
+              const long long v = sJ[3 * (dst - P0) + c];
+              constexpr long long kLim = (long long)kNbrPartialMax << 24;
+              if (v >= kLim || v < -kLim) st |= MD_STATUS_FIXED_OVERFLOW;
+              else if (v != 0)
+                global_add(&a.acc64[(int64_t)c * a.n + src],
+                           (long long)((unsigned long long)v << 8));
+            } else {
+              // two words, the low one reduced into [0, 2^52) so that the 14 neighbour-side
+              // partials of an atom cannot wrap it; each partial below 2^27 kcal/mol/A
+              const Fix2 v = normalize2(sJ[6 * (dst - P0) + 2 * c], sJ[6 * (dst - P0) + 2 * c + 1]);
+              constexpr long long kLim = (long long)kNbrPartialMax << 20;
+              if (v.hi >= kLim || v.hi < -kLim) {
+                st |= MD_STATUS_FIXED_OVERFLOW;
+              } else {
+                if (v.hi != 0) global_add(&a.acc64[(int64_t)c * a.n + src], v.hi);
+                if (v.lo != 0) global_add(&a.acc64[(int64_t)(3 + c) * a.n + src], v.lo);
+              }
+            }
           }
           if (kDiag) {
             const int v = sJn[dst - P0];
@@ -833,17 +1006,34 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
     }
   }
 
-  // workgroup energy (the full shell saw each pair from both atoms)
+  // workgroup energy (the full shell saw each pair from both atoms), a fixed tree over
+  // 1024 lanes of exact integer sums
   long long* sE = reinterpret_cast<long long*>(s_dyn + LL.f4);
-  sE[tid] = e_fix;
-  for (int e = kThreads + tid; e < 1024; e += kThreads) sE[e] = 0;   // pad the tree to 1024
-  __syncthreads();
-  for (int off = 512; off > 0; off >>= 1) {
-    if (tid < off) sE[tid] += sE[tid + off];
+  if constexpr (kF32) {
+    sE[tid] = e_fix;
+    for (int e = kThreads + tid; e < 1024; e += kThreads) sE[e] = 0;   // pad the tree to 1024
     __syncthreads();
+    for (int off = 512; off > 0; off >>= 1) {
+      if (tid < off) sE[tid] += sE[tid + off];
+      __syncthreads();
+    }
+    if (tid == 0)
+      a.epart[cellA] = (kHalf ? 1.0 : 0.5) * ((double)sE[0] * 5.9604644775390625e-08);   // 2^-24
+  } else {
+    const Fix2 v = normalize2(e_fix, e_lo);   // low words below 2^52: 1024 of them fit
+    sE[tid] = v.hi;
+    sE[1024 + tid] = v.lo;
+    for (int e = kThreads + tid; e < 1024; e += kThreads) sE[e] = sE[1024 + e] = 0;
+    __syncthreads();
+    for (int off = 512; off > 0; off >>= 1) {
+      if (tid < off) {
+        sE[tid] += sE[tid + off];
+        sE[1024 + tid] += sE[1024 + tid + off];
+      }
+      __syncthreads();
+    }
+    if (tid == 0) a.epart[cellA] = (kHalf ? 1.0 : 0.5) * from_fix2(sE[0], sE[1024]);
   }
-  if (tid == 0)
-    a.epart[cellA] = (kHalf ? 1.0 : 0.5) * ((double)sE[0] * 5.9604644775390625e-08);   // 2^-24
   if (st) atomicOr(&a.hdr->status, st);
   if (diag && lane == 0) {
     // candidates of Algorithm 1: every (home atom, other neighbour-list atom), counted
@@ -871,7 +1061,8 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<floa
 // The same workgroup also adds its shader-clock cycles (s_memtime) and its 100 MHz ticks
 // to the header's two clock sums: their ratio is the clock the kernel ran at, weighted by
 // workgroup time.
-__device__ inline void record_cost(const SysArgs<float>& a, int64_t cell, uint64_t t0,
+template <typename Real>
+__device__ inline void record_cost(const SysArgs<Real>& a, int64_t cell, uint64_t t0,
                                    uint64_t c0, bool first) {
   if (threadIdx.x == 0) {   // after the workgroup's last barrier
     const uint64_t dc = __builtin_amdgcn_s_memtime() - c0;
@@ -886,14 +1077,14 @@ __device__ inline void record_cost(const SysArgs<float>& a, int64_t cell, uint64
   }
 }
 
-template <bool kHalf, bool kSwitchCoulomb, bool kClamp, bool kDiag, int kDrain>
+template <typename Real, bool kHalf, bool kSwitchCoulomb, bool kClamp, bool kDiag, int kDrain>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNW / 4, kNW / 4)))
-void k_pair_fs(SysArgs<float> a, int cap) {
+void k_pair_fs(SysArgs<Real> a, int cap) {
   // home cells in the order the binning chose (longest first)
   const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
   const uint64_t c0 = __builtin_amdgcn_s_memtime();
   const int64_t cell = a.order[blockIdx.x];
-  pair_fs<kHalf, kSwitchCoulomb, kClamp, kDiag, kDrain>(a, cap, cell);
+  pair_fs<Real, kHalf, kSwitchCoulomb, kClamp, kDiag, kDrain>(a, cap, cell);
   record_cost(a, cell, t0, c0, blockIdx.x == 0);
 }
 
@@ -906,7 +1097,7 @@ void k_pair_fs_batch(Batch<float> b, int cap) {
   int64_t unit;
   const int s = b.pick(blockIdx.x, unit);
   const int64_t cell = b.sys[s].order[unit];
-  pair_fs<kHalf, kSwitchCoulomb, kClamp, kDiag, kDrain>(b.sys[s], cap, cell);
+  pair_fs<float, kHalf, kSwitchCoulomb, kClamp, kDiag, kDrain>(b.sys[s], cap, cell);
   record_cost(b.sys[s], cell, t0, c0, unit == 0);
 }
 
@@ -917,32 +1108,37 @@ struct launch_tag {
 };
 
 // Neighbour atoms staged in LDS per pass (a multiple of 64).
+template <typename Real>
 int fs_cap(int n_types, bool half, bool diag, int drain) {
-  int cap = (kLdsBytes - lds_layout(0, n_types, half, diag, drain).total) / slot_bytes(half, diag);
+  int cap = (kLdsBytes - lds_layout<Real>(0, n_types, half, diag, drain).total) /
+            slot_bytes<Real>(half, diag);
   cap -= cap % 64;
-  while (cap > 0 && lds_layout(cap, n_types, half, diag, drain).total > kLdsBytes) cap -= 64;
+  while (cap > 0 && lds_layout<Real>(cap, n_types, half, diag, drain).total > kLdsBytes) cap -= 64;
   return cap;
 }
 
 // The kernel instance for a system's flags: half or full shell, how the switch applies
 // (whole energy with the clamp, whole energy, or LJ only), and the drain depth (other
-// depths than the default only for the half shell with the clamp; the API checks that).
-template <typename Args, typename Launch>
-hipError_t dispatch(const SysArgs<float>& a, const Args& args, int n_types, int64_t blocks,
+// depths than the default only for the float32 half shell with the clamp; the API checks
+// that).
+template <typename Real, typename Args, typename Launch>
+hipError_t dispatch(const SysArgs<Real>& a, const Args& args, int n_types, int64_t blocks,
                     hipStream_t stream, Launch launch) {
   const bool half = a.half_shell != 0;
   const bool diag = (a.flags & MD_DIAG_COUNTERS) != 0;
   const bool trunc = (a.flags & MD_COULOMB_TRUNCATED) != 0;
-  const bool clamp = !trunc && a.inv_sw > 0.f;
+  const bool clamp = !trunc && a.inv_sw > Real(0);
   const int drain = md_pair_drain(a.flags);
-  if (drain != kDrainDefault && !(half && clamp)) return hipErrorInvalidValue;
-  const int cap = fs_cap(n_types, half, diag, drain);
-  const size_t shmem = (size_t)lds_layout(cap, n_types, half, diag, drain).total;
+  if (drain != kDrainDefault && !(half && clamp && sizeof(Real) == 4)) return hipErrorInvalidValue;
+  const int cap = fs_cap<Real>(n_types, half, diag, drain);
+  // the float64 energy tree takes 2 x 1024 int64 of the staged-atom block
+  if (sizeof(Real) == 8 && cap < 512) return hipErrorInvalidValue;
+  const size_t shmem = (size_t)lds_layout<Real>(cap, n_types, half, diag, drain).total;
   const dim3 grid((unsigned)blocks), block(kThreads);
   auto go = [&](auto h, auto d) {
     constexpr bool H = decltype(h)::value, D = decltype(d)::value;
     if (clamp) {
-      if constexpr (H) {
+      if constexpr (H && sizeof(Real) == 4) {
         if (drain == 1) return launch(launch_tag<H, true, true, D, 1>(), grid, block, shmem, stream, args, cap);
         if (drain == 3) return launch(launch_tag<H, true, true, D, 3>(), grid, block, shmem, stream, args, cap);
         if (drain == 4) return launch(launch_tag<H, true, true, D, 4>(), grid, block, shmem, stream, args, cap);
@@ -966,16 +1162,21 @@ hipError_t dispatch(const SysArgs<float>& a, const Args& args, int n_types, int6
 
 }  // namespace
 
-hipError_t launch_pair_fs(const SysArgs<float>& a, hipStream_t stream) {
+template <typename Real>
+hipError_t launch_pair_fs(const SysArgs<Real>& a, hipStream_t stream) {
   if (a.n == 0) return hipSuccess;
   return dispatch(a, a, a.n_types, a.n_cells, stream,
-                  [](auto tag, dim3 g, dim3 b, size_t sh, hipStream_t st, const SysArgs<float>& x,
+                  [](auto tag, dim3 g, dim3 b, size_t sh, hipStream_t st, const SysArgs<Real>& x,
                      int cap) {
                     using Tg = decltype(tag);
-                    hipLaunchKernelGGL((k_pair_fs<Tg::half, Tg::sw, Tg::clamp, Tg::diag, Tg::drain>),
-                                       g, b, sh, st, x, cap);
+                    hipLaunchKernelGGL(
+                        (k_pair_fs<Real, Tg::half, Tg::sw, Tg::clamp, Tg::diag, Tg::drain>), g, b,
+                        sh, st, x, cap);
                   });
 }
+
+template hipError_t launch_pair_fs<float>(const SysArgs<float>&, hipStream_t);
+template hipError_t launch_pair_fs<double>(const SysArgs<double>&, hipStream_t);
 
 hipError_t launch_pair_fs_batch(const Batch<float>& b0, hipStream_t stream) {
   Batch<float> b = b0;

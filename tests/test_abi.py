@@ -69,12 +69,13 @@ def test_workspace_grows_with_atoms():
     b = api.workspace_bytes(p, 92224)
     c = api.workspace_bytes(p, 92224, True)
     assert 0 < a < b < c
-    # the compacted float32 kernel keeps three int64 sums per atom; the half-shell
-    # kernels 27 partial-force slots
+    # the compacted kernel keeps three int64 sums per atom (float64: two words each); the
+    # predicated kernel 27 partial-force slots
     assert b >= 3 * 8 * 92224
+    assert c >= 3 * 16 * 92224
     pred = dict(p, flags=api.PAIR_PREDICATED)
     assert api.workspace_bytes(pred, 92224) >= 27 * 3 * 4 * 92224 > b
-    assert c >= 27 * 3 * 8 * 92224
+    assert api.workspace_bytes(pred, 92224, True) >= 27 * 3 * 8 * 92224 > c
 
 
 def _call_f32(params, n=10, ws_bytes=1 << 20, ws_ptr=256, ptr=4096):

@@ -43,12 +43,15 @@ def _check_fp32(params, pos, types, q, g_force, g_energy, g_counts, tol=1e-5):
     return r, err
 
 
-def test_fp64_small_config_exact(gpu):
-    _say("case: 3,000-atom system, float64 path")
+@pytest.mark.parametrize("flags", [0, api.PAIR_FULL_SHELL, api.PAIR_PREDICATED])
+def test_fp64_small_config_exact(gpu, flags):
+    """FP64 everywhere: the compacted kernel instantiated for float64 (half and full
+    shell) and the predicated kernel, to 1e-12 with bit-exact partner counts."""
+    _say("case: 3,000-atom system, float64 path, flags", flags)
     s = W.small_system()
     p = s.params()
     f, e, ws, cnt = run(p, s.pos.astype(np.float64), s.types, s.charges.astype(np.float64), gpu,
-                        double=True, flags=api.DIAG_COUNTERS)
+                        double=True, flags=flags | api.DIAG_COUNTERS)
     r = _ref(p, s.pos, s.types, s.charges, "bruteforce")
     err = force_errors(f, r.force, r.abs_sum)
     _say("fp64 errors", err)
@@ -250,7 +253,7 @@ def _random_system(n, box, seed, min_sep=1.2):
 
 @pytest.mark.parametrize("box,n,seed", [((24.5, 24.5, 24.5), 150, 1), ((36.5, 36.5, 36.5), 300, 2),
                                         ((24.5, 37.0, 50.0), 260, 3), ((40.0, 26.0, 31.0), 5, 4)])
-@pytest.mark.parametrize("flags", [0, api.PAIR_PREDICATED])
+@pytest.mark.parametrize("flags", [0, api.PAIR_FULL_SHELL, api.PAIR_PREDICATED])
 def test_fp64_tiny_grids(gpu, box, n, seed, flags):
     _say("case: tiny system", box, n, seed, flags)
     pos, t, q, p = _random_system(n, box, seed)
@@ -296,12 +299,14 @@ def _lattice_blob(rng, origin, n_side, spacing, jitter):
     return origin + pts + rng.uniform(-jitter, jitter, pts.shape)
 
 
+@pytest.mark.parametrize("double", [False, True])
 @pytest.mark.parametrize("flags", [0, api.PAIR_FULL_SHELL])
-def test_compact_multi_pass(gpu, flags):
+def test_compact_multi_pass(gpu, flags, double):
     """8,000 atoms in a 3x3x3 grid: every home cell sees all of them (27 images, or 14
-    in the half shell), more than one LDS load of neighbours, so the float32 kernel
-    stages, filters and (half shell) hands back neighbour sums in several passes."""
-    _say("case: 8,000 atoms, 37 A box, neighbour list beyond LDS, flags", flags)
+    in the half shell), more than one LDS load of neighbours, so the compacted kernel
+    stages, filters and (half shell) hands back neighbour sums in several passes; in
+    float32 and in float64 (1e-12, bit-exact partner counts)."""
+    _say("case: 8,000 atoms, 37 A box, neighbour list beyond LDS, flags", flags, "double", double)
     rng = np.random.default_rng(11)
     L = 37.0
     pos = np.mod(_lattice_blob(rng, np.zeros(3), 20, 1.85, 0.3), L)
@@ -311,8 +316,17 @@ def test_compact_multi_pass(gpu, flags):
     q = rng.normal(0, 0.3, n)
     p = dict(box=(L, L, L), r_cut=12.0, r_switch=10.0, coulomb_k=W.COULOMB_K,
              sigma=np.array([1.0, 1.2]), epsilon=np.array([0.05, 0.1]), flags=0)
-    f, e, ws, cnt = run(p, pos, t, q, gpu, flags=flags | api.DIAG_COUNTERS)
-    _check_fp32(p, pos, t, q, f, e, cnt)
+    f, e, ws, cnt = run(p, pos, t, q, gpu, double=double, flags=flags | api.DIAG_COUNTERS)
+    if not double:
+        _check_fp32(p, pos, t, q, f, e, cnt)
+        return
+    r = _ref(p, pos, t, q)
+    err = force_errors(f, r.force, r.abs_sum)
+    _say("fp64 errors", err)
+    assert err["max_norm"] <= 1e-12 and err["rms"] <= 1e-12
+    assert e == pytest.approx(r.energy, rel=1e-12)
+    assert np.array_equal(cnt, r.count)
+    assert api.read_status(ws) == 0
 
 
 def test_cell_beyond_one_sort_chunk(gpu):
