@@ -273,9 +273,10 @@ def serving(n_req, dev, max_batch, inflight):
     items = S.prepare(systems, dev)
     pairs = np.array(S.count_pairs(items, dev), dtype=np.int64)
     arrivals = np.array([r.arrival_s for r in reqs])
-    backend = S.GpuBackend(dev)
-    # warm both paths; one replay of every request at once also grows torch's caching
-    # allocator to the largest resident set, so no replay below waits on a device malloc
+    # every request's device buffers come from one pool allocated here, sized for the
+    # largest budget below (64 GB, or all requests resident if that is less)
+    backend = S.GpuBackend(dev, S.pool_bytes(items, 64 << 30), len(items), inflight)
+    # warm both paths
     S.run_policy(items, np.zeros(len(items)), backend, 64 << 30, max_batch, inflight)
     S.replay_plain(items[:8], np.zeros(8), dev)
     torch.cuda.synchronize()

@@ -222,6 +222,22 @@ md_status md_run_vv_f32(const md_params* p, int64_t n_atoms, float* d_pos, float
                         float* d_force, double dt_fs, int32_t n_steps, double* d_energies,
                         void* d_ws, size_t ws_bytes, void* stream);
 
+/* Serving runtime support (no passage of the paper: moving requests in and out).
+ * Copies n_segs byte ranges, each between device memory and pinned (hipHostMalloc) host
+ * memory or within device memory, with kernel launches on `stream` (one per 128 segments):
+ * the copies are enqueued in stream order like a kernel, without the runtime's copy
+ * engines. Segments of 0 bytes are skipped; the ranges of one call must not overlap. All
+ * memory is caller-owned and stays valid until the stream reaches the call.
+ * Errors: MD_ERR_INVALID_ARG (n_segs < 0, a null array, or a null address in a non-empty
+ * segment), MD_ERR_HIP if a launch fails. */
+typedef struct {
+  void* dst;
+  const void* src;
+  size_t bytes;
+} md_copy_segment;
+
+md_status md_copy_segments(const md_copy_segment* segs, int32_t n_segs, void* stream);
+
 /* Copies the sticky device status word of a workspace to *bits (MD_STATUS_* bits).
  * Synchronises `stream`. */
 md_status md_read_device_status(const void* d_ws, void* stream, uint32_t* bits);

@@ -59,6 +59,10 @@ class _System(C.Structure):
                 ("d_energy", C.c_void_p), ("d_ws", C.c_void_p), ("ws_bytes", C.c_size_t)]
 
 
+class _CopySegment(C.Structure):
+    _fields_ = [("dst", C.c_void_p), ("src", C.c_void_p), ("bytes", C.c_size_t)]
+
+
 class _Layout(C.Structure):
     _fields_ = [("dims", C.c_int32 * 3), ("n_cells", C.c_int64), ("cell_start", C.c_size_t),
                 ("perm", C.c_size_t), ("pair_count", C.c_size_t), ("energy_partials", C.c_size_t),
@@ -94,6 +98,8 @@ def lib():
         L.md_forces_batched.restype = C.c_int
         L.md_forces_f32_noalloc.argtypes = [pp, C.c_int64, vp, vp, vp, vp, vp, vp, vp]
         L.md_forces_f32_noalloc.restype = C.c_int
+        L.md_copy_segments.argtypes = [C.POINTER(_CopySegment), C.c_int32, vp]
+        L.md_copy_segments.restype = C.c_int
         L.md_run_vv_f32.argtypes = [pp, C.c_int64, vp, vp, vp, vp, vp, vp, C.c_double, C.c_int32,
                                     vp, vp, C.c_size_t, vp]
         L.md_run_vv_f32.restype = C.c_int
@@ -110,7 +116,7 @@ def lib():
 
 
 EXPORTED = ("md_workspace_bytes", "md_forces_f32", "md_forces_f32_stages", "md_forces_f64",
-            "md_forces_batched", "md_forces_f32_noalloc", "md_run_vv_f32",
+            "md_forces_batched", "md_forces_f32_noalloc", "md_copy_segments", "md_run_vv_f32",
             "md_read_device_status", "md_read_diag", "md_read_clock", "md_workspace_layout",
             "md_status_string")
 
@@ -307,6 +313,39 @@ def forces_batched(systems, stream=None):
     rc = lib().md_forces_batched(arr, len(systems), _stream_ptr(stream))
     if rc != MD_OK:
         raise MDError(rc, "md_forces_batched")
+
+
+def forces_batched_raw(systems, stream_ptr):
+    """md_forces_batched on raw device addresses: systems is a list of tuples
+    (params, n_atoms, pos, types, charges, force, energy, workspace, workspace_bytes)."""
+    arr = (_System * len(systems))()
+    keep = []
+    for k, (prm, n, pos, typ, q, f, e, ws, wsb) in enumerate(systems):
+        p = _as_params(prm)
+        keep.append(p)
+        arr[k].p = p.c
+        arr[k].n_atoms = n
+        arr[k].d_pos = pos
+        arr[k].d_type = typ
+        arr[k].d_charge = q
+        arr[k].d_force = f
+        arr[k].d_energy = e
+        arr[k].d_ws = ws
+        arr[k].ws_bytes = wsb
+    rc = lib().md_forces_batched(arr, len(systems), C.c_void_p(stream_ptr))
+    if rc != MD_OK:
+        raise MDError(rc, "md_forces_batched")
+
+
+def copy_segments(segments, stream_ptr):
+    """md_copy_segments: (dst, src, nbytes) address triples between device memory and
+    pinned host memory, copied by kernel on the stream."""
+    arr = (_CopySegment * len(segments))()
+    for k, (d, s_, nb) in enumerate(segments):
+        arr[k].dst, arr[k].src, arr[k].bytes = d, s_, nb
+    rc = lib().md_copy_segments(arr, len(segments), C.c_void_p(stream_ptr))
+    if rc != MD_OK:
+        raise MDError(rc, "md_copy_segments")
 
 
 def run_vv(params, pos, vel, types, charges, inv_mass, force, dt, n_steps, *, energies=None,

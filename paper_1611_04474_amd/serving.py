@@ -7,14 +7,27 @@ memory until its result is back on the host, and:
   * admits arrived requests in arrival order while the bytes they need stay within
     an HBM budget (workspace from md_workspace_bytes plus inputs and outputs);
   * copies an admitted request's inputs to the device on a copy stream as soon as it
-    is admitted, so copies overlap the batches already running;
+    is admitted, so copies overlap the batches already running (on an idle GPU they go on
+    the compute stream in front of the batch instead);
   * launches every admitted, not yet launched request as one batched call
     (md_forces_batched: one launch per kernel of the path for up to 10 systems of one
     kind) whenever fewer than `max_inflight` batches are on the GPU, so requests that
     arrive while others run join the next batch instead of waiting for the queue to
     drain;
-  * copies forces and energy back to pinned host memory behind each batch and retires
-    the batch when its event completes, releasing its budget.
+  * copies forces, energy and the workspace's device status word back to pinned host
+    memory behind each batch and retires the batch when its event completes, releasing
+    its budget; a request whose status word is set (NaN or out-of-box positions, bad
+    types, fixed-point overflow), or whose parameters the library rejects at admission,
+    is reported as failed without holding back the others.
+
+Nothing in the loop allocates or creates runtime objects: every request's device
+buffers are carved from one device buffer allocated up front (DeviceRing: requests are
+placed in admission order and released in launch order, so the free space is the ring
+between them), the streams' events are created up front and reused, and inputs and
+outputs move by md_copy_segments, a copy kernel that reads and writes the pinned host
+buffers through the device's mapping of them (checked once in prepare()): one launch per
+admitted request and one per batch. Runtime copies (hipMemcpyAsync) of the device-to-host
+results had now and then held the host for 6-8 ms in the call that enqueued them.
 
 `replay_plain` serves the same trace one request at a time with the plain call, the
 baseline. Both report per-request latency = host time at which the request's
@@ -26,12 +39,30 @@ interface so that it can be exercised without a GPU.
 from __future__ import annotations
 
 import collections
+import ctypes as C
 import time
 from dataclasses import dataclass, field
 
 import numpy as np
 
 IO_BYTES_PER_ATOM = 12 + 4 + 4 + 12     # float32 xyz, int32 type, float32 charge, float32 force
+_ALIGN = 256
+
+
+def _align(x):
+    return (x + _ALIGN - 1) // _ALIGN * _ALIGN
+
+
+def slot_layout(n, ws_bytes):
+    """Byte offsets of one request's device buffers within its slot, and the slot size:
+    the workspace first (256-byte aligned, its status word at offset 0), then positions,
+    types, charges, forces and energy."""
+    off, o = {}, 0
+    for name, nb in (("ws", ws_bytes), ("pos", 12 * n), ("types", 4 * n), ("charges", 4 * n),
+                     ("force", 12 * n), ("energy", 8)):
+        off[name] = o
+        o = _align(o + nb)
+    return off, o
 
 
 @dataclass
@@ -43,10 +74,15 @@ class Item:
     pos: object = None                   # pinned host tensors
     types: object = None
     charges: object = None
-    force_out: object = None             # pinned host output
+    force_out: object = None             # pinned host outputs
     energy_out: object = None
+    status_out: object = None            # pinned int32 [1]: the device status word
     pairs: int = 0                       # unique pairs within the cutoff (for throughput)
     bytes: int = 0                       # device bytes while resident
+    ws_bytes: int = 0
+    layout: dict = None                  # slot_layout offsets
+    valid: bool = True                   # False: the library rejects the parameters
+    status: int = 0                      # status word of the last evaluation
 
 
 @dataclass
@@ -57,6 +93,7 @@ class Stats:
     batches: list = field(default_factory=list)     # sizes of launched batches
     busy_s: float = 0.0                              # GPU time of the batches (events)
     peak_bytes: int = 0
+    failed: list = field(default_factory=list)       # rids rejected or with a status word set
 
     def summary(self, pairs):
         lat = self.latency_s * 1e3
@@ -72,6 +109,7 @@ class Stats:
             "mean_batch": float(np.mean(self.batches)) if self.batches else None,
             "max_batch": int(np.max(self.batches)) if self.batches else None,
             "peak_resident_MB": self.peak_bytes / 2 ** 20,
+            "failed": len(self.failed),
         }
 
 
@@ -80,7 +118,8 @@ def run_policy(items, arrivals, backend, budget_bytes, max_batch=32, max_infligh
     """Continuous batching over `items` arriving at `arrivals` (seconds from start).
 
     backend: admit(item) -> handle; launch(handles) -> batch; done(batch) -> bool;
-             release(handle); busy(batch) -> seconds of GPU time (after done).
+             release(handle) (sets item.status); busy(batch) -> seconds of GPU time
+             (after done).
     Returns Stats."""
     n = len(items)
     order = sorted(range(n), key=lambda k: arrivals[k])
@@ -94,6 +133,7 @@ def run_policy(items, arrivals, backend, budget_bytes, max_batch=32, max_infligh
     used = peak = 0
     done_s = np.full(n, np.nan)
     sizes = []
+    failed = []
     busy = 0.0
     t0 = clock()
     remaining = n
@@ -108,10 +148,18 @@ def run_policy(items, arrivals, backend, budget_bytes, max_batch=32, max_infligh
                 done_s[k] = t
                 used -= items[k].bytes
                 backend.release(h)
+                if items[k].status:
+                    failed.append(items[k].rid)
                 remaining -= 1
-        # admit arrived requests, in arrival order, within the budget
+        # admit arrived requests, in arrival order, within the budget; a request whose
+        # parameters the library rejects completes at once, as failed
         while waiting and arrivals[waiting[0]] <= now and used + items[waiting[0]].bytes <= budget_bytes:
             k = waiting.popleft()
+            if not items[k].valid:
+                done_s[k] = clock() - t0
+                failed.append(items[k].rid)
+                remaining -= 1
+                continue
             ready.append((k, backend.admit(items[k])))
             used += items[k].bytes
             peak = max(peak, used)
@@ -122,86 +170,190 @@ def run_policy(items, arrivals, backend, budget_bytes, max_batch=32, max_infligh
             sizes.append(len(members))
     arr = np.asarray(arrivals, dtype=np.float64)
     return Stats(latency_s=done_s - arr, arrival_s=arr, done_s=done_s, batches=sizes,
-                 busy_s=busy, peak_bytes=peak)
+                 busy_s=busy, peak_bytes=peak, failed=failed)
 
+
+# ------------------------------------------------------------------ device side ----
 
 _HIP = None
 
 
-def copy_async(dst, src, stream):
-    """Stream-ordered copy between a pinned host tensor and a device tensor of the same
-    byte size, through hipMemcpyAsync itself. torch's non-blocking copy also records an
-    event on the pinned host block for each copy; the serving buffers live for the whole
-    run, so those events pile up, and now and then recording one held the host for 7-10 ms,
-    which showed as the batched tail at high request rates."""
+def _hip():
     global _HIP
-    import ctypes as C
     if _HIP is None:
         lib = C.CDLL("libamdhip64.so")
         lib.hipMemcpyAsync.restype = C.c_int
         lib.hipMemcpyAsync.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p]
         _HIP = lib
+    return _HIP
+
+
+H2D, D2H = 1, 2      # hipMemcpyHostToDevice, hipMemcpyDeviceToHost
+
+
+def memcpy_async(dst, src, nbytes, kind, stream_ptr):
+    """Stream-ordered hipMemcpyAsync between pinned host memory and device memory, on raw
+    addresses (the caller has checked them). torch's non-blocking copy records an event
+    on the pinned host block for every copy, and long-lived serving buffers pile those
+    up; a plain hipMemcpyAsync has no such bookkeeping."""
+    rc = _hip().hipMemcpyAsync(C.c_void_p(dst), C.c_void_p(src), nbytes, kind,
+                               C.c_void_p(stream_ptr))
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpyAsync failed with code {rc}")
+
+
+def copy_async(dst, src, stream):
+    """memcpy_async between one pinned host tensor and one device tensor of the same byte
+    size (checked)."""
     nbytes = src.numel() * src.element_size()
     if dst.numel() * dst.element_size() != nbytes:
         raise ValueError("copy_async: sizes differ")
     host = src if dst.is_cuda else dst
     if host.is_cuda or not host.is_pinned() or not (src.is_contiguous() and dst.is_contiguous()):
         raise ValueError("copy_async: needs one pinned host and one device tensor, contiguous")
-    kind = 1 if dst.is_cuda else 2          # hipMemcpyHostToDevice, hipMemcpyDeviceToHost
-    rc = _HIP.hipMemcpyAsync(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), nbytes, kind,
-                             C.c_void_p(stream.cuda_stream))
-    if rc != 0:
-        raise RuntimeError(f"hipMemcpyAsync failed with code {rc}")
+    memcpy_async(dst.data_ptr(), src.data_ptr(), nbytes, H2D if dst.is_cuda else D2H,
+                 stream.cuda_stream)
 
 
-def _to_device(t, device, stream):
-    import torch
-    d = torch.empty(t.shape, dtype=t.dtype, device=device)
-    copy_async(d, t, stream)
-    return d
+def _inputs(it, p):
+    """Copy segments of a request's inputs, pinned host -> its device slot."""
+    return [(p["pos"], it.pos.data_ptr(), 12 * it.n), (p["types"], it.types.data_ptr(), 4 * it.n),
+            (p["charges"], it.charges.data_ptr(), 4 * it.n)]
+
+
+def _outputs(it, p):
+    """Copy segments of a request's results, device slot -> pinned host: forces, energy
+    and the workspace's status word."""
+    return [(it.force_out.data_ptr(), p["force"], 12 * it.n),
+            (it.energy_out.data_ptr(), p["energy"], 8), (it.status_out.data_ptr(), p["ws"], 4)]
+
+
+def device_mapped(t):
+    """True if the pinned host tensor t is mapped into the device's address space at its
+    host address (hipHostGetDevicePointer gives the same address), so a kernel may read and
+    write it there."""
+    dp = C.c_void_p(0)
+    lib = _hip()
+    lib.hipHostGetDevicePointer.restype = C.c_int
+    lib.hipHostGetDevicePointer.argtypes = [C.POINTER(C.c_void_p), C.c_void_p, C.c_uint]
+    rc = lib.hipHostGetDevicePointer(C.byref(dp), C.c_void_p(t.data_ptr()), 0)
+    return rc == 0 and dp.value == t.data_ptr()
+
+
+class DeviceRing:
+    """FIFO sub-allocator over one device buffer allocated up front. Requests are placed
+    in admission order and released in launch order (batches retire in order), so the
+    live slots form one run around the ring and the free space is the rest of it, in at
+    most two pieces. With a capacity of (most bytes ever resident) + (largest slot), a
+    slot that fits the byte budget always finds a contiguous place: at most one piece is
+    lost to a wrap, and it is smaller than the slot that wrapped."""
+
+    def __init__(self, capacity, device):
+        import torch
+        self.capacity = _align(int(capacity))
+        self.buf = torch.empty(self.capacity, dtype=torch.uint8, device=device)
+        self.base = self.buf.data_ptr()
+        self.live = collections.deque()     # [start, end, freed] in placement order
+
+    def alloc(self, nbytes):
+        n = _align(int(nbytes))
+        if not self.live:
+            start = 0
+        else:
+            tail, head = self.live[0][0], self.live[-1][1]
+            if head > tail:                  # not wrapped: free [head, end) and [0, tail)
+                if self.capacity - head >= n:
+                    start = head
+                elif tail >= n:
+                    start = 0
+                else:
+                    return None
+            else:                            # wrapped: the free run is [head, tail)
+                if tail - head >= n:
+                    start = head
+                else:
+                    return None
+        if start + n > self.capacity:
+            return None
+        self.live.append([start, start + n, False])
+        return start
+
+    def free(self, start):
+        for rec in self.live:
+            if rec[0] == start and not rec[2]:
+                rec[2] = True
+                break
+        else:
+            raise ValueError("DeviceRing.free: no live slot at that offset")
+        while self.live and self.live[0][2]:
+            self.live.popleft()
+
+
+class _Handle:
+    __slots__ = ("item", "off", "ptr", "copied")
 
 
 class GpuBackend:
-    """Backend of run_policy on one HIP device: device tensors per admitted request,
-    host-to-device copies on a copy stream, batched force calls and device-to-host
-    copies on a compute stream, one event pair per batch."""
+    """Backend of run_policy on one HIP device: a slot of one preallocated device buffer
+    per admitted request, host-to-device copies on a copy stream, batched force calls and
+    device-to-host copies (forces, energy, status word) on a compute stream, timing events
+    reused from a pool."""
 
-    def __init__(self, device):
+    def __init__(self, device, pool_bytes, max_requests, max_inflight=2):
         import torch
         self.torch = torch
         self.device = device
+        self.ring = DeviceRing(pool_bytes, device)
         self.copy = torch.cuda.Stream(device)       # default priority
         self.compute = torch.cuda.Stream(device)
+        self.copy_ptr = self.copy.cuda_stream
+        self.compute_ptr = self.compute.cuda_stream
+        # one "inputs copied" event per request that can be admitted and not yet launched,
+        # one timing pair per batch that can be in flight (plus one being retired)
+        self.copied = [torch.cuda.Event() for _ in range(max(1, max_requests))]
+        self.next_copied = 0
+        self.timers = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                       for _ in range(max_inflight + 2)]
+        self.next_timer = 0
+        self.running = 0          # batches launched and not yet retired
 
     def admit(self, it):
         from . import api
-        torch = self.torch
-        with torch.cuda.stream(self.copy):
-            h = dict(item=it,
-                     pos=_to_device(it.pos, self.device, self.copy),
-                     types=_to_device(it.types, self.device, self.copy),
-                     charges=_to_device(it.charges, self.device, self.copy),
-                     force=torch.empty((it.n, 3), dtype=torch.float32, device=self.device),
-                     energy=torch.empty(1, dtype=torch.float64, device=self.device),
-                     workspace=api.alloc_workspace(it.params, it.n, self.device))
-            h["copied"] = torch.cuda.Event()
-            h["copied"].record(self.copy)
+        off = self.ring.alloc(it.bytes)
+        if off is None:
+            raise RuntimeError(f"request {it.rid}: no room in the device pool "
+                               f"({self.ring.capacity} bytes)")
+        h = _Handle()
+        h.item, h.off = it, off
+        h.ptr = {k: self.ring.base + off + v for k, v in it.layout.items()}
+        if self.running == 0:
+            # the GPU is idle: the inputs go in on the compute stream in front of the batch
+            # (launch), with no event between two streams
+            h.copied = None
+            return h
+        api.copy_segments(_inputs(it, h.ptr), self.copy_ptr)
+        h.copied = self.copied[self.next_copied]
+        self.next_copied = (self.next_copied + 1) % len(self.copied)
+        h.copied.record(self.copy)
         return h
 
     def launch(self, handles):
         from . import api
-        torch = self.torch
         for h in handles:
-            self.compute.wait_event(h["copied"])
-        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            if h.copied is not None:
+                self.compute.wait_event(h.copied)
+        start, end = self.timers[self.next_timer]
+        self.next_timer = (self.next_timer + 1) % len(self.timers)
         start.record(self.compute)
-        api.forces_batched([dict(params=h["item"].params, pos=h["pos"], types=h["types"],
-                                 charges=h["charges"], force=h["force"], energy=h["energy"],
-                                 workspace=h["workspace"]) for h in handles],
-                           stream=self.compute)
-        for h in handles:
-            copy_async(h["item"].force_out, h["force"], self.compute)
-            copy_async(h["item"].energy_out, h["energy"], self.compute)
+        deferred = [seg for h in handles if h.copied is None for seg in _inputs(h.item, h.ptr)]
+        if deferred:
+            api.copy_segments(deferred, self.compute_ptr)
+        self.running += 1
+        api.forces_batched_raw([(h.item.params, h.item.n, h.ptr["pos"], h.ptr["types"],
+                                 h.ptr["charges"], h.ptr["force"], h.ptr["energy"], h.ptr["ws"],
+                                 h.item.ws_bytes) for h in handles], self.compute_ptr)
+        api.copy_segments([seg for h in handles for seg in _outputs(h.item, h.ptr)],
+                          self.compute_ptr)
         end.record(self.compute)
         return (start, end)
 
@@ -209,47 +361,62 @@ class GpuBackend:
         return batch[1].query()
 
     def busy(self, batch):
+        # called once per batch, when it retires
+        self.running -= 1
         return batch[0].elapsed_time(batch[1]) * 1e-3
 
     def release(self, h):
-        h.clear()
+        h.item.status = int(h.item.status_out[0])
+        self.ring.free(h.off)
 
 
 def replay_plain(items, arrivals, device, clock=time.perf_counter):
     """Baseline: FIFO, one request at a time with the plain call (copy in, md_forces_f32,
-    copy out, wait)."""
+    copy out, wait), on device buffers and events made before the replay starts."""
     import torch
     from . import api
     n = len(items)
     order = sorted(range(n), key=lambda k: arrivals[k])
     done_s = np.full(n, np.nan)
+    ring = DeviceRing(max(it.bytes for it in items), device)
     stream = torch.cuda.Stream(device)
+    sp = stream.cuda_stream
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    failed = []
     busy = 0.0
     t0 = clock()
     for k in order:
         while clock() - t0 < arrivals[k]:
             pass
         it = items[k]
-        with torch.cuda.stream(stream):
-            start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            start.record(stream)
-            pos = _to_device(it.pos, device, stream)
-            types = _to_device(it.types, device, stream)
-            q = _to_device(it.charges, device, stream)
-            f, e = api.forces(it.params, pos, types, q, stream=stream)
-            copy_async(it.force_out, f, stream)
-            copy_async(it.energy_out, e, stream)
-            end.record(stream)
+        if not it.valid:
+            done_s[k] = clock() - t0
+            failed.append(it.rid)
+            continue
+        p = {key: ring.base + v for key, v in it.layout.items()}
+        start.record(stream)
+        api.copy_segments(_inputs(it, p), sp)
+        rc = api.forces_raw(it.params, it.n, p["pos"], p["types"], p["charges"], p["force"],
+                            p["energy"], p["ws"], it.ws_bytes, sp)
+        if rc != api.MD_OK:
+            raise api.MDError(rc, "md_forces_f32")
+        api.copy_segments(_outputs(it, p), sp)
+        end.record(stream)
         end.synchronize()
         done_s[k] = clock() - t0
         busy += start.elapsed_time(end) * 1e-3
+        it.status = int(it.status_out[0])
+        if it.status:
+            failed.append(it.rid)
     arr = np.asarray(arrivals, dtype=np.float64)
     return Stats(latency_s=done_s - arr, arrival_s=arr, done_s=done_s, batches=[1] * n,
-                 busy_s=busy)
+                 busy_s=busy, failed=failed)
 
 
 def prepare(systems, device, pairs=None):
-    """Items with pinned host inputs and outputs for a list of workloads.System."""
+    """Items with pinned host inputs and outputs for a list of workloads.System; the
+    slot layout of each request's device buffers. A request whose parameters the library
+    rejects is marked invalid (it will be reported as failed, never launched)."""
     import torch
     from . import api
     items = []
@@ -260,12 +427,26 @@ def prepare(systems, device, pairs=None):
                   types=torch.from_numpy(np.ascontiguousarray(s.types, dtype=np.int32)).pin_memory(),
                   charges=torch.from_numpy(np.ascontiguousarray(s.charges, dtype=np.float32)).pin_memory(),
                   force_out=torch.empty((s.n, 3), dtype=torch.float32).pin_memory(),
-                  energy_out=torch.empty(1, dtype=torch.float64).pin_memory())
-        it.bytes = api.workspace_bytes(p, s.n) + IO_BYTES_PER_ATOM * s.n + 8
+                  energy_out=torch.empty(1, dtype=torch.float64).pin_memory(),
+                  status_out=torch.zeros(1, dtype=torch.int32).pin_memory())
+        for t in (it.pos, it.types, it.charges, it.force_out, it.energy_out, it.status_out):
+            if not (t.is_pinned() and t.is_contiguous() and device_mapped(t)):
+                raise RuntimeError("serving buffers must be pinned host memory mapped into the "
+                                   "device at the same address")
+        it.ws_bytes = api.workspace_bytes(p, s.n)
+        it.valid = it.ws_bytes > 0
+        it.layout, it.bytes = slot_layout(s.n, max(it.ws_bytes, _ALIGN))
         if pairs is not None:
             it.pairs = int(pairs[k])
         items.append(it)
     return items
+
+
+def pool_bytes(items, budget_bytes):
+    """Device pool for a GpuBackend serving `items` under `budget_bytes`: the most that can
+    be resident (the budget, or all the requests if that is less) plus the largest slot."""
+    total = sum(it.bytes for it in items if it.valid)
+    return min(budget_bytes, total) + max(it.bytes for it in items)
 
 
 def count_pairs(items, device):

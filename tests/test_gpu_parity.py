@@ -518,9 +518,9 @@ def test_batched_matches_alone(gpu):
 
 def test_serving_loop_outputs(gpu):
     """The serving loop's results equal the plain call's on the same requests, bit for bit:
-    inputs copied in and forces copied out with copy_async (hipMemcpyAsync between pinned
-    host and device memory), batched launches of up to 4 requests; and so do the results
-    of the one-at-a-time replay."""
+    inputs copied in and forces copied out with hipMemcpyAsync between pinned host memory
+    and slots of one preallocated device pool, batched launches of up to 4 requests; and
+    so do the results of the one-at-a-time replay."""
     _say("case: serving loop and plain replay, 12 trace requests, against direct calls")
     import torch
     from paper_1611_04474_amd import serving as S
@@ -531,7 +531,9 @@ def test_serving_loop_outputs(gpu):
     for it in items:
         it.force_out.fill_(float("nan"))
         it.energy_out.fill_(float("nan"))
-    st = S.run_policy(items, np.zeros(len(items)), S.GpuBackend(gpu), 64 << 30, 4, 2)
+    be = S.GpuBackend(gpu, S.pool_bytes(items, 64 << 30), len(items), 2)
+    st = S.run_policy(items, np.zeros(len(items)), be, 64 << 30, 4, 2)
+    assert st.failed == []
     assert max(st.batches) > 1
     torch.cuda.synchronize()
     got = [(it.force_out.clone(), it.energy_out.clone()) for it in items]
@@ -750,3 +752,59 @@ def test_overflow_bound_follows_slices(gpu):
             ref = oracle.forces(p, pos, t, q, "bruteforce")
             err = force_errors(f[:2], ref.force[:2], ref.abs_sum[:2])
             assert err["max_norm"] <= 1e-5 and err["rms"] <= 1e-5, err
+
+
+def test_serving_failed_request_alone(gpu):
+    """A request with a NaN position in a batch of six comes back failed (its device status
+    word, copied back behind the results); the other five give the plain call's bits. A
+    request whose box the library rejects fails at admission and is never launched."""
+    _say("case: serving loop with a NaN request and a rejected one")
+    import torch
+    from paper_1611_04474_amd import serving as S
+    from _gpu import to_dev
+    reqs, table = W.serving_trace(n_req=7)
+    systems = [W.request_system(r, table) for r in reqs]
+    systems[5].box = np.array([20.0, 20.0, 20.0])      # under 2 r_cut: rejected
+    items = S.prepare(systems, gpu)
+    assert not items[5].valid and all(it.valid for k, it in enumerate(items) if k != 5)
+    items[3].pos[5, 0] = float("nan")
+    be = S.GpuBackend(gpu, S.pool_bytes(items, 64 << 30), len(items), 2)
+    st = S.run_policy(items, np.zeros(len(items)), be, 64 << 30, 8, 2)
+    assert sorted(st.failed) == [3, 5], st.failed
+    assert items[3].status & api.STATUS_NAN
+    for k, (it, s) in enumerate(zip(items, systems)):
+        if k in (3, 5):
+            continue
+        assert it.status == 0
+        d = to_dev((s.pos, s.types, s.charges), gpu)
+        f, e = api.forces(it.params, *d)
+        assert torch.equal(it.force_out, f.cpu()) and torch.equal(it.energy_out, e.cpu()), k
+    st = S.replay_plain(items, np.zeros(len(items)), gpu)
+    assert sorted(st.failed) == [3, 5]
+
+
+def test_copy_segments(gpu):
+    """md_copy_segments moves byte ranges pinned host -> device and device -> pinned host
+    with one kernel launch per call: 16-byte and byte-wise paths (misaligned ends), ranges
+    of several 64 KB chunks, and empty ranges."""
+    _say("case: md_copy_segments")
+    import torch
+    from paper_1611_04474_amd import serving as S
+    rng = np.random.default_rng(8)
+    sizes = [0, 1, 15, 16, 4096 + 3, 3 * 65536 + 40, 1 << 20]
+    host = [torch.from_numpy(rng.integers(0, 256, n + 32, dtype=np.uint8)).pin_memory() for n in sizes]
+    for h in host:
+        assert S.device_mapped(h)
+    dev = [torch.zeros(n + 32, dtype=torch.uint8, device=gpu) for n in sizes]
+    back = [torch.zeros(n + 32, dtype=torch.uint8).pin_memory() for n in sizes]
+    stream = torch.cuda.current_stream()
+    # host -> device at offsets 0 (aligned) and 3 (misaligned), then device -> host
+    for off in (0, 3):
+        api.copy_segments([(d.data_ptr() + off, h.data_ptr() + off, n)
+                           for d, h, n in zip(dev, host, sizes)], stream.cuda_stream)
+        api.copy_segments([(b.data_ptr() + off, d.data_ptr() + off, n)
+                           for b, d, n in zip(back, dev, sizes)], stream.cuda_stream)
+        torch.cuda.synchronize()
+        for d, h, b, n in zip(dev, host, back, sizes):
+            assert torch.equal(d.cpu()[off:off + n], h[off:off + n]), n
+            assert torch.equal(b[off:off + n], h[off:off + n]), n

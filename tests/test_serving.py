@@ -96,3 +96,57 @@ def test_request_larger_than_budget_is_refused():
     items = _items([10, 1000])
     with pytest.raises(ValueError):
         run_policy(items, np.zeros(2), FakeBackend(), budget_bytes=50_000)
+
+
+def test_invalid_request_fails_alone():
+    """A request the library rejects at admission is reported as failed at once; the
+    others are served."""
+    items = _items([10, 20, 30, 40])
+    items[2].valid = False
+    be = FakeBackend(batch_s=0.001)
+    st = run_policy(items, np.zeros(4), be, budget_bytes=10 ** 6, max_batch=8)
+    assert st.failed == [2]
+    launched = [r for e in be.events if e[0] == "launch" for r in e[2]]
+    assert sorted(launched) == [0, 1, 3]
+    assert np.all(np.isfinite(st.done_s))
+
+
+class _Ring:
+    """The DeviceRing placement logic on a host stand-in for the device buffer."""
+
+    def __new__(cls, capacity):
+        from paper_1611_04474_amd import serving as S
+        r = object.__new__(S.DeviceRing)
+        r.capacity = S._align(capacity)
+        r.base = 0
+        r.live = __import__("collections").deque()
+        return r
+
+
+def test_device_ring_fifo_placement():
+    """Slots placed in admission order and freed in launch order never overlap and always
+    fit while the bytes held stay within capacity - largest slot."""
+    rng = np.random.default_rng(4)
+    big = 256 * 40
+    ring = _Ring(256 * 400 + big)
+    live = []                       # (start, size) in placement order
+    held = 0
+    for step in range(3000):
+        if live and (rng.random() < 0.45 or held > 256 * 350):
+            start, size = live.pop(0)
+            ring.free(start)
+            held -= size
+            continue
+        size = 256 * int(rng.integers(1, 41))
+        if held + size > 256 * 400:
+            continue
+        start = ring.alloc(size)
+        assert start is not None, (step, held, size)
+        for s0, n0 in live:
+            assert start + size <= s0 or s0 + n0 <= start
+        assert 0 <= start and start + size <= ring.capacity
+        live.append((start, size))
+        held += size
+    for start, _ in live:
+        ring.free(start)
+    assert not ring.live
