@@ -20,6 +20,7 @@ _LIB_PATH = os.path.join(_HERE, "libmdoracle.so")
 _lib = None
 
 FLAG_TRUNCATED_COULOMB = 1 << 1
+FLAG_EWALD = 1 << 7
 STATUS_NAN = 1 << 0
 STATUS_OUT_OF_BOX = 1 << 1
 
@@ -28,7 +29,7 @@ class _Params(C.Structure):
     _fields_ = [("box", C.c_double * 3), ("r_cut", C.c_double), ("r_switch", C.c_double),
                 ("coulomb_k", C.c_double), ("n_types", C.c_int32),
                 ("sigma", C.POINTER(C.c_double)), ("epsilon", C.POINTER(C.c_double)),
-                ("flags", C.c_uint32)]
+                ("flags", C.c_uint32), ("ewald_alpha", C.c_double)]
 
 
 class OracleError(RuntimeError):
@@ -62,10 +63,11 @@ def lib():
         _lib.mdo_pairs_bruteforce.argtypes = [pp, C.c_int64, dp, C.c_int64, lp, ip]
         _lib.mdo_pairs_celllist.argtypes = [pp, C.c_int64, dp, C.c_int64, lp, ip]
         _lib.mdo_band_atoms.argtypes = [pp, C.c_int64, dp, C.c_double, lp, lp, C.c_int]
+        _lib.mdo_ewald_recip.argtypes = [pp, C.c_int64, dp, dp, ip, dp, dp, dp, dp, C.c_int]
         for f in ("mdo_grid", "mdo_bin", "mdo_canonicalize_f32", "mdo_canonicalize_f64",
                   "mdo_pair_terms", "mdo_forces_bruteforce", "mdo_forces_celllist",
                   "mdo_forces_subset", "mdo_pairs_bruteforce", "mdo_pairs_celllist",
-                  "mdo_band_atoms"):
+                  "mdo_band_atoms", "mdo_ewald_recip"):
             getattr(_lib, f).restype = C.c_int
     return _lib
 
@@ -77,19 +79,19 @@ def _ptr(a, ctype):
 class Params:
     """Holds a C parameter struct and keeps its arrays alive."""
 
-    def __init__(self, box, r_cut, r_switch, coulomb_k, sigma, epsilon, flags=0):
+    def __init__(self, box, r_cut, r_switch, coulomb_k, sigma, epsilon, flags=0, ewald_alpha=0.0):
         self.sigma = np.ascontiguousarray(sigma, dtype=np.float64)
         self.epsilon = np.ascontiguousarray(epsilon, dtype=np.float64)
         self.box = np.asarray(box, dtype=np.float64)
         self.c = _Params((C.c_double * 3)(*[float(b) for b in self.box]), float(r_cut),
                          float(r_switch), float(coulomb_k), int(self.sigma.shape[0]),
                          _ptr(self.sigma, C.c_double), _ptr(self.epsilon, C.c_double),
-                         int(flags))
+                         int(flags), float(ewald_alpha))
 
     @classmethod
     def from_dict(cls, d):
         return cls(d["box"], d["r_cut"], d["r_switch"], d["coulomb_k"], d["sigma"],
-                   d["epsilon"], d.get("flags", 0))
+                   d["epsilon"], d.get("flags", 0), d.get("ewald_alpha", 0.0))
 
     def ref(self):
         return C.byref(self.c)
@@ -240,6 +242,25 @@ def band_atoms(params, pos, band, n_threads=0):
     _check(lib().mdo_band_atoms(p.ref(), n, _ptr(pos64, C.c_double), float(band), C.byref(tot),
                                 _ptr(per, C.c_int64), int(n_threads)), "mdo_band_atoms")
     return per, int(tot.value)
+
+
+def ewald_recip(params, pos, charges, kmax, n_threads=0):
+    """Ewald reciprocal-space forces [n,3] and the energies (recip, self, background) for
+    positions pos (canonicalised like the force path) and charges, over every wave vector
+    with |m_d| <= kmax[d] (params['ewald_alpha'] is the splitting parameter)."""
+    p = _as_params(params)
+    pos64, st = canonicalize(pos, p.box)
+    if st:
+        raise OracleError(f"input positions rejected (status {st:#x})")
+    q = np.ascontiguousarray(np.asarray(charges).astype(np.float64))
+    km = np.ascontiguousarray(kmax, dtype=np.int32)
+    n = pos64.shape[0]
+    F = np.zeros((n, 3), dtype=np.float64)
+    er, es, eb = C.c_double(0), C.c_double(0), C.c_double(0)
+    _check(lib().mdo_ewald_recip(p.ref(), n, _ptr(pos64, C.c_double), _ptr(q, C.c_double),
+                                 _ptr(km, C.c_int32), _ptr(F, C.c_double), C.byref(er),
+                                 C.byref(es), C.byref(eb), int(n_threads)), "mdo_ewald_recip")
+    return F, er.value, es.value, eb.value
 
 
 # ---------------------------------------------------------------------------------------

@@ -41,6 +41,12 @@
  * n_d - 1 cells so that rounding at a cell face can never hide a pair; fewer than
  * 2 cells on an axis (L_d < 2 rc) is rejected.
  *
+ * Beyond the cutoff (Section 2.1 hands the long-range Coulomb force to an O(N)
+ * approximation on the CPU), read as Ewald summation: with MDO_FLAG_EWALD the Coulomb
+ * term inside the cutoff is the real-space part k qi qj erfc(alpha r)/r (only the LJ
+ * energy switched), and mdo_ewald_recip sums the reciprocal-space part, the self term
+ * and the neutralising background plainly over wave vectors.
+ *
  * Canonicalisation: positions in [-L, 2L) are wrapped into [0, L] by one add or
  * subtract of L in the precision of the input (float32 inputs are wrapped in
  * float32, then promoted exactly to double). NaN or positions outside [-L, 2L)
@@ -63,6 +69,8 @@
 #define MDO_ERR_NOMEM (-7)
 
 #define MDO_FLAG_TRUNCATED_COULOMB (1u << 1)
+#define MDO_FLAG_EWALD (1u << 7)
+#define MDO_PI 3.14159265358979323846
 
 #define MDO_STATUS_NAN (1u << 0)
 #define MDO_STATUS_OUT_OF_BOX (1u << 1)
@@ -77,6 +85,7 @@ typedef struct {
   const double* sigma;
   const double* epsilon;
   uint32_t flags;
+  double ewald_alpha; /* 1/A, with MDO_FLAG_EWALD */
 } mdo_params;
 
 /* Per-call constants: the mixed LJ table and the switching constants. */
@@ -87,6 +96,8 @@ typedef struct {
   double rc2, rs2, k;
   int switching;
   int truncated_coulomb;
+  int ewald;
+  double alpha;
   double L[3];
 } ctx_t;
 
@@ -119,6 +130,13 @@ static int ctx_init(ctx_t* c, const mdo_params* p) {
   c->k = p->coulomb_k;
   c->switching = p->r_switch < p->r_cut;
   c->truncated_coulomb = (p->flags & MDO_FLAG_TRUNCATED_COULOMB) != 0;
+  c->ewald = (p->flags & MDO_FLAG_EWALD) != 0;
+  c->alpha = p->ewald_alpha;
+  if (c->ewald && !(c->alpha > 0)) {
+    free(c->c12);
+    free(c->c6);
+    return MDO_ERR_ARG;
+  }
   return MDO_OK;
 }
 
@@ -161,6 +179,17 @@ static double pair_fe(const ctx_t* c, int ti, int tj, double qi, double qj, doub
   double f_c = e_c * inv_u;
   double S, dS;
   switch_fn(c, u, &S, &dS);
+  if (c->ewald) {
+    /* Ewald real-space term (the Coulomb energy split as erfc + erf, the erf part summed
+     * in reciprocal space): e = k qi qj erfc(alpha r) / r, and
+     * f = -(1/r) de/dr = k qi qj (erfc(alpha r)/r + 2 alpha/sqrt(pi) exp(-alpha^2 r^2)) / r^2;
+     * only the LJ energy is switched */
+    const double ar = c->alpha * r;
+    e_c = c->k * qi * qj * erfc(ar) / r;
+    f_c = c->k * qi * qj * (erfc(ar) / r + 2.0 * c->alpha / sqrt(MDO_PI) * exp(-ar * ar)) * inv_u;
+    *e = S * e_lj + e_c;
+    return S * f_lj - 2.0 * dS * e_lj + f_c;
+  }
   if (c->truncated_coulomb) {
     *e = S * e_lj + e_c;
     return S * f_lj - 2.0 * dS * e_lj + f_c;
@@ -707,5 +736,100 @@ int mdo_band_atoms(const mdo_params* p, int64_t n, const double* pos, double ban
   *n_band_pairs = total;
   cells_free(&cl);
   ctx_free(&c);
+  return MDO_OK;
+}
+
+/* --------------------------------------------- Ewald reciprocal space ---- */
+
+/*
+ * The Coulomb interaction beyond the cutoff (Section 2.1 leaves it to an O(N)
+ * approximation outside the short-range kernel). Read here as Ewald summation for the
+ * periodic box: with the real-space erfc term inside the cutoff (MDO_FLAG_EWALD), the
+ * rest of the Coulomb energy is
+ *   E_recip = k/(2V) sum_{kv != 0} (4 pi / |kv|^2) exp(-|kv|^2 / (4 alpha^2)) |S(kv)|^2,
+ *   S(kv)   = sum_j q_j exp(i kv . r_j),   kv = 2 pi (mx/Lx, my/Ly, mz/Lz),
+ *   E_self  = -k alpha / sqrt(pi) sum_j q_j^2,
+ *   E_bg    = -k pi Q^2 / (2 V alpha^2)   (neutralising background for net charge Q),
+ * summed here over every kv with |m_d| <= kmax_d, written out plainly (no symmetry,
+ * no tables), and
+ *   F_i = -dE_recip/dr_i = (4 pi k q_i / V) sum_kv (kv / |kv|^2) exp(-|kv|^2/(4 alpha^2))
+ *         Im(conj(S(kv)) exp(i kv . r_i)).
+ */
+int mdo_ewald_recip(const mdo_params* p, int64_t n, const double* pos, const double* q,
+                    const int32_t kmax[3], double* force, double* e_recip, double* e_self,
+                    double* e_bg, int n_threads) {
+  if (!p || n < 0 || (n > 0 && (!pos || !q)) || !kmax || !(p->ewald_alpha > 0)) return MDO_ERR_ARG;
+  for (int d = 0; d < 3; ++d)
+    if (kmax[d] < 0 || !(p->box[d] > 0)) return MDO_ERR_ARG;
+  const double a = p->ewald_alpha, k = p->coulomb_k;
+  const double V = p->box[0] * p->box[1] * p->box[2];
+  const int64_t nx = 2 * kmax[0] + 1, ny = 2 * kmax[1] + 1, nz = 2 * kmax[2] + 1;
+  const int64_t nk = nx * ny * nz;
+  double* sre = (double*)calloc((size_t)nk, sizeof(double));
+  double* sim = (double*)calloc((size_t)nk, sizeof(double));
+  double* ek = (double*)calloc((size_t)nk, sizeof(double));
+  if (!sre || !sim || !ek) {
+    free(sre);
+    free(sim);
+    free(ek);
+    return MDO_ERR_NOMEM;
+  }
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(static)
+#endif
+  for (int64_t t = 0; t < nk; ++t) {
+    const int mx = (int)(t / (ny * nz)) - kmax[0];
+    const int my = (int)((t / nz) % ny) - kmax[1];
+    const int mz = (int)(t % nz) - kmax[2];
+    if (mx == 0 && my == 0 && mz == 0) continue;
+    const double kv[3] = {2.0 * MDO_PI * mx / p->box[0], 2.0 * MDO_PI * my / p->box[1],
+                          2.0 * MDO_PI * mz / p->box[2]};
+    const double k2 = kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2];
+    double re = 0.0, im = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+      const double th = kv[0] * pos[3 * j] + kv[1] * pos[3 * j + 1] + kv[2] * pos[3 * j + 2];
+      re += q[j] * cos(th);
+      im += q[j] * sin(th);
+    }
+    sre[t] = re;
+    sim[t] = im;
+    ek[t] = k / (2.0 * V) * (4.0 * MDO_PI / k2) * exp(-k2 / (4.0 * a * a)) * (re * re + im * im);
+  }
+  double E = 0.0;
+  for (int64_t t = 0; t < nk; ++t) E += ek[t];
+  if (force) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+      double F[3] = {0.0, 0.0, 0.0};
+      for (int64_t t = 0; t < nk; ++t) {
+        const int mx = (int)(t / (ny * nz)) - kmax[0];
+        const int my = (int)((t / nz) % ny) - kmax[1];
+        const int mz = (int)(t % nz) - kmax[2];
+        if (mx == 0 && my == 0 && mz == 0) continue;
+        const double kv[3] = {2.0 * MDO_PI * mx / p->box[0], 2.0 * MDO_PI * my / p->box[1],
+                              2.0 * MDO_PI * mz / p->box[2]};
+        const double k2 = kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2];
+        const double th = kv[0] * pos[3 * i] + kv[1] * pos[3 * i + 1] + kv[2] * pos[3 * i + 2];
+        /* Im(conj(S) e^{i th}) = S_re sin(th) - S_im cos(th) */
+        const double w = exp(-k2 / (4.0 * a * a)) / k2 * (sre[t] * sin(th) - sim[t] * cos(th));
+        for (int d = 0; d < 3; ++d) F[d] += kv[d] * w;
+      }
+      for (int d = 0; d < 3; ++d) force[3 * i + d] = 4.0 * MDO_PI * k * q[i] / V * F[d];
+    }
+  }
+  double q2 = 0.0, Q = 0.0;
+  for (int64_t j = 0; j < n; ++j) {
+    q2 += q[j] * q[j];
+    Q += q[j];
+  }
+  if (e_recip) *e_recip = E;
+  if (e_self) *e_self = -k * a / sqrt(MDO_PI) * q2;
+  if (e_bg) *e_bg = -k * MDO_PI * Q * Q / (2.0 * V * a * a);
+  free(sre);
+  free(sim);
+  free(ek);
   return MDO_OK;
 }
