@@ -66,6 +66,14 @@ enum {
   MD_DIAG_COUNTERS = 1 << 2,    /* count candidates, filter passes and per-atom partners */
   MD_PAIR_PREDICATED = 1 << 3,  /* evaluate the force under the cutoff predicate, without
                                    compacting passing pairs (the uncompacted data flow) */
+  MD_COULOMB_EWALD = 1 << 7,    /* Coulomb inside the cutoff is the real-space term of an Ewald
+                                   sum, k q_i q_j erfc(alpha r)/r with alpha = ewald_alpha; only
+                                   the LJ energy is switched. The rest of the Coulomb energy (its
+                                   beyond-cutoff part, which Section 2.1 leaves to an O(N)
+                                   approximation outside the short-range kernel) comes from
+                                   md_ewald_recip_f32. Compacted kernel only (not with
+                                   MD_PAIR_PREDICATED, MD_COULOMB_TRUNCATED, or float64 with
+                                   MD_ACCUM_F32_ATOMIC) */
   MD_PAIR_FULL_SHELL = 1 << 4   /* compacted float32 path: evaluate every pair from both of
                                    its atoms, in the loop order of Algorithm 1 (Section 2.1),
                                    each atom's sum kept by one wave, no atomics. Default: each
@@ -104,6 +112,7 @@ typedef struct {
   const double* sigma;    /* host [n_types], A */
   const double* epsilon;  /* host [n_types], kcal/mol, >= 0 */
   uint32_t flags;         /* MD_* flags above */
+  double ewald_alpha;     /* 1/A, > 0: Ewald splitting parameter (MD_COULOMB_EWALD) */
 } md_params;
 
 /* Bytes of device workspace needed by md_forces_f32 (double_precision = 0) or
@@ -181,6 +190,36 @@ md_status md_forces_f32_noalloc(const md_params* p, int64_t n_atoms, const float
 md_status md_forces_f64(const md_params* p, int64_t n_atoms, const double* d_pos,
                         const int32_t* d_type, const double* d_charge, double* d_force,
                         double* d_energy, void* d_ws, size_t ws_bytes, void* stream);
+
+/* Ewald reciprocal-space sum: the Coulomb energy and forces beyond the short-range
+ * kernel. Section 2.1 splits the non-bonded work at the cutoff and leaves the Coulomb part
+ * beyond it to an approximation outside the short-range kernel; with MD_COULOMB_EWALD the
+ * short-range call evaluates the screened term k q_i q_j erfc(alpha r)/r inside the cutoff
+ * and this call the rest of the periodic Coulomb sum:
+ *   E = k/(2V) sum_{kv != 0} (4 pi/|kv|^2) exp(-|kv|^2/(4 alpha^2)) |S(kv)|^2
+ *       - k alpha/sqrt(pi) sum_j q_j^2 - k pi Q^2/(2 V alpha^2),
+ *   S(kv) = sum_j q_j exp(i kv . r_j),  kv = 2 pi (mx/Lx, my/Ly, mz/Lz), |m_d| <= kmax[d],
+ * (reciprocal sum, self term, neutralising background for net charge Q) and the forces
+ * -dE/dr_i. alpha is p->ewald_alpha (> 0); the box is p->box rounded to float32, r_cut and
+ * the type table are not used. Each atom's phase is exact modulo one turn (32-bit
+ * fixed-point fractional coordinates); sums run in float32 within tiles and float64
+ * across them, in a fixed order.
+ *   d_pos     [n_atoms][3] float32, any coordinates (the sum is periodic)
+ *   d_charge  [n_atoms] float32
+ *   kmax      host int32[3], each 0..255, not all 0
+ *   d_force   [n_atoms][3] float32 out, caller order: written, or added to when
+ *             accumulate != 0 (e.g. onto the short-range forces)
+ *   d_energy  [1] float64 out: reciprocal + self + background energy
+ *   d_ws      workspace of md_ewald_workspace_bytes(p, n_atoms, kmax) bytes, 256-B aligned;
+ *             its first word is a status word (MD_STATUS_NAN for a NaN position or charge),
+ *             read with md_read_device_status
+ * Errors: MD_ERR_INVALID_ARG (alpha, box, kmax, pointers), MD_ERR_WORKSPACE, MD_ERR_HIP.
+ * md_ewald_workspace_bytes returns 0 for invalid arguments. */
+size_t md_ewald_workspace_bytes(const md_params* p, int64_t n_atoms, const int32_t kmax[3]);
+md_status md_ewald_recip_f32(const md_params* p, int64_t n_atoms, const float* d_pos,
+                             const float* d_charge, const int32_t kmax[3], float* d_force,
+                             double* d_energy, int32_t accumulate, void* d_ws, size_t ws_bytes,
+                             void* stream);
 
 /* One system of a batch (float32 path). Every field as in md_forces_f32. */
 typedef struct {

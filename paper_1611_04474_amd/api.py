@@ -24,6 +24,7 @@ COULOMB_TRUNCATED = 1 << 1
 DIAG_COUNTERS = 1 << 2
 PAIR_PREDICATED = 1 << 3
 PAIR_FULL_SHELL = 1 << 4
+COULOMB_EWALD = 1 << 7
 PAIR_DRAIN_MASK = 3 << 5
 
 
@@ -50,7 +51,7 @@ class _Params(C.Structure):
     _fields_ = [("box", C.c_double * 3), ("r_cut", C.c_double), ("r_switch", C.c_double),
                 ("coulomb_k", C.c_double), ("n_types", C.c_int32),
                 ("sigma", C.POINTER(C.c_double)), ("epsilon", C.POINTER(C.c_double)),
-                ("flags", C.c_uint32)]
+                ("flags", C.c_uint32), ("ewald_alpha", C.c_double)]
 
 
 class _System(C.Structure):
@@ -100,6 +101,12 @@ def lib():
         L.md_forces_f32_noalloc.restype = C.c_int
         L.md_copy_segments.argtypes = [C.POINTER(_CopySegment), C.c_int32, vp]
         L.md_copy_segments.restype = C.c_int
+        ip3 = C.POINTER(C.c_int32)
+        L.md_ewald_workspace_bytes.argtypes = [pp, C.c_int64, ip3]
+        L.md_ewald_workspace_bytes.restype = C.c_size_t
+        L.md_ewald_recip_f32.argtypes = [pp, C.c_int64, vp, vp, ip3, vp, vp, C.c_int32, vp,
+                                         C.c_size_t, vp]
+        L.md_ewald_recip_f32.restype = C.c_int
         L.md_run_vv_f32.argtypes = [pp, C.c_int64, vp, vp, vp, vp, vp, vp, C.c_double, C.c_int32,
                                     vp, vp, C.c_size_t, vp]
         L.md_run_vv_f32.restype = C.c_int
@@ -116,7 +123,8 @@ def lib():
 
 
 EXPORTED = ("md_workspace_bytes", "md_forces_f32", "md_forces_f32_stages", "md_forces_f64",
-            "md_forces_batched", "md_forces_f32_noalloc", "md_copy_segments", "md_run_vv_f32",
+            "md_forces_batched", "md_forces_f32_noalloc", "md_copy_segments",
+            "md_ewald_workspace_bytes", "md_ewald_recip_f32", "md_run_vv_f32",
             "md_read_device_status", "md_read_diag", "md_read_clock", "md_workspace_layout",
             "md_status_string")
 
@@ -124,25 +132,28 @@ EXPORTED = ("md_workspace_bytes", "md_forces_f32", "md_forces_f32_stages", "md_f
 class Params:
     """md_params plus the host arrays it points to."""
 
-    def __init__(self, box, r_cut, r_switch, coulomb_k, sigma, epsilon, flags=0):
+    def __init__(self, box, r_cut, r_switch, coulomb_k, sigma, epsilon, flags=0, ewald_alpha=0.0):
         self.sigma = np.ascontiguousarray(sigma, dtype=np.float64)
         self.epsilon = np.ascontiguousarray(epsilon, dtype=np.float64)
         self.box = tuple(float(b) for b in box)
         self.r_cut, self.r_switch, self.coulomb_k = float(r_cut), float(r_switch), float(coulomb_k)
         self.flags = int(flags)
+        self.ewald_alpha = float(ewald_alpha)
         self.c = _Params((C.c_double * 3)(*self.box), self.r_cut, self.r_switch, self.coulomb_k,
                          int(self.sigma.shape[0]),
                          self.sigma.ctypes.data_as(C.POINTER(C.c_double)),
-                         self.epsilon.ctypes.data_as(C.POINTER(C.c_double)), self.flags)
+                         self.epsilon.ctypes.data_as(C.POINTER(C.c_double)), self.flags,
+                         self.ewald_alpha)
 
     @classmethod
     def from_dict(cls, d, flags=None):
         f = d.get("flags", 0) if flags is None else flags
-        return cls(d["box"], d["r_cut"], d["r_switch"], d["coulomb_k"], d["sigma"], d["epsilon"], f)
+        return cls(d["box"], d["r_cut"], d["r_switch"], d["coulomb_k"], d["sigma"], d["epsilon"], f,
+                   d.get("ewald_alpha", 0.0))
 
     def with_flags(self, flags):
         return Params(self.box, self.r_cut, self.r_switch, self.coulomb_k, self.sigma,
-                      self.epsilon, flags)
+                      self.epsilon, flags, self.ewald_alpha)
 
     def ref(self):
         return C.byref(self.c)
@@ -335,6 +346,42 @@ def forces_batched_raw(systems, stream_ptr):
     rc = lib().md_forces_batched(arr, len(systems), C.c_void_p(stream_ptr))
     if rc != MD_OK:
         raise MDError(rc, "md_forces_batched")
+
+
+def ewald_workspace_bytes(params, n_atoms, kmax):
+    p = _as_params(params)
+    km = (C.c_int32 * 3)(*[int(k) for k in kmax])
+    return int(lib().md_ewald_workspace_bytes(p.ref(), int(n_atoms), km))
+
+
+def ewald_recip(params, pos, charges, kmax, *, force=None, energy=None, accumulate=False,
+                workspace=None, stream=None):
+    """md_ewald_recip_f32: reciprocal-space forces (written, or added into `force` with
+    accumulate=True) and the reciprocal + self + background energy, for float32 device
+    tensors pos [n,3] and charges [n]. Returns (force, energy, workspace)."""
+    import torch
+    p = _as_params(params)
+    n = int(pos.shape[0])
+    _check_tensor(pos, torch.float32, (n, 3), "pos")
+    _check_tensor(charges, torch.float32, (n,), "charges")
+    if force is None:
+        force = torch.zeros((n, 3), dtype=torch.float32, device=pos.device)
+    if energy is None:
+        energy = torch.empty(1, dtype=torch.float64, device=pos.device)
+    km = (C.c_int32 * 3)(*[int(k) for k in kmax])
+    nb = lib().md_ewald_workspace_bytes(p.ref(), n, km)
+    if nb == 0:
+        raise MDError(-1, "md_ewald_workspace_bytes")
+    if workspace is None or workspace.numel() < nb:
+        workspace = torch.empty(nb, dtype=torch.uint8, device=pos.device)
+    rc = lib().md_ewald_recip_f32(p.ref(), n, C.c_void_p(pos.data_ptr()),
+                                  C.c_void_p(charges.data_ptr()), km, C.c_void_p(force.data_ptr()),
+                                  C.c_void_p(energy.data_ptr()), int(bool(accumulate)),
+                                  C.c_void_p(workspace.data_ptr()), int(workspace.numel()),
+                                  _stream_ptr(stream))
+    if rc != MD_OK:
+        raise MDError(rc, "md_ewald_recip_f32")
+    return force, energy, workspace
 
 
 def copy_segments(segments, stream_ptr):

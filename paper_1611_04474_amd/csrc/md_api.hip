@@ -57,13 +57,20 @@ static md_status check_params(const md_params* p) {
   if (!(p->r_switch > 0) || p->r_switch > p->r_cut) return MD_ERR_INVALID_ARG;
   if (!isfinite(p->coulomb_k)) return MD_ERR_INVALID_ARG;
   const uint32_t known = MD_ACCUM_F32_ATOMIC | MD_COULOMB_TRUNCATED | MD_DIAG_COUNTERS |
-                         MD_PAIR_PREDICATED | MD_PAIR_FULL_SHELL | MD_PAIR_DRAIN_MASK;
+                         MD_PAIR_PREDICATED | MD_PAIR_FULL_SHELL | MD_PAIR_DRAIN_MASK |
+                         MD_COULOMB_EWALD;
   if (p->flags & ~known) return MD_ERR_INVALID_ARG;
+  // Ewald's real-space term: a finite positive splitting parameter, on the compacted kernel
+  // (float32 sums only there), not together with the truncated form
+  if (p->flags & MD_COULOMB_EWALD) {
+    if (!(p->ewald_alpha > 0) || !isfinite(p->ewald_alpha)) return MD_ERR_INVALID_ARG;
+    if (p->flags & (MD_COULOMB_TRUNCATED | MD_PAIR_PREDICATED)) return MD_ERR_INVALID_ARG;
+  }
   // another drain depth only for the kernel that has it: the compacted half shell with the
   // whole energy switched (the float64 path is checked in check_call)
   if ((p->flags & MD_PAIR_DRAIN_MASK) &&
       ((p->flags & (MD_ACCUM_F32_ATOMIC | MD_COULOMB_TRUNCATED | MD_PAIR_PREDICATED |
-                    MD_PAIR_FULL_SHELL)) ||
+                    MD_PAIR_FULL_SHELL | MD_COULOMB_EWALD)) ||
        !(p->r_switch < p->r_cut)))
     return MD_ERR_INVALID_ARG;
   for (int d = 0; d < 3; ++d)
@@ -193,6 +200,7 @@ SysArgs<Real> make_args(const md_params* p, const Plan& pl, int64_t n, const Rea
   a.rs2 = (Real)rs2;
   a.inv_sw = p->r_switch < p->r_cut ? (Real)(1.0 / (rc2 - rs2)) : Real(0);
   a.coulomb_k = (Real)p->coulomb_k;
+  a.ewald_alpha = (p->flags & MD_COULOMB_EWALD) ? (Real)p->ewald_alpha : Real(0);
   a.flags = p->flags;
   a.compact = uses_compact(p, (int)sizeof(Real)) ? 1 : 0;
   a.half_shell =
@@ -214,6 +222,9 @@ static md_status check_call(const md_params* p, int64_t n, const Real* pos, cons
   md_status s = make_plan(p, n, (int)sizeof(Real), pl);
   if (s != MD_OK) return s;
   if (sizeof(Real) == 8 && (p->flags & MD_PAIR_DRAIN_MASK)) return MD_ERR_INVALID_ARG;
+  // float64 with float32 atomics takes the predicated kernel, which has no Ewald form
+  if (sizeof(Real) == 8 && (p->flags & MD_COULOMB_EWALD) && (p->flags & MD_ACCUM_F32_ATOMIC))
+    return MD_ERR_INVALID_ARG;
   if (!energy || ((uintptr_t)energy & 7)) return MD_ERR_INVALID_ARG;
   if (n > 0) {
     if (!pos || !type || !q || !force) return MD_ERR_INVALID_ARG;
@@ -228,7 +239,8 @@ static md_status check_call(const md_params* p, int64_t n, const Real* pos, cons
 // Systems that may share one batched launch: same flags and the same type table.
 static bool same_kind(const md_params* x, const md_params* y) {
   if (x->flags != y->flags || x->n_types != y->n_types || x->r_cut != y->r_cut ||
-      x->r_switch != y->r_switch || x->coulomb_k != y->coulomb_k)
+      x->r_switch != y->r_switch || x->coulomb_k != y->coulomb_k ||
+      ((x->flags & MD_COULOMB_EWALD) && x->ewald_alpha != y->ewald_alpha))
     return false;
   for (int t = 0; t < x->n_types; ++t)
     if (x->sigma[t] != y->sigma[t] || x->epsilon[t] != y->epsilon[t]) return false;

@@ -118,6 +118,7 @@ struct SysArgs {
   Real inv_w[3];               // n_d / L_d
   Real rc2, rs2, inv_sw;       // inv_sw = 1/(rc2 - rs2), 0 when switching is off
   Real coulomb_k;
+  Real ewald_alpha;            // 1/A, with MD_COULOMB_EWALD (0 otherwise)
   uint32_t flags;
   int compact;                 // 1: per-atom sums come from the compacted pair kernel (acc64,
                                //    or, float32 only, facc with MD_ACCUM_F32_ATOMIC)

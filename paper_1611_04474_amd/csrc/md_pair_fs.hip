@@ -258,14 +258,23 @@ __device__ inline void global_add(long long* p, long long v) {
                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Forms of the Coulomb term (kCoul):
+//   kCoulSwitched  the whole pair energy (LJ and Coulomb) is switched;
+//   kCoulPlain     only the LJ energy is switched; Coulomb is Eq. 2 up to the cutoff;
+//   kCoulEwald     only the LJ energy is switched; Coulomb is the real-space term of an
+//                  Ewald sum, k q_i q_j erfc(alpha r) / r, the rest of it being summed in
+//                  reciprocal space beyond the short-range kernel.
+constexpr int kCoulSwitched = 0, kCoulPlain = 1, kCoulEwald = 2;
+
 // Pair force factor f (F_i = f r_ij) and pair energy e at squared distance u.
 // c12 = 4 eps s^12, c6 = 4 eps s^6 (Eq. 1: A = 12 c12, B = 6 c6); qq = k q_i q_j (Eq. 2).
 // The switch t = clamp((u - rs^2)/(rc^2 - rs^2), 0, 1), S = (1-t)^2 (1+2t), and
-// g = 12 t (1-t) / (rc^2 - rs^2) = -2 dS/du. With kSwitchCoulomb the whole energy is
-// switched, so at t = 1 both f and e are exactly zero.
-template <bool kSwitchCoulomb, typename Real>
+// g = 12 t (1-t) / (rc^2 - rs^2) = -2 dS/du. With the whole energy switched, at t = 1 both
+// f and e are exactly zero. Ewald: e_C = qq erfc(a r)/r and -(1/r) de_C/dr =
+// qq (erfc(a r)/r + (2a/sqrt(pi)) exp(-a^2 u)) / u, with ew = (a, 2a/sqrt(pi)).
+template <int kCoul, typename Real>
 __device__ inline Real pair_f(Real u, Real c12, Real c6, Real qq, Real rs2, Real inv_sw,
-                              Real sw12, Real& e) {
+                              Real sw12, Real& e, V2<Real> ew = {}) {
   Real rinv, t;
   if constexpr (sizeof(Real) == 4) {
     rinv = __builtin_amdgcn_rsqf(u);
@@ -283,10 +292,24 @@ __device__ inline Real pair_f(Real u, Real c12, Real c6, Real qq, Real rs2, Real
   const Real t2 = t * t;
   const Real S = mad(t2, mad(Real(2), t, Real(-3)), Real(1));   // (1-t)^2 (1+2t)
   const Real g = (t - t2) * sw12;
-  if (kSwitchCoulomb) {
+  if (kCoul == kCoulSwitched) {
     const Real et = elj + ec;
     e = S * et;
     return mad(g, et, S * mad(Real(6), x6, ec) * r2);
+  }
+  if (kCoul == kCoulEwald) {
+    const Real ar = ew.x * (u * rinv);
+    Real sc, ex;
+    if constexpr (sizeof(Real) == 4) {
+      sc = erfcf(ar);
+      ex = expf(-ar * ar);
+    } else {
+      sc = erfc(ar);
+      ex = exp(-ar * ar);
+    }
+    const Real es = ec * sc;                          // qq erfc(a r) / r
+    e = mad(S, elj, es);
+    return mad(g, elj, mad(Real(6) * S, x6, mad(qq * ew.y, ex, es)) * r2);
   }
   e = mad(S, elj, ec);
   return mad(g, elj, mad(Real(6) * S, x6, ec) * r2);
@@ -330,7 +353,7 @@ __device__ inline void lds_store_u16_lanes4(uint32_t a0, uint32_t a1, uint32_t a
 // and e, and pairs beyond the cutoff need no test (t clamps to 1).
 // kDiag: count filter passes, cutoff passes and filtered slots (MD_DIAG_COUNTERS).
 // kHalf: the half shell (64-bit fixed-point sums only). kDrain: force batches per drain.
-template <typename Real, bool kHalf, bool kSwitchCoulomb, bool kClamp, bool kDiag, int kDrain>
+template <typename Real, bool kHalf, int kCoul, bool kClamp, bool kDiag, int kDrain>
 __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<Real>& a, int cap,
                                                               int64_t cellA) {
   extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
@@ -362,6 +385,7 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<Real
   const bool f32 = kF32 && !kHalf && (a.flags & MD_ACCUM_F32_ATOMIC) != 0;
   const Real rc2 = a.rc2, rs2 = a.rs2, inv_sw = a.inv_sw, sw12 = Real(12) * a.inv_sw;
   const Real kc = a.coulomb_k;
+  const R2 ew = mk2<Real>(a.ewald_alpha, a.ewald_alpha * Real(1.1283791670955126));   // 2/sqrt(pi)
   const Real L0 = a.L[0], L1 = a.L[1], L2 = a.L[2];
   const int ac0 = (int)(cellA % a.nx), ac1 = (int)((cellA / a.nx) % a.ny),
             ac2 = (int)(cellA / ((int64_t)a.nx * a.ny));
@@ -668,12 +692,12 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<Real
         Real e, f;
         if (kClamp) {
           u = (in && (kHalf || u > Real(0))) ? u : Real(kBigU);
-          f = pair_f<kSwitchCoulomb>(u, lj.x, lj.y, kq[k] * qj, rs2, inv_sw, sw12, e);
+          f = pair_f<kCoul>(u, lj.x, lj.y, kq[k] * qj, rs2, inv_sw, sw12, e, ew);
           if (diag) cnt[k] += __builtin_popcountll(__builtin_amdgcn_ballot_w64(u < rc2));
           if (kHalf && diag && u < rc2) atomicAdd(&sJn[jl], 1);
         } else {
           const bool lv = in && u < rc2 && u > Real(0);
-          f = pair_f<kSwitchCoulomb>(u, lj.x, lj.y, kq[k] * qj, rs2, inv_sw, sw12, e);
+          f = pair_f<kCoul>(u, lj.x, lj.y, kq[k] * qj, rs2, inv_sw, sw12, e, ew);
           f = lv ? f : Real(0);
           e = lv ? e : Real(0);
           if (diag) cnt[k] += __builtin_popcountll(__builtin_amdgcn_ballot_w64(lv));
@@ -1077,19 +1101,19 @@ __device__ inline void record_cost(const SysArgs<Real>& a, int64_t cell, uint64_
   }
 }
 
-template <typename Real, bool kHalf, bool kSwitchCoulomb, bool kClamp, bool kDiag, int kDrain>
+template <typename Real, bool kHalf, int kCoul, bool kClamp, bool kDiag, int kDrain>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNW / 4, kNW / 4)))
 void k_pair_fs(SysArgs<Real> a, int cap) {
   // home cells in the order the binning chose (longest first)
   const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
   const uint64_t c0 = __builtin_amdgcn_s_memtime();
   const int64_t cell = a.order[blockIdx.x];
-  pair_fs<Real, kHalf, kSwitchCoulomb, kClamp, kDiag, kDrain>(a, cap, cell);
+  pair_fs<Real, kHalf, kCoul, kClamp, kDiag, kDrain>(a, cap, cell);
   record_cost(a, cell, t0, c0, blockIdx.x == 0);
 }
 
 // One launch for a batch: block b is cell order[b - cum[s]] of system s.
-template <bool kHalf, bool kSwitchCoulomb, bool kClamp, bool kDiag, int kDrain>
+template <bool kHalf, int kCoul, bool kClamp, bool kDiag, int kDrain>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNW / 4, kNW / 4)))
 void k_pair_fs_batch(Batch<float> b, int cap) {
   const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
@@ -1097,14 +1121,14 @@ void k_pair_fs_batch(Batch<float> b, int cap) {
   int64_t unit;
   const int s = b.pick(blockIdx.x, unit);
   const int64_t cell = b.sys[s].order[unit];
-  pair_fs<float, kHalf, kSwitchCoulomb, kClamp, kDiag, kDrain>(b.sys[s], cap, cell);
+  pair_fs<float, kHalf, kCoul, kClamp, kDiag, kDrain>(b.sys[s], cap, cell);
   record_cost(b.sys[s], cell, t0, c0, unit == 0);
 }
 
-template <bool H, bool S, bool C, bool D, int R>
+template <bool H, int S, bool C, bool D, int R>
 struct launch_tag {
-  static constexpr bool half = H, sw = S, clamp = C, diag = D;
-  static constexpr int drain = R;
+  static constexpr bool half = H, clamp = C, diag = D;
+  static constexpr int coul = S, drain = R;
 };
 
 // Neighbour atoms staged in LDS per pass (a multiple of 64).
@@ -1127,7 +1151,8 @@ hipError_t dispatch(const SysArgs<Real>& a, const Args& args, int n_types, int64
   const bool half = a.half_shell != 0;
   const bool diag = (a.flags & MD_DIAG_COUNTERS) != 0;
   const bool trunc = (a.flags & MD_COULOMB_TRUNCATED) != 0;
-  const bool clamp = !trunc && a.inv_sw > Real(0);
+  const bool ewald = (a.flags & MD_COULOMB_EWALD) != 0;
+  const bool clamp = !trunc && !ewald && a.inv_sw > Real(0);
   const int drain = md_pair_drain(a.flags);
   if (drain != kDrainDefault && !(half && clamp && sizeof(Real) == 4)) return hipErrorInvalidValue;
   const int cap = fs_cap<Real>(n_types, half, diag, drain);
@@ -1139,15 +1164,17 @@ hipError_t dispatch(const SysArgs<Real>& a, const Args& args, int n_types, int64
     constexpr bool H = decltype(h)::value, D = decltype(d)::value;
     if (clamp) {
       if constexpr (H && sizeof(Real) == 4) {
-        if (drain == 1) return launch(launch_tag<H, true, true, D, 1>(), grid, block, shmem, stream, args, cap);
-        if (drain == 3) return launch(launch_tag<H, true, true, D, 3>(), grid, block, shmem, stream, args, cap);
-        if (drain == 4) return launch(launch_tag<H, true, true, D, 4>(), grid, block, shmem, stream, args, cap);
+        if (drain == 1) return launch(launch_tag<H, kCoulSwitched, true, D, 1>(), grid, block, shmem, stream, args, cap);
+        if (drain == 3) return launch(launch_tag<H, kCoulSwitched, true, D, 3>(), grid, block, shmem, stream, args, cap);
+        if (drain == 4) return launch(launch_tag<H, kCoulSwitched, true, D, 4>(), grid, block, shmem, stream, args, cap);
       }
-      launch(launch_tag<H, true, true, D, kDrainDefault>(), grid, block, shmem, stream, args, cap);
+      launch(launch_tag<H, kCoulSwitched, true, D, kDrainDefault>(), grid, block, shmem, stream, args, cap);
+    } else if (ewald) {
+      launch(launch_tag<H, kCoulEwald, false, D, kDrainDefault>(), grid, block, shmem, stream, args, cap);
     } else if (!trunc) {
-      launch(launch_tag<H, true, false, D, kDrainDefault>(), grid, block, shmem, stream, args, cap);
+      launch(launch_tag<H, kCoulSwitched, false, D, kDrainDefault>(), grid, block, shmem, stream, args, cap);
     } else {
-      launch(launch_tag<H, false, false, D, kDrainDefault>(), grid, block, shmem, stream, args, cap);
+      launch(launch_tag<H, kCoulPlain, false, D, kDrainDefault>(), grid, block, shmem, stream, args, cap);
     }
   };
   using T = std::true_type;
@@ -1170,7 +1197,7 @@ hipError_t launch_pair_fs(const SysArgs<Real>& a, hipStream_t stream) {
                      int cap) {
                     using Tg = decltype(tag);
                     hipLaunchKernelGGL(
-                        (k_pair_fs<Real, Tg::half, Tg::sw, Tg::clamp, Tg::diag, Tg::drain>), g, b,
+                        (k_pair_fs<Real, Tg::half, Tg::coul, Tg::clamp, Tg::diag, Tg::drain>), g, b,
                         sh, st, x, cap);
                   });
 }
@@ -1191,7 +1218,7 @@ hipError_t launch_pair_fs_batch(const Batch<float>& b0, hipStream_t stream) {
                      int cap) {
                     using Tg = decltype(tag);
                     hipLaunchKernelGGL(
-                        (k_pair_fs_batch<Tg::half, Tg::sw, Tg::clamp, Tg::diag, Tg::drain>), g, bl,
+                        (k_pair_fs_batch<Tg::half, Tg::coul, Tg::clamp, Tg::diag, Tg::drain>), g, bl,
                         sh, st, x, cap);
                   });
 }

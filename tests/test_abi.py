@@ -181,3 +181,31 @@ def test_noalloc_rejects_before_any_device_call():
     assert f(p.ref(), 10, ptr, ptr, ptr, ptr, ptr, C.c_void_p(4098), None) == -1    # status alignment
     bad = api.Params.from_dict(dict(base, box=(20.0, 30.0, 30.0)))
     assert f(bad.ref(), 10, ptr, ptr, ptr, ptr, ptr, None, None) == -2
+
+
+def test_ewald_arguments():
+    """Ewald: real-space flag needs a positive splitting parameter and the compacted kernel;
+    the reciprocal call checks alpha, kmax and pointers before anything is enqueued."""
+    base = W.small_system().params()
+    need = api.workspace_bytes(base, 10)
+    ew = dict(base, flags=api.COULOMB_EWALD, ewald_alpha=0.3)
+    assert api.workspace_bytes(ew, 10) > 0
+    assert api.workspace_bytes(dict(ew, ewald_alpha=0.0), 10) == 0
+    assert api.workspace_bytes(dict(ew, flags=api.COULOMB_EWALD | api.PAIR_PREDICATED), 10) == 0
+    assert api.workspace_bytes(dict(ew, flags=api.COULOMB_EWALD | api.COULOMB_TRUNCATED), 10) == 0
+    assert _call_f32(dict(ew, flags=api.COULOMB_EWALD | api.PAIR_DRAIN(3)), ws_bytes=need) == -1
+    assert api.ewald_workspace_bytes(ew, 100, (5, 6, 7)) > 0
+    assert api.ewald_workspace_bytes(dict(ew, ewald_alpha=-1.0), 100, (5, 6, 7)) == 0
+    assert api.ewald_workspace_bytes(ew, 100, (0, 0, 0)) == 0
+    assert api.ewald_workspace_bytes(ew, 100, (256, 1, 1)) == 0
+    L = api.lib()
+    p = api.Params.from_dict(ew)
+    km = (C.c_int32 * 3)(5, 5, 5)
+    ptr = C.c_void_p(4096)
+    nb = api.ewald_workspace_bytes(ew, 10, (5, 5, 5))
+    assert L.md_ewald_recip_f32(p.ref(), 10, ptr, ptr, km, ptr, ptr, 0, C.c_void_p(256), nb - 1,
+                                None) == -3
+    assert L.md_ewald_recip_f32(p.ref(), 10, ptr, ptr, km, None, ptr, 0, C.c_void_p(256), nb,
+                                None) == -1
+    assert L.md_ewald_recip_f32(p.ref(), 10, ptr, ptr, km, ptr, C.c_void_p(4100), 0,
+                                C.c_void_p(256), nb, None) == -1
