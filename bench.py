@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run a plain copy kernel over this many MiB (read and write) before "
                          "the benchmark, as the reference point of HBM byte counters")
+    ap.add_argument("--ewald-steps", type=int, default=5,
+                    help="evaluations of the Ewald form at 92k atoms (0 skips it)")
     ap.add_argument("--ablation-steps", type=int, default=10,
                     help="pair-stage timings per data flow in the compacted vs predicated "
                          "comparison (0 disables it)")
@@ -103,7 +105,7 @@ def pair_traffic(args):
 
 
 def pct(v, q):
-    return float(np.percentile(np.asarray(v), q))
+    return float(np.percentile(np.asarray(v), q)) if len(v) else None
 
 
 def main():
@@ -257,6 +259,8 @@ def main():
         out["md_vv_92k"] = md_loop(args.md_steps, dev)
     if args.ablation_steps > 0:
         out["ablation_data_flow"] = ablation(args.ablation_steps, dev)
+    if args.ewald_steps > 0:
+        out["ewald_92k"] = ewald(args.ewald_steps, dev)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds)
         out["config"]["pairs_oracle_fp64"] = out["cpu_baseline"].pop("n_pairs")
@@ -305,6 +309,56 @@ def serving(n_req, dev, max_batch, inflight):
         both(f"poisson_{int(rate)}hz", arr - arr[0], 64 << 30)
     gc.enable()
     return out
+
+
+EWALD_ALPHA = 0.3              # 1/A: erfc(0.3 x 12) = 3.6e-7 at the cutoff
+EWALD_TOL = 1e-6               # first omitted reciprocal term exp(-pi^2 h^2 / alpha^2)
+FLOP_PER_ATOM_WAVEVECTOR = 24  # structure factor 8 (complex multiply-add), forces 16 (two)
+
+
+def ewald(steps, dev):
+    """Coulomb beyond the cutoff by Ewald summation at 92,224 atoms: the short-range call
+    with the erfc-screened real-space term, and the reciprocal-space sum. Reports both times
+    and the reciprocal kernels' algorithmic rate (24 FLOP per atom and half-space wave
+    vector) against the float32 peak."""
+    import math
+    import torch
+    from paper_1611_04474_amd import api
+    from paper_1611_04474_amd import workloads as W
+    s = W.apoa1_system()
+    p = dict(s.params(), flags=api.COULOMB_EWALD, ewald_alpha=EWALD_ALPHA)
+    P = api.Params.from_dict(p)
+    h = EWALD_ALPHA * math.sqrt(-math.log(EWALD_TOL)) / math.pi
+    kmax = [int(math.ceil(h * float(L))) for L in s.box]
+    pos = torch.as_tensor(s.pos).to(dev)
+    typ = torch.as_tensor(s.types).to(dev)
+    q = torch.as_tensor(s.charges).to(dev)
+    force = torch.empty((s.n, 3), dtype=torch.float32, device=dev)
+    e_short = torch.empty(1, dtype=torch.float64, device=dev)
+    e_rec = torch.empty(1, dtype=torch.float64, device=dev)
+    ws = api.alloc_workspace(P, s.n, dev)
+    _, _, ews = api.ewald_recip(P, pos, q, kmax, force=force, energy=e_rec)
+    stream = torch.cuda.current_stream()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps + 2)]
+    for k in range(steps + 2):
+        evs[k][0].record(stream)
+        api.forces(P, pos, typ, q, force=force, energy=e_short, workspace=ws)
+        evs[k][1].record(stream)
+        api.ewald_recip(P, pos, q, kmax, force=force, energy=e_rec, accumulate=True, workspace=ews)
+        evs[k][2].record(stream)
+    torch.cuda.synchronize()
+    short_ms = [e[0].elapsed_time(e[1]) for e in evs[2:]]
+    rec_ms = [e[1].elapsed_time(e[2]) for e in evs[2:]]
+    n_half = ((2 * kmax[0] + 1) * (2 * kmax[1] + 1) * (2 * kmax[2] + 1) - 1) // 2
+    flop = FLOP_PER_ATOM_WAVEVECTOR * s.n * n_half
+    rec_s = statistics.median(rec_ms) * 1e-3
+    return {"alpha_per_A": EWALD_ALPHA, "kmax": kmax, "half_space_wavevectors": n_half,
+            "short_range_ms_median": statistics.median(short_ms),
+            "reciprocal_ms_median": statistics.median(rec_ms),
+            "energy_short": float(e_short.item()), "energy_reciprocal_self_background": float(e_rec.item()),
+            "reciprocal_flop": flop, "reciprocal_TFLOPs": flop / rec_s / 1e12,
+            "reciprocal_frac_of_fp32_peak": flop / rec_s / 1e12 / PEAK_FP32_TFLOPS,
+            "status": api.read_status(ws) | api.read_status(ews)}
 
 
 def md_loop(steps, dev, dt=0.5):

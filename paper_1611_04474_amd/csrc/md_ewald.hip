@@ -35,7 +35,7 @@ namespace {
 
 constexpr int kEwTile = 64;       // atoms per LDS tile of the structure-factor kernel
 constexpr int kEwRows = 16;       // rows per structure-factor workgroup (one per wave)
-constexpr int kEwZ = 48;          // mz values held in registers by the force kernel
+constexpr int kEwZ = 32;          // mz values held in registers by the force kernel
 constexpr int kEwForceRows = 16;  // rows of G staged in LDS at a time by the force kernel
 constexpr int kEwMaxK = 255;      // largest kmax per axis
 

@@ -33,7 +33,8 @@
 //              wave that owns it, so no atomics are needed;
 //   half (kHalf = true)  -- every pair is evaluated once (Newton's third law, F_j = -F_i):
 //              the home cell with j > i and the 13 images ahead of it. The force on the
-//              neighbour atom, rounded to a multiple of 2^-24, is added in 64-bit fixed
+//              neighbour atom, -f dx rounded once to a multiple of 2^-24 (through one float64
+//              fused multiply-add), is added in 64-bit fixed
 //              point into an LDS accumulator per staged atom (integer atomics, so the sum
 //              does not depend on the order of the adds), and the accumulators go to the
 //              per-atom sums with 64-bit global integer atomics when the workgroup is
@@ -216,12 +217,13 @@ __device__ inline long long to_fixed(float v, uint32_t& st) {
   return v < 0.f ? -(long long)m : (long long)m;
 }
 
-// round(x) (to nearest even) as a 64-bit integer, for |x| < 2^51: the add places it in
-// the low mantissa bits of 1.5 * 2^52, whose bit pattern then differs from that of
-// 1.5 * 2^52 by exactly that integer.
-__device__ inline long long round_to_i64(float x) {
-  const double t = (double)x + 6755399441055744.0;
-  return __builtin_bit_cast(long long, t) - 0x4338000000000000ll;
+// round(a b 2^24) (to nearest even) as a 64-bit integer, for float32 a, b with
+// |a b| < 2^27: the product is exact in float64, and the fused add of 1.5 * 2^28 rounds it
+// once to a multiple of 2^-24 (the ulp of values in [2^28, 2^29)), so the bit pattern of
+// the sum differs from that of 1.5 * 2^28 by exactly the rounded product in units of 2^-24.
+__device__ inline long long round_prod_2m24(double a, float b) {
+  const double t = fma(a, (double)b, 402653184.0);
+  return __builtin_bit_cast(long long, t) - 0x41b8000000000000ll;
 }
 
 // Two-word fixed point of the float64 path: v = hi 2^-20 + lo 2^-72 with hi = round(v 2^20)
@@ -275,6 +277,7 @@ constexpr int kCoulSwitched = 0, kCoulPlain = 1, kCoulEwald = 2;
 template <int kCoul, typename Real>
 __device__ inline Real pair_f(Real u, Real c12, Real c6, Real qq, Real rs2, Real inv_sw,
                               Real sw12, Real& e, V2<Real> ew = {}) {
+  // u - rs2 is exact near the cutoff (Sterbenz), so t keeps its accuracy where S is small
   Real rinv, t;
   if constexpr (sizeof(Real) == 4) {
     rinv = __builtin_amdgcn_rsqf(u);
@@ -638,8 +641,9 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<Real
         cnt[k] = 0;
       }
       Real e_lane = 0;
-      Real jmax = 0;   // largest |F_j| component handed to the neighbour side (float32: in
-                       // units of 2^-24, as given to round_to_i64)
+      // the largest |F_j| component |f dx| handed to the neighbour side (float32: as
+      // |f| times the largest |dx|)
+      Real jmax = 0;
 
       // x-window of every segment: [lo, hi) of segment s with x in [min x_i - w, max x_i + w)
       // in the segment's frame (two lower_bound searches, in lanes s and s + 32 when the
@@ -683,8 +687,8 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<Real
       // FIFO's fill level. The full shell's u > 0 drops the home atom itself; the half
       // shell never pairs an atom with itself (j > i in the home image). The half shell
       // adds -F to neighbour j's accumulator as well (zero for lanes that add nothing):
-      // float32 in units of 2^-24 kcal/mol/A (-f 2^24 dx is an exact scaling of the float32
-      // product, rounded once to an integer), float64 as a two-word fixed-point value.
+      // float32 in units of 2^-24 kcal/mol/A (-f dx, exact in float64, rounded once to a
+      // multiple of 2^-24), float64 as a two-word fixed-point value.
       auto pair_lane = [&](int k, int jl, const R4& pj, Real qj, const R2& lj,
                            bool in) __attribute__((always_inline)) {
         const Real dx = xs[k] - pj.x, dy = ys[k] - pj.y, dz = zs[k] - pj.z;
@@ -709,13 +713,13 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<Real
         e_lane += e;
         if (kHalf) {
           if constexpr (kF32) {
-            const float g24 = f * -16777216.f;
-            const float px = g24 * dx, py = g24 * dy, pz = g24 * dz;
-            jmax = fmaxf(jmax, fmaxf(fabsf(px), fmaxf(fabsf(py), fabsf(pz))));
+            const double nf = -(double)f;
+            const float m3 = fmaxf(fmaxf(fabsf(dx), fabsf(dy)), fabsf(dz));   // one v_max3
+            jmax = fmaxf(jmax, fabsf(f * m3));
             long long* d = sJ + 3 * jl;
-            lds_add(d, round_to_i64(px));
-            lds_add(d + 1, round_to_i64(py));
-            lds_add(d + 2, round_to_i64(pz));
+            lds_add(d, round_prod_2m24(nf, dx));
+            lds_add(d + 1, round_prod_2m24(nf, dy));
+            lds_add(d + 2, round_prod_2m24(nf, dz));
           } else {
             const double p3[3] = {-f * dx, -f * dy, -f * dz};
             long long* d = sJ + 6 * jl;
@@ -975,7 +979,7 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<Real
         const float v = e_lane * 16777216.0f;
         if (!(fabsf(v) < 4.6116860184273879e18f)) st |= MD_STATUS_FIXED_OVERFLOW;
         else e_fix += __float2ll_rn(v);
-        if (kHalf && !(jmax < 2251799813685248.f)) st |= MD_STATUS_FIXED_OVERFLOW;   // 2^51
+        if (kHalf && !(jmax < kNbrPartialMax)) st |= MD_STATUS_FIXED_OVERFLOW;
       } else {
         if (!(fabs(e_lane) < 1.0e9)) {
           st |= MD_STATUS_FIXED_OVERFLOW;
