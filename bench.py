@@ -543,6 +543,38 @@ def ablation(steps, dev):
     out["drain_depth_sweep_half_shell"] = sweep
     out["speedup_half_over_full_shell"] = (out["compacted_full_shell"]["pair_ms_median"] /
                                            out["compacted_half_shell"]["pair_ms_median"])
+    # workgroups per home cell: the 92,224-atom system (486 cells) and a 20,000-atom cube
+    # of 4^3 cells (a median serving request), whole evaluations
+    split = {}
+    for label, sysm in (("apoa1_92k_486_cells", s), ("cube_20k_64_cells",
+                                                    W.gen_system(20000, (58.5, 58.5, 58.5), 12))):
+        pos_s = torch.as_tensor(sysm.pos).to(dev)
+        typ_s = torch.as_tensor(sysm.types).to(dev)
+        q_s = torch.as_tensor(sysm.charges).to(dev)
+        f_s = torch.empty((sysm.n, 3), dtype=torch.float32, device=dev)
+        row = {}
+        for sv in (1, 2, 4):
+            P = api.Params.from_dict(sysm.params(), api.PAIR_SPLIT(sv))
+            ws = api.alloc_workspace(P, sysm.n, dev)
+            api.forces(P.with_flags(P.flags | api.DIAG_COUNTERS), pos_s, typ_s, q_s, force=f_s,
+                       energy=energy, workspace=ws)
+            pairs = api.read_diag(ws)[2]
+            evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps + 2)]
+            for k in range(steps + 2):
+                evs[k][0].record(stream)
+                api.forces_stages(P, pos_s, typ_s, q_s, f_s, energy, ws, api.STAGE_BIN)
+                evs[k][1].record(stream)
+                api.forces_stages(P, pos_s, typ_s, q_s, f_s, energy, ws, api.STAGE_PAIR)
+                evs[k][2].record(stream)
+                api.forces_stages(P, pos_s, typ_s, q_s, f_s, energy, ws, api.STAGE_FINALIZE)
+            torch.cuda.synchronize()
+            pair_ms = pct([e[1].elapsed_time(e[2]) for e in evs[2:]], 50)
+            row[str(sv)] = {"pair_ms_median": pair_ms, "pairs_per_s_pair_stage": pairs / (pair_ms * 1e-3)}
+        cells = int(np.prod(api.workspace_layout(sysm.params(), sysm.n)["dims"]))
+        sa = 256 // cells
+        row["automatic"] = 4 if sa >= 4 else 2 if sa >= 2 else 1
+        split[label] = row
+    out["workgroups_per_home_cell"] = split
     return out
 
 

@@ -57,7 +57,8 @@ typedef enum {
 
 /* md_params.flags */
 enum {
-  MD_ACCUM_FIXED64 = 0,         /* default: per-atom sums in 64-bit fixed point (2^-32 kcal/mol/A) */
+  MD_ACCUM_FIXED64 = 0,         /* default: per-atom sums in 64-bit fixed point (2^-28 kcal/mol/A
+                                   in float32; hi 2^-20 + lo 2^-72 in float64) */
   MD_ACCUM_F32_ATOMIC = 1 << 0, /* per-atom sums in float32: with float32 atomics (order-
                                    dependent) in the predicated kernels; on the compacted path
                                    by the full-shell kernel, which owns each atom in one wave,
@@ -90,6 +91,14 @@ enum {
  * r_switch == r_cut) accepts only 0 and returns MD_ERR_INVALID_ARG otherwise. */
 #define MD_PAIR_DRAIN_MASK (3u << 5)
 #define MD_PAIR_DRAIN(d) ((uint32_t)((d) == 1 ? 1 : (d) == 3 ? 2 : (d) == 4 ? 3 : 0) << 5)
+
+/* md_params.flags bits 8-9: workgroups of the compacted kernel per home cell, each taking
+ * every s-th group of the cell's home atoms (the work units of the loop over home atoms of
+ * Algorithm 1, spread over more compute units). 0 chooses automatically (4 on grids of at
+ * most 64 cells, 2 up to 128, else 1); MD_PAIR_SPLIT(s) forces s = 1, 2 or 4. Results are the
+ * same bits for every s. Not with MD_PAIR_PREDICATED (MD_ERR_INVALID_ARG). */
+#define MD_PAIR_SPLIT_MASK (3u << 8)
+#define MD_PAIR_SPLIT(s) ((uint32_t)((s) == 1 ? 1 : (s) == 2 ? 2 : (s) == 4 ? 3 : 0) << 8)
 
 /* Device status bits (sticky until the next force call on the workspace). */
 enum {
@@ -313,7 +322,10 @@ md_status md_read_clock(const void* d_ws, void* stream, double* ghz);
  *   perm:       int32 [n_atoms], original index of each sorted atom
  *   pair_count: int32 [n_atoms], partners inside the cutoff (MD_DIAG_COUNTERS),
  *               in the caller's atom order
- *   energy_partials: float64 [n_energy_partials], per-workgroup energy sums
+ *   energy_partials: per-workgroup energy sums, n_energy_partials of them: after the
+ *               predicated kernel float64; after the compacted kernel exact integers,
+ *               int64 in units of 2^-24 kcal/mol (float32) or two int64 words, hi 2^-20 +
+ *               lo 2^-72 kcal/mol (float64), times 1/2 for the full shell
  *   z_split:    int32 [n_cells], atoms of each cell in its lower z half; a cell's sorted
  *               atoms are ordered by (z half, x, original index) */
 typedef struct {

@@ -28,6 +28,14 @@ COULOMB_EWALD = 1 << 7
 PAIR_DRAIN_MASK = 3 << 5
 
 
+PAIR_SPLIT_MASK = 3 << 8
+
+
+def PAIR_SPLIT(s):
+    """Flag bits forcing s = 1, 2 or 4 workgroups per home cell (0: automatic)."""
+    return {1: 1 << 8, 2: 2 << 8, 4: 3 << 8}[int(s)]
+
+
 def PAIR_DRAIN(d):
     """Flag bits selecting d force batches per FIFO drain (d = 1..4; 2 is the default)."""
     return {2: 0, 1: 1 << 5, 3: 2 << 5, 4: 3 << 5}[int(d)]

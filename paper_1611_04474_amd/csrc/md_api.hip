@@ -58,7 +58,7 @@ static md_status check_params(const md_params* p) {
   if (!isfinite(p->coulomb_k)) return MD_ERR_INVALID_ARG;
   const uint32_t known = MD_ACCUM_F32_ATOMIC | MD_COULOMB_TRUNCATED | MD_DIAG_COUNTERS |
                          MD_PAIR_PREDICATED | MD_PAIR_FULL_SHELL | MD_PAIR_DRAIN_MASK |
-                         MD_COULOMB_EWALD;
+                         MD_COULOMB_EWALD | MD_PAIR_SPLIT_MASK;
   if (p->flags & ~known) return MD_ERR_INVALID_ARG;
   // Ewald's real-space term: a finite positive splitting parameter, on the compacted kernel
   // (float32 sums only there), not together with the truncated form
@@ -66,6 +66,8 @@ static md_status check_params(const md_params* p) {
     if (!(p->ewald_alpha > 0) || !isfinite(p->ewald_alpha)) return MD_ERR_INVALID_ARG;
     if (p->flags & (MD_COULOMB_TRUNCATED | MD_PAIR_PREDICATED)) return MD_ERR_INVALID_ARG;
   }
+  // a work split only for the compacted kernel
+  if ((p->flags & MD_PAIR_SPLIT_MASK) && (p->flags & MD_PAIR_PREDICATED)) return MD_ERR_INVALID_ARG;
   // another drain depth only for the kernel that has it: the compacted half shell with the
   // whole energy switched (the float64 path is checked in check_call)
   if ((p->flags & MD_PAIR_DRAIN_MASK) &&
@@ -205,6 +207,7 @@ SysArgs<Real> make_args(const md_params* p, const Plan& pl, int64_t n, const Rea
   a.compact = uses_compact(p, (int)sizeof(Real)) ? 1 : 0;
   a.half_shell =
       (a.compact && !(p->flags & (MD_ACCUM_F32_ATOMIC | MD_PAIR_FULL_SHELL))) ? 1 : 0;
+  a.fs_split = a.compact ? md_fs_split(p->flags, pl.n_cells) : 1;
   return a;
 }
 
@@ -297,7 +300,9 @@ md_status md_workspace_layout(const md_params* p, int64_t n_atoms, int double_pr
   out->pair_count = pl.off_paircount;
   out->energy_partials = pl.off_epart;
   out->n_energy_partials =
-      md::uses_compact(p, double_precision ? 8 : 4) ? pl.n_cells * md::kFsSplit : pl.n_tasks;
+      md::uses_compact(p, double_precision ? 8 : 4)
+          ? pl.n_cells * md::md_fs_split(p->flags, pl.n_cells)
+          : pl.n_tasks;
   out->z_split = pl.off_zsplit;
   out->total_bytes = pl.total;
   return MD_OK;

@@ -14,7 +14,6 @@ constexpr int kTasksPerCell = 14;    // predicated kernel: home cell + 13 forwar
 constexpr int kSlots = 27;           // partial-force slots per atom: 14 as home, 13 as neighbour
 constexpr int kTile = 256;           // atoms of one cell staged in LDS at a time
 constexpr int kPairThreads = 256;    // threads of one predicated pair workgroup (4 waves)
-constexpr int kFsSplit = 1;          // compacted-kernel workgroups per home cell
 constexpr int64_t kMaxCells = 1 << 24;
 constexpr int64_t kMaxAtoms = (int64_t)1 << 30;
 constexpr int kBinLdsCells = 32768;  // largest grid binned with a per-block LDS histogram
@@ -27,6 +26,19 @@ constexpr int kBinChunkUnit = 2048;  // atoms per block: a multiple of this (4 p
 __host__ __device__ inline int md_pair_drain(uint32_t flags) {
   const uint32_t v = (flags & MD_PAIR_DRAIN_MASK) >> 5;
   return v == 0 ? 2 : v == 1 ? 1 : v == 2 ? 3 : 4;
+}
+
+// Workgroups of the compacted pair kernel per home cell, each taking every split-th group
+// of the cell's home atoms: MD_PAIR_SPLIT(s) in md_params.flags, or (field 0) automatic:
+// grids of fewer than 128 (4) or 64 (2) cells take 2 or 4, so that the 256 compute units get
+// work; larger grids take 1 (a split repeats the staging and the neighbour-side flush, which
+// measured 25% slower at 486 cells).
+__host__ __device__ inline int md_fs_split(uint32_t flags, int64_t n_cells) {
+  const uint32_t v = (flags & MD_PAIR_SPLIT_MASK) >> 8;
+  if (v) return v == 1 ? 1 : v == 2 ? 2 : 4;
+  if (n_cells <= 0) return 1;
+  const int64_t s = 256 / n_cells;   // workgroups per compute unit's worth of cells
+  return s >= 4 ? 4 : s >= 2 ? 2 : 1;
 }
 
 struct WsHeader {
@@ -101,7 +113,7 @@ struct SysArgs {
   Real* lj;                    // [n_types^2][2] (c12, c6)
   int32_t* paircount;          // [2][n]: caller order (after finalize), sorted order (pass)
   long long* acc64;            // per-atom fixed-point sums of the compacted kernel: float32
-                               // [3][n] (2^-32 kcal/mol/A); float64 [2][3][n], the high
+                               // [3][n] (2^-28 kcal/mol/A); float64 [2][3][n], the high
                                // words (2^-20) then the low words (2^-72)
   int32_t* bhist;              // [bin_blocks][n_cells] per-block cell counts (offsets in place
                                // after k_bin_colscan, for grids of more than 1024 cells)
@@ -124,6 +136,7 @@ struct SysArgs {
                                //    or, float32 only, facc with MD_ACCUM_F32_ATOMIC)
   int half_shell;              // 1: the compacted kernel visits each pair once and adds
                                //    into acc64 with integer atomics (acc64 starts at zero)
+  int fs_split;                // compacted-kernel workgroups per home cell (md_fs_split)
 };
 
 // Up to kBatchMax systems evaluated by one launch of each kernel of the path. The

@@ -2,7 +2,7 @@
 //
 // k_finalize writes each sorted atom's force in the caller's atom order. After the
 // compacted kernel it converts the per-atom fixed-point sums to float: float32 from one
-// 64-bit word (2^-32 kcal/mol/A), float64 from two (hi 2^-20 + lo 2^-72). After the
+// 64-bit word (2^-28 kcal/mol/A), float64 from two (hi 2^-20 + lo 2^-72). After the
 // predicated kernel it adds the 27 partial forces of the atom (14 as a home atom, 13 as a
 // neighbour): in float32 converted to 64-bit fixed point (one unit = 2^-32 kcal/mol/A,
 // round to nearest even) and summed as integers, so the per-atom total does not depend on
@@ -50,7 +50,7 @@ __device__ inline void finalize(const SysArgs<Real>& a, int64_t blk) {
     if (a.flags & MD_ACCUM_F32_ATOMIC) {
       v = (Real)a.facc[(int64_t)c * a.n + s];
     } else if (a.compact && sizeof(Real) == 4) {
-      v = (Real)(__ll2float_rn(a.acc64[(int64_t)c * a.n + s]) * 2.3283064365386963e-10f);
+      v = (Real)(__ll2float_rn(a.acc64[(int64_t)c * a.n + s]) * 3.725290298461914e-09f);   // 2^-28
     } else if (a.compact) {
       // two-word sum: hi 2^-20 + lo 2^-72 (hi exact in float64, one rounding of lo, one of
       // the sum)
@@ -102,12 +102,52 @@ __device__ inline void energy(const double* epart, int64_t n_tasks, double* out,
 
 template <typename Real>
 __host__ __device__ inline int64_t energy_parts(const SysArgs<Real>& a) {
-  return a.n > 0 ? (a.compact ? a.n_cells * kFsSplit : a.n_tasks) : 0;
+  return a.n > 0 ? (a.compact ? a.n_cells * a.fs_split : a.n_tasks) : 0;
 }
 
 template <typename Real>
 __host__ __device__ inline int halve_diag(const SysArgs<Real>& a) {
   return (a.compact && !a.half_shell && (a.flags & MD_DIAG_COUNTERS) && a.n > 0) ? 1 : 0;
+}
+
+// Energy after the compacted kernel: its workgroups' exact integer sums (float32: one int64
+// in units of 2^-24 kcal/mol; float64: two words, hi 2^-20 + lo 2^-72, lo in [0, 2^52)),
+// added as integers in a fixed order, so the total is the same bits however the work was
+// split into workgroups; the full shell saw every pair twice (factor 1/2, exact).
+template <typename Real>
+__device__ inline void energy_fixed(const SysArgs<Real>& a, int64_t n_parts) {
+  if (halve_diag(a) && threadIdx.x < 5) a.hdr->diag[threadIdx.x] /= 2;
+  __shared__ long long s_hi[256], s_lo[256];
+  const long long* ep = reinterpret_cast<const long long*>(a.epart);
+  constexpr bool f64 = sizeof(Real) == 8;
+  long long hi = 0, lo = 0;
+  for (int64_t t = threadIdx.x; t < n_parts; t += 256) {
+    if (f64) {
+      hi += ep[2 * t];
+      lo += ep[2 * t + 1];
+      hi += lo >> 52;   // carry: lo stays in [0, 2^52)
+      lo &= (1ll << 52) - 1;
+    } else {
+      hi += ep[t];
+    }
+  }
+  s_hi[threadIdx.x] = hi;
+  s_lo[threadIdx.x] = lo;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      long long h = s_hi[threadIdx.x] + s_hi[threadIdx.x + off];
+      long long l = s_lo[threadIdx.x] + s_lo[threadIdx.x + off];
+      s_hi[threadIdx.x] = h + (l >> 52);
+      s_lo[threadIdx.x] = l & ((1ll << 52) - 1);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double f = a.half_shell ? 1.0 : 0.5;
+    *a.energy_out = f64 ? f * ((double)s_hi[0] * 9.5367431640625e-07 + (double)s_lo[0] * 2.117582368135751e-22)
+                        : f * ((double)s_hi[0] * 5.9604644775390625e-08);   // 2^-20, 2^-72; 2^-24
+  }
 }
 
 // Block 0 sums the energy partials, which the pair kernel has completed, and blocks
@@ -116,7 +156,10 @@ __host__ __device__ inline int halve_diag(const SysArgs<Real>& a) {
 template <typename Real>
 __device__ inline void finalize_or_energy(const SysArgs<Real>& a, int64_t blk) {
   if (blk == 0) {
-    energy(a.epart, energy_parts(a), a.energy_out, a.hdr, halve_diag(a));
+    if (a.compact)
+      energy_fixed(a, energy_parts(a));
+    else
+      energy(a.epart, energy_parts(a), a.energy_out, a.hdr, halve_diag(a));
     return;
   }
   finalize(a, blk - 1);

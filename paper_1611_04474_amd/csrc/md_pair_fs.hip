@@ -22,8 +22,8 @@
 //              u < rc^2, and the force summed on the home atom in registers.
 // Each home atom is owned by one wave and its sum runs in a fixed order: the 64 lane
 // partials are added in one fixed order (wave halves and rows exchanging partial sums,
-// then a butterfly within a row) and the total converted exactly to 64-bit fixed point
-// (2^-32 kcal/mol/A); lane energies are summed in 64-bit fixed point (2^-24 kcal/mol),
+// then a butterfly within a row) and the total converted to 64-bit fixed point
+// (2^-28 kcal/mol/A, one rounding); lane energies are summed in 64-bit fixed point (2^-24 kcal/mol),
 // so the energy does not depend on how groups of home atoms were spread over the waves
 // either.
 //
@@ -73,15 +73,16 @@ constexpr int kLdsBytes = 160 * 1024;
 constexpr float kMargin = 0.05f;    // A^2 added to rc^2 by the expanded-form prefilter
 constexpr float kWin = 1.0e-3f;     // A added to r_cut for the x-window
 constexpr float kBigU = 1.0e30f;    // squared distance given to lanes that must add nothing
-// Range of the per-atom 64-bit fixed-point sums (2^31 kcal/mol/A). In the half shell an
-// atom's sum gathers one neighbour-side partial from each of the 14 images that stage it
-// (its home image and the 13 workgroups that have its cell ahead), each below 2^27
-// (kNbrPartialMax), and one home-side partial per LDS slice of its home cell's neighbour
-// list, S of them, each below 2^28 / S: 14 * 2^27 + 2^28 = 2^31. In the full shell an
-// atom's S home-side partials are each below 2^31 / S.
+// Range of the per-atom 64-bit fixed-point sums of the float32 path: units of 2^-28
+// kcal/mol/A, magnitudes below 2^35. In the half shell an atom's sum gathers one
+// neighbour-side partial from each of the 14 images that stage it, in each of the n_split
+// workgroups of the staging cell (its home image and the 13 cells that have its cell
+// ahead), each below 2^27 (kNbrPartialMax, also the bound of one pair's term), and one
+// home-side partial per LDS slice of its home cell's neighbour list, S of them, sharing
+// what is left: (2^35 - 14 n_split 2^27) / S each. In the full shell an atom's S home-side
+// partials are each below 2^35 / S. Every partial is checked, so a sum can never wrap.
 constexpr float kNbrPartialMax = 134217728.f;      // 2^27
-constexpr float kHalfHomeBudget = 268435456.f;     // 2^28
-constexpr float kFullHomeBudget = 2147483648.f;    // 2^31
+constexpr float kAccRange = 34359738368.f;         // 2^35
 static_assert(kMaxTypes <= 64, "a type must fit the low 6 bits of a staged c_j");
 
 // Staged atom (x, y, z, c_j) and LJ (c12, c6) vector types of each precision.
@@ -202,18 +203,19 @@ __device__ inline float rowsum16(float v) {
   return v;
 }
 
-// float -> 64-bit fixed point, one unit = 2^-32, round to nearest even, exact.
+// float -> 64-bit fixed point, one unit = 2^-28, round to nearest even, exact but for
+// that one rounding.
 __device__ inline long long to_fixed(float v, uint32_t& st) {
   float a = fabsf(v);
-  if (!(a < 2147483648.0f)) {
+  if (!(a < kAccRange)) {
     st |= MD_STATUS_FIXED_OVERFLOW;
     return 0;
   }
   float hi = floorf(a);
   float fr = a - hi;                                // exact
-  float lo = rintf(fr * 4294967296.0f);             // exact scaling; < 2^32
+  float lo = rintf(fr * 268435456.0f);              // exact scaling; < 2^28
   unsigned long long m =
-      ((unsigned long long)(unsigned)hi << 32) + (unsigned long long)(unsigned)lo;
+      ((unsigned long long)hi << 28) + (unsigned long long)(unsigned)lo;
   return v < 0.f ? -(long long)m : (long long)m;
 }
 
@@ -358,7 +360,7 @@ __device__ inline void lds_store_u16_lanes4(uint32_t a0, uint32_t a1, uint32_t a
 // kHalf: the half shell (64-bit fixed-point sums only). kDrain: force batches per drain.
 template <typename Real, bool kHalf, int kCoul, bool kClamp, bool kDiag, int kDrain>
 __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<Real>& a, int cap,
-                                                              int64_t cellA) {
+                                                              int64_t cellA, int part) {
   extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
   constexpr bool kF32 = sizeof(Real) == 4;
   constexpr int kImg = kHalf ? 14 : 27;   // neighbour images
@@ -497,8 +499,11 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<Real
   const int n_seg = H.n_seg;
   const int iters = H.iters;
   const int n_grp_q = (nA + kQ - 1) / kQ;
-  // largest home-side partial of one slice (see kHalfHomeBudget)
-  const float home_max = (kHalf ? kHalfHomeBudget : kFullHomeBudget) / (float)max(1, (total + cap - 1) / cap);
+  // this workgroup's share of the home cell: groups part, part + n_split, part + 2 n_split, ..
+  const int n_split = a.fs_split;
+  // largest home-side partial of one slice (see kAccRange)
+  const float home_max = (kHalf ? kAccRange - 14.f * (float)a.fs_split * kNbrPartialMax : kAccRange) /
+                         (float)max(1, (total + cap - 1) / cap);
   const Real R = vsqrt(rc2) + Real(kWin);
   // energy: float32 in units of 2^-24 kcal/mol; float64 two-word (e_fix, e_lo): exact,
   // order-independent sums
@@ -596,7 +601,7 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<Real
     while (true) {
       int o = 0;
       if (lane == 0) o = atomicAdd(&H.next, 1);
-      o = __builtin_amdgcn_readfirstlane(__shfl(o, 0));
+      o = part + n_split * __builtin_amdgcn_readfirstlane(__shfl(o, 0));
       if (o >= n_grp_q) break;
       const int ib = kQ * o;
       const int nv = min(kQ, nA - ib);   // home atoms present in this group
@@ -936,7 +941,7 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<Real
               *dst = P0 == 0 ? (float)r3[c] : *dst + (float)r3[c];
             } else {
               // one of the slice count's home-side partials of this atom: within its share
-              // of the fixed point's range (kHalfHomeBudget, kFullHomeBudget)
+              // of the fixed point's range (kAccRange)
               if (!(fabs(r3[c]) < (Real)home_max)) st |= MD_STATUS_FIXED_OVERFLOW;
               if constexpr (kF32) {
                 const long long qv = to_fixed(r3[c], st);
@@ -1003,14 +1008,14 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<Real
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             if constexpr (kF32) {
-              // units of 2^-24 to the sums' 2^-32, each partial below 2^27 kcal/mol/A (2^51
+              // units of 2^-24 to the sums' 2^-28, each partial below 2^27 kcal/mol/A (2^51
               // units, kNbrPartialMax)
               const long long v = sJ[3 * (dst - P0) + c];
               constexpr long long kLim = (long long)kNbrPartialMax << 24;
               if (v >= kLim || v < -kLim) st |= MD_STATUS_FIXED_OVERFLOW;
               else if (v != 0)
                 global_add(&a.acc64[(int64_t)c * a.n + src],
-                           (long long)((unsigned long long)v << 8));
+                           (long long)((unsigned long long)v << 4));
             } else {
               // two words, the low one reduced into [0, 2^52) so that the 14 neighbour-side
               // partials of an atom cannot wrap it; each partial below 2^27 kcal/mol/A
@@ -1045,8 +1050,9 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<Real
       if (tid < off) sE[tid] += sE[tid + off];
       __syncthreads();
     }
+    // the workgroup's exact integer sum; the finalize kernel adds them as integers too
     if (tid == 0)
-      a.epart[cellA] = (kHalf ? 1.0 : 0.5) * ((double)sE[0] * 5.9604644775390625e-08);   // 2^-24
+      reinterpret_cast<long long*>(a.epart)[part * a.n_cells + cellA] = sE[0];
   } else {
     const Fix2 v = normalize2(e_fix, e_lo);   // low words below 2^52: 1024 of them fit
     sE[tid] = v.hi;
@@ -1060,14 +1066,19 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<Real
       }
       __syncthreads();
     }
-    if (tid == 0) a.epart[cellA] = (kHalf ? 1.0 : 0.5) * from_fix2(sE[0], sE[1024]);
+    if (tid == 0) {
+      long long* ep = reinterpret_cast<long long*>(a.epart) + 2 * (part * a.n_cells + cellA);
+      const Fix2 t = normalize2(sE[0], sE[1024]);
+      ep[0] = t.hi;
+      ep[1] = t.lo;
+    }
   }
   if (st) atomicOr(&a.hdr->status, st);
   if (diag && lane == 0) {
     // candidates of Algorithm 1: every (home atom, other neighbour-list atom), counted
     // from both atoms in the full shell (halved after the kernel) and once in the half
     // shell; the neighbour slots this kernel actually filtered come separately
-    if (w == 0) {
+    if (w == 0 && part == 0) {
       const unsigned long long nA_ = (unsigned long long)nA;
       const unsigned long long cand =
           kHalf ? nA_ * (nA_ - 1) / 2 + nA_ * (unsigned long long)(total - nA)
@@ -1090,12 +1101,12 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<Real
 // to the header's two clock sums: their ratio is the clock the kernel ran at, weighted by
 // workgroup time.
 template <typename Real>
-__device__ inline void record_cost(const SysArgs<Real>& a, int64_t cell, uint64_t t0,
+__device__ inline void record_cost(const SysArgs<Real>& a, int64_t cell, int part, uint64_t t0,
                                    uint64_t c0, bool first) {
   if (threadIdx.x == 0) {   // after the workgroup's last barrier
     const uint64_t dc = __builtin_amdgcn_s_memtime() - c0;
     const uint64_t dt = __builtin_amdgcn_s_memrealtime() - t0;
-    a.cost[cell] = dt < 0xffffffffull ? (uint32_t)dt : 0xffffffffu;
+    if (part == 0) a.cost[cell] = dt < 0xffffffffull ? (uint32_t)dt : 0xffffffffu;
     atomicAdd(&a.hdr->clock[0], (unsigned long long)dc);
     atomicAdd(&a.hdr->clock[1], (unsigned long long)dt);
     if (first) {
@@ -1111,9 +1122,11 @@ void k_pair_fs(SysArgs<Real> a, int cap) {
   // home cells in the order the binning chose (longest first)
   const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
   const uint64_t c0 = __builtin_amdgcn_s_memtime();
-  const int64_t cell = a.order[blockIdx.x];
-  pair_fs<Real, kHalf, kCoul, kClamp, kDiag, kDrain>(a, cap, cell);
-  record_cost(a, cell, t0, c0, blockIdx.x == 0);
+  // workgroup b: cell order[b % n_cells], part b / n_cells (every cell's first part first)
+  const int64_t cell = a.order[blockIdx.x % a.n_cells];
+  const int part = (int)(blockIdx.x / a.n_cells);
+  pair_fs<Real, kHalf, kCoul, kClamp, kDiag, kDrain>(a, cap, cell, part);
+  record_cost(a, cell, part, t0, c0, blockIdx.x == 0);
 }
 
 // One launch for a batch: block b is cell order[b - cum[s]] of system s.
@@ -1124,9 +1137,10 @@ void k_pair_fs_batch(Batch<float> b, int cap) {
   const uint64_t c0 = __builtin_amdgcn_s_memtime();
   int64_t unit;
   const int s = b.pick(blockIdx.x, unit);
-  const int64_t cell = b.sys[s].order[unit];
-  pair_fs<float, kHalf, kCoul, kClamp, kDiag, kDrain>(b.sys[s], cap, cell);
-  record_cost(b.sys[s], cell, t0, c0, unit == 0);
+  const int64_t cell = b.sys[s].order[unit % b.sys[s].n_cells];
+  const int part = (int)(unit / b.sys[s].n_cells);
+  pair_fs<float, kHalf, kCoul, kClamp, kDiag, kDrain>(b.sys[s], cap, cell, part);
+  record_cost(b.sys[s], cell, part, t0, c0, unit == 0);
 }
 
 template <bool H, int S, bool C, bool D, int R>
@@ -1196,7 +1210,7 @@ hipError_t dispatch(const SysArgs<Real>& a, const Args& args, int n_types, int64
 template <typename Real>
 hipError_t launch_pair_fs(const SysArgs<Real>& a, hipStream_t stream) {
   if (a.n == 0) return hipSuccess;
-  return dispatch(a, a, a.n_types, a.n_cells, stream,
+  return dispatch(a, a, a.n_types, a.n_cells * a.fs_split, stream,
                   [](auto tag, dim3 g, dim3 b, size_t sh, hipStream_t st, const SysArgs<Real>& x,
                      int cap) {
                     using Tg = decltype(tag);
@@ -1214,7 +1228,7 @@ hipError_t launch_pair_fs_batch(const Batch<float>& b0, hipStream_t stream) {
   int nt = 1;
   b.cum[0] = 0;
   for (int s = 0; s < b.n; ++s) {
-    b.cum[s + 1] = b.cum[s] + b.sys[s].n_cells;
+    b.cum[s + 1] = b.cum[s] + b.sys[s].n_cells * b.sys[s].fs_split;
     nt = b.sys[s].n_types > nt ? b.sys[s].n_types : nt;
   }
   return dispatch(b.sys[0], b, nt, b.cum[b.n], stream,

@@ -712,46 +712,49 @@ def test_exact_cutoff_pairs(gpu, switch):
         assert api.read_diag(ws)[2] == 2
 
 
-def test_overflow_bound_follows_slices(gpu):
-    """The half shell bounds an atom's home-side partials by 2^28 / S kcal/mol/A, S being
-    the LDS slices of its home cell's neighbour list, so its 14 neighbour-side partials
-    (each below 2^27) and S home-side ones cannot wrap the 2^31 fixed-point range. A pair
-    force of 1.1e8 along x lies between 2^28 / 3 and 2^27: it sets the overflow bit in a
-    system whose neighbour lists take three slices, and not in one that takes one."""
-    _say("case: 1.1e8 kcal/mol/A pair force, three slices and one slice")
+def test_overflow_bound_per_partial(gpu):
+    """The float32 per-atom sums have a 2^35 kcal/mol/A range; every partial added into one
+    is checked against its share (one pair's or one workgroup's neighbour-side term below
+    2^27, home-side partials below what the 14 n_split neighbour-side ones leave, divided
+    by the LDS slices), so a sum can never wrap. A pair force of 1.1e8 (below 2^27) sets no
+    status bit, in a system whose neighbour lists take three slices and in one that takes
+    one; a pair force of 1.5e8 (above) sets it in both."""
+    _say("case: 1.1e8 and 1.5e8 kcal/mol/A pair forces, three slices and one slice")
     p_of = lambda L: dict(box=(L, L, L), r_cut=12.0, r_switch=10.0, coulomb_k=W.COULOMB_K,
                           sigma=np.array([1.0, 1.2]), epsilon=np.array([0.05, 0.1]), flags=0)
-    target = 1.1e8
-    lo, hi = 0.1, 0.6                  # |F| of a type-0 pair falls with r on [0.1, 0.6] A
-    for _ in range(80):
-        mid = 0.5 * (lo + hi)
-        f = oracle.pair_terms(p_of(24.5), 0, 0, 0.0, 0.0, mid * mid)[1] * mid
-        lo, hi = (mid, hi) if f > target else (lo, mid)
-    r = np.float32(lo)
+
+    def distance_for(target):
+        lo, hi = 0.1, 0.6              # |F| of a type-0 pair falls with r on [0.1, 0.6] A
+        for _ in range(80):
+            mid = 0.5 * (lo + hi)
+            f = oracle.pair_terms(p_of(24.5), 0, 0, 0.0, 0.0, mid * mid)[1] * mid
+            lo, hi = (mid, hi) if f > target else (lo, mid)
+        return np.float32(lo)
+
     rng = np.random.default_rng(31)
     # 4,096 atoms on a 16^3 lattice in a 24.5 A box (2x2x2 cells): 14 x 512 atoms in each
-    # home cell's half-shell list, three LDS slices
+    # home cell's half-shell list, three LDS slices; 60 atoms in a 40 A box: one slice
     dense = np.mod(_lattice_blob(rng, np.full(3, 0.4), 16, 1.53, 0.05), 24.5)
-    # 60 atoms in a 40 A box (3x3x3 cells): one slice
     sparse = np.mod(_lattice_blob(rng, np.full(3, 1.0), 4, 9.5, 0.5), 40.0)[:60]
-    for pos, L, want in ((dense, 24.5, True), (sparse, 40.0, False)):
-        pos = pos.astype(np.float32)
-        pos[1] = pos[0] + np.array([r, 0, 0], np.float32)   # the close pair, along x
-        n = len(pos)
-        t = np.zeros(n, np.int32)
-        q = np.zeros(n)
-        p = p_of(L)
-        f, e, ws, _ = run(p, pos.astype(np.float64), t, q, gpu)
-        st = api.read_status(ws)
-        _say("box", L, "atoms", n, "status", st, "force on the pair", f[0, 0], f[1, 0])
-        assert abs(f[0, 0]) > 2 ** 28 / 3 and abs(f[0, 0]) < 2 ** 27
-        assert bool(st & api.STATUS_FIXED_OVERFLOW) == want, (L, st)
-        if not want:
-            # the pair's own forces (the other atoms carry ~1e-6 kcal/mol/A, below the
-            # 2^-24 rounding of the neighbour-side sums)
-            ref = oracle.forces(p, pos, t, q, "bruteforce")
-            err = force_errors(f[:2], ref.force[:2], ref.abs_sum[:2])
-            assert err["max_norm"] <= 1e-5 and err["rms"] <= 1e-5, err
+    for target, want in ((1.1e8, False), (1.5e8, True)):
+        r = distance_for(target)
+        for base, L in ((dense, 24.5), (sparse, 40.0)):
+            pos = base.astype(np.float32)
+            pos[1] = pos[0] + np.array([r, 0, 0], np.float32)   # the close pair, along x
+            n = len(pos)
+            t = np.zeros(n, np.int32)
+            q = np.zeros(n)
+            p = p_of(L)
+            f, e, ws, _ = run(p, pos.astype(np.float64), t, q, gpu)
+            st = api.read_status(ws)
+            _say("target", target, "box", L, "atoms", n, "status", st, "pair force", f[0, 0])
+            assert bool(st & api.STATUS_FIXED_OVERFLOW) == want, (target, L, st)
+            if not want:
+                # the pair's own forces (the other atoms carry ~1e-6 kcal/mol/A, below the
+                # 2^-24 rounding of the neighbour-side sums)
+                ref = oracle.forces(p, pos, t, q, "bruteforce")
+                err = force_errors(f[:2], ref.force[:2], ref.abs_sum[:2])
+                assert err["max_norm"] <= 1e-5 and err["rms"] <= 1e-5, err
 
 
 def test_serving_failed_request_alone(gpu):
@@ -808,3 +811,24 @@ def test_copy_segments(gpu):
         for d, h, b, n in zip(dev, host, back, sizes):
             assert torch.equal(d.cpu()[off:off + n], h[off:off + n]), n
             assert torch.equal(b[off:off + n], h[off:off + n]), n
+
+
+@pytest.mark.parametrize("shell", [0, api.PAIR_FULL_SHELL])
+@pytest.mark.parametrize("double", [False, True])
+def test_work_split_same_bits(gpu, shell, double):
+    """One, two or four workgroups per home cell (each taking every s-th group of home atoms;
+    automatic choice too) give the same bits: forces from integer sums, and the energy from
+    the workgroups' exact integer partials added as integers. A 20,000-atom cube of 4^3
+    cells and the 3,000-atom system of 2^3 cells."""
+    _say("case: work split 1/2/4/auto, shell", shell, "double", double)
+    for s in (W.gen_system(20000, (58.5, 58.5, 58.5), 12), W.small_system()):
+        p = s.params()
+        pos = s.pos.astype(np.float64) if double else s.pos
+        q = s.charges.astype(np.float64) if double else s.charges
+        res = [run(p, pos, s.types, q, gpu, double=double, flags=shell | fl)[:2]
+               for fl in (api.PAIR_SPLIT(1), api.PAIR_SPLIT(2), api.PAIR_SPLIT(4), 0)]
+        for f, e in res[1:]:
+            assert np.array_equal(f, res[0][0]) and e == res[0][1]
+    r = oracle.forces(p, s.pos, s.types, s.charges, "celllist")
+    err = force_errors(res[0][0], r.force, r.abs_sum)
+    assert err["max_norm"] <= (1e-12 if double else 1e-5)
