@@ -174,7 +174,7 @@ md_status md_forces_f32_stages(const md_params* p, int64_t n_atoms, const float*
  *     until the process ends. Its device address is looked up once per device, on the
  *     first call with that device current.
  *   - Systems whose md_workspace_bytes(p, n_atoms, 0) exceeds that size are rejected with
- *     MD_ERR_CAPACITY before anything is enqueued (at 8 atom types about 280,000 atoms
+ *     MD_ERR_CAPACITY before anything is enqueued (at 8 atom types about 230,000 atoms
  *     of the 0.1 atoms/A^3 systems). Other argument errors as for md_forces_f32.
  *   - Every call on one device uses that device's one array: calls that overlap on one
  *     device (other streams, other host threads) race and give undefined results;

@@ -117,13 +117,14 @@ md_status make_plan(const md_params* p, int64_t n, int real_bytes, Plan* pl) {
   pl->off_start = o;     o = align_up(o + sizeof(int32_t) * (cells + 1));
   pl->off_cell = o;      o = align_up(o + sizeof(int32_t) * nn);
   pl->off_rank = o;      o = align_up(o + sizeof(int32_t) * nn);
+  const bool compact = uses_compact(p, real_bytes);
   pl->off_pos = o;       o = align_up(o + (size_t)4 * real_bytes * nn);
+  pl->off_hpre = o;      o = align_up(o + (compact ? (size_t)8 * real_bytes * nn : 0));
   pl->off_type = o;      o = align_up(o + sizeof(int32_t) * nn);
   pl->off_perm = o;      o = align_up(o + sizeof(int32_t) * nn);
   // per-atom partials: 27 slots x 3 components for the predicated kernel, or three
   // 64-bit fixed-point sums (float32) or three two-word ones (float64) for the compacted
   // kernel
-  const bool compact = uses_compact(p, real_bytes);
   pl->off_part = o;
   o = align_up(o + (compact ? sizeof(long long) * 3 * (real_bytes / 4) * nn
                             : (size_t)real_bytes * kSlots * 3 * nn));
@@ -169,6 +170,7 @@ SysArgs<Real> make_args(const md_params* p, const Plan& pl, int64_t n, const Rea
   a.cell = (int32_t*)(b + pl.off_cell);
   a.rank = (int32_t*)(b + pl.off_rank);
   a.pos = (P4<Real>*)(b + pl.off_pos);
+  a.hpre = (P4<Real>*)(b + pl.off_hpre);
   a.type = (int32_t*)(b + pl.off_type);
   a.perm = (int32_t*)(b + pl.off_perm);
   a.part = (Real*)(b + pl.off_part);

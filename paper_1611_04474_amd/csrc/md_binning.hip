@@ -585,6 +585,35 @@ __device__ inline void count_low(int32_t* s_low, bool low) {
   if ((threadIdx.x & 63) == 0 && b != 0ull) atomicAdd(s_low, (int32_t)__builtin_popcountll(b));
 }
 
+// The compacted kernel's constants of the atom at sorted position d of cell c as a home
+// atom (SysArgs::hpre): a = r - o with o the cell's centre, so that the kernel's
+// expanded-form prefilter |r_j - r_i|^2 = c_j - 2 a.(r_j - o) + |a|^2 becomes
+// c_j + (-2 a).r_j < rc^2 + margin - |a|^2 + (-2 a).o; and k q and the atom's row of the
+// type-pair table.
+template <typename Real>
+__device__ inline void write_hpre(const SysArgs<Real>& a, int64_t c, int32_t d, const P4<Real>& p,
+                                  int t) {
+  const int c0 = (int)(c % a.nx), c1 = (int)((c / a.nx) % a.ny),
+            c2 = (int)(c / ((int64_t)a.nx * a.ny));
+  const Real O0 = ((Real)c0 + Real(0.5)) * (a.L[0] / (Real)a.nx);
+  const Real O1 = ((Real)c1 + Real(0.5)) * (a.L[1] / (Real)a.ny);
+  const Real O2 = ((Real)c2 + Real(0.5)) * (a.L[2] / (Real)a.nz);
+  const Real rx = p.x - O0, ry = p.y - O1, rz = p.z - O2;
+  const Real ax = Real(-2) * rx, ay = Real(-2) * ry, az = Real(-2) * rz;
+  P4<Real> h0, h1;
+  h0.x = ax;
+  h0.y = ay;
+  h0.z = az;
+  h0.w = (a.rc2 + Real(kPrefilterMargin)) - fma(rz, rz, fma(ry, ry, rx * rx)) +
+         (ax * O0 + ay * O1 + az * O2);
+  h1.x = a.coulomb_k * p.w;
+  h1.y = int_to_slot<Real>(t * a.n_types);
+  h1.z = Real(0);
+  h1.w = Real(0);
+  a.hpre[2 * (int64_t)d] = h0;
+  a.hpre[2 * (int64_t)d + 1] = h1;
+}
+
 template <typename Real>
 __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
   constexpr int kChunk = 1024;
@@ -652,6 +681,7 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
       a.pos[d] = p;
       a.type[d] = my_t[k];
       a.perm[d] = (int32_t)(my_key[k] & 0x7fffffffull);
+      if (a.compact) write_hpre(a, c, d, p, my_t[k]);
     }
     __syncthreads();
     if (threadIdx.x == 0) a.zsplit[c] = s_low;
@@ -687,9 +717,12 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
       count_low(&s_low, in && !(my_key[k] >> 63));
       if (!in) continue;
       const int32_t d = s0 + my_rank[k];
-      a.pos[d] = a.upos[s0 + e];
-      a.type[d] = a.ukey[s0 + e].type;
+      const P4<Real> p = a.upos[s0 + e];
+      const int32_t ty = a.ukey[s0 + e].type;
+      a.pos[d] = p;
+      a.type[d] = ty;
       a.perm[d] = (int32_t)(my_key[k] & 0x7fffffffull);
+      if (a.compact) write_hpre(a, c, d, p, ty);
     }
   }
   __syncthreads();

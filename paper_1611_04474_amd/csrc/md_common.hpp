@@ -20,6 +20,9 @@ constexpr int kBinLdsCells = 32768;  // largest grid binned with a per-block LDS
 constexpr int kBinMaxBlocks = 1024;  // blocks of that pass
 constexpr int kBinThreads = 512;     // threads per block of that pass
 constexpr int kBinChunkUnit = 2048;  // atoms per block: a multiple of this (4 per thread)
+// A^2 added to rc^2 by the compacted kernel's expanded-form prefilter (its constants per
+// home atom are written by the in-cell sort)
+constexpr float kPrefilterMargin = 0.05f;
 
 // Workspace header (first 256 bytes).
 // Drain depth selected by MD_PAIR_DRAIN in md_params.flags (2 when the field is 0).
@@ -67,6 +70,18 @@ struct alignas(4 * sizeof(Real)) P4 {
   Real x, y, z, w;
 };
 
+// A small non-negative integer carried in a Real slot as bits (no arithmetic is done on it).
+template <typename Real>
+__device__ inline Real int_to_slot(int32_t v) {
+  if constexpr (sizeof(Real) == 4) return __int_as_float(v);
+  else return __longlong_as_double((long long)v);
+}
+template <typename Real>
+__device__ inline int32_t slot_to_int(Real v) {
+  if constexpr (sizeof(Real) == 4) return __float_as_int(v);
+  else return (int32_t)__double_as_longlong(v);
+}
+
 // Cell grid and workspace carve-up for one system.
 struct Plan {
   int32_t dims[3];
@@ -75,7 +90,7 @@ struct Plan {
   int64_t n;
   int real_bytes;               // 4 or 8
   // byte offsets
-  size_t off_count, off_start, off_cell, off_rank, off_pos, off_type, off_perm,
+  size_t off_count, off_start, off_cell, off_rank, off_pos, off_hpre, off_type, off_perm,
       off_part, off_facc, off_epart, off_lj, off_paircount, off_bhist, off_bstat, off_order,
       off_cost,
       off_zsplit, off_ukey, off_upos, off_kpart, total;
@@ -105,6 +120,11 @@ struct SysArgs {
                                // in-cell sort
   P4<Real>* upos;              // [n] wrapped (x, y, z, q), same order
   P4<Real>* pos;               // [n] sorted (x,y,z,q)
+  P4<Real>* hpre;              // [2n] sorted, for the compacted kernel (written by the
+                               // in-cell sort): the atom's prefilter constants as a home
+                               // atom, (ax, ay, az, thb) = (-2 a, rc^2 + margin - |a|^2 -
+                               // 2 a.o) with a = r - o, o its cell's centre, and
+                               // (k q, type n_types as integer bits, 0, 0)
   int32_t* type;               // [n] sorted
   int32_t* perm;               // [n] sorted -> original
   Real* part;                  // [kSlots][3][n]

@@ -70,7 +70,6 @@ __host__ __device__ constexpr int fifo_entries(int drain) { return 64 * (drain +
 constexpr int kMaxSeg = 36;         // 9 (dy, dz) rows x 2 z halves, each split at most once by
                                     // an x wrap
 constexpr int kLdsBytes = 160 * 1024;
-constexpr float kMargin = 0.05f;    // A^2 added to rc^2 by the expanded-form prefilter
 constexpr float kWin = 1.0e-3f;     // A added to r_cut for the x-window
 constexpr float kBigU = 1.0e30f;    // squared distance given to lanes that must add nothing
 // Range of the per-atom 64-bit fixed-point sums of the float32 path: units of 2^-28
@@ -102,6 +101,10 @@ __device__ inline float vmax(float a, float b) { return fmaxf(a, b); }
 __device__ inline double vmax(double a, double b) { return fmax(a, b); }
 __device__ inline float vsqrt(float a) { return __builtin_sqrtf(a); }
 __device__ inline double vsqrt(double a) { return sqrt(a); }
+// square root of the x-window's half-width: float32's hardware square root (within 1 ulp,
+// far inside the window's 1e-3 A margin), float64's correctly rounded one
+__device__ inline float wsqrt(float a) { return __builtin_amdgcn_sqrtf(a); }
+__device__ inline double wsqrt(double a) { return sqrt(a); }
 __device__ inline float4 mk4(float x, float y, float z, float w) { return make_float4(x, y, z, w); }
 __device__ inline double4 mk4(double x, double y, double z, double w) {
   return make_double4(x, y, z, w);
@@ -159,6 +162,8 @@ struct Hdr {
   int total;        // neighbour-list length
   int iters;        // binary-search steps that cover the longest segment
   int next;         // next group of home atoms to hand out
+  int done;         // waves that have added their energy to esum
+  long long esum[2];   // the workgroup's energy (float64: high and low words)
 };
 
 // LDS layout in bytes: header | FIFOs | LJ (c12, c6) [nt^2] | (x, y, z, |r - o_g|^2, in
@@ -203,20 +208,24 @@ __device__ inline float rowsum16(float v) {
   return v;
 }
 
+// Round to nearest even of s to a 64-bit integer, for s a float64 integer or |s| < 2^51:
+// below 2^51 the add of 1.5 * 2^52 rounds s once to an integer, which the low bits of the
+// sum then hold (as the neighbour side's round_prod_2m24); larger s are integers already
+// (a float32 value scaled by a power of two) and take the library conversion.
+__device__ inline long long round_to_i64(double s) {
+  if (fabs(s) < 2251799813685248.0)   // 2^51
+    return __builtin_bit_cast(long long, s + 6755399441055744.0) - 0x4338000000000000ll;
+  return __double2ll_rn(s);
+}
+
 // float -> 64-bit fixed point, one unit = 2^-28, round to nearest even, exact but for
-// that one rounding.
+// that one rounding (v 2^28 is exact in float64).
 __device__ inline long long to_fixed(float v, uint32_t& st) {
-  float a = fabsf(v);
-  if (!(a < kAccRange)) {
+  if (!(fabsf(v) < kAccRange)) {
     st |= MD_STATUS_FIXED_OVERFLOW;
     return 0;
   }
-  float hi = floorf(a);
-  float fr = a - hi;                                // exact
-  float lo = rintf(fr * 268435456.0f);              // exact scaling; < 2^28
-  unsigned long long m =
-      ((unsigned long long)hi << 28) + (unsigned long long)(unsigned)lo;
-  return v < 0.f ? -(long long)m : (long long)m;
+  return round_to_i64((double)v * 268435456.0);
 }
 
 // round(a b 2^24) (to nearest even) as a 64-bit integer, for float32 a, b with
@@ -359,7 +368,7 @@ __device__ inline void lds_store_u16_lanes4(uint32_t a0, uint32_t a1, uint32_t a
 // kDiag: count filter passes, cutoff passes and filtered slots (MD_DIAG_COUNTERS).
 // kHalf: the half shell (64-bit fixed-point sums only). kDrain: force batches per drain.
 template <typename Real, bool kHalf, int kCoul, bool kClamp, bool kDiag, int kDrain>
-__device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<Real>& a, int cap,
+__device__ __attribute__((always_inline)) inline bool pair_fs(const SysArgs<Real>& a, int cap,
                                                               int64_t cellA, int part) {
   extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
   constexpr bool kF32 = sizeof(Real) == 4;
@@ -389,7 +398,6 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<Real
   constexpr bool diag = kDiag;
   const bool f32 = kF32 && !kHalf && (a.flags & MD_ACCUM_F32_ATOMIC) != 0;
   const Real rc2 = a.rc2, rs2 = a.rs2, inv_sw = a.inv_sw, sw12 = Real(12) * a.inv_sw;
-  const Real kc = a.coulomb_k;
   const R2 ew = mk2<Real>(a.ewald_alpha, a.ewald_alpha * Real(1.1283791670955126));   // 2/sqrt(pi)
   const Real L0 = a.L[0], L1 = a.L[1], L2 = a.L[2];
   const int ac0 = (int)(cellA % a.nx), ac1 = (int)((cellA / a.nx) % a.ny),
@@ -488,6 +496,8 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<Real
     if (lane == 0) {
       H.n_seg = __builtin_popcountll(heads);
       H.total = tot;
+      H.done = 0;
+      H.esum[0] = H.esum[1] = 0;
       int it = 0;
       while ((1 << it) <= ml) ++it;   // steps of a lower_bound over ml elements
       H.iters = it;
@@ -606,8 +616,14 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<Real
       const int ib = kQ * o;
       const int nv = min(kQ, nA - ib);   // home atoms present in this group
 
-      Real xi[kQ], yi[kQ], zi[kQ], kq[kQ], fx[kQ], fy[kQ], fz[kQ];
-      Real ax[kQ], ay[kQ], az[kQ], thb[kQ];
+      // home atom k of the group in the frame of no shift (xi, yi, zi) and in that of the
+      // current segment (xs, ys, zs; its shift class cur_g), its prefilter constants (ax,
+      // ay, az; thb, and thr, the threshold in the current frame), k q and its row of the
+      // type-pair table, loaded as the in-cell sort wrote them; an absent atom (past nv)
+      // repeats the last one with ax = 0 and thb = -1, which c_j >= 0 never passes
+      Real xi[kQ], yi[kQ], zi[kQ], thb[kQ];   // frame of no shift
+      Real xs[kQ], ys[kQ], zs[kQ], thr[kQ], kq[kQ], fx[kQ], fy[kQ], fz[kQ];
+      Real ax[kQ], ay[kQ], az[kQ];
       int row[kQ];
       uint32_t fb[kQ];   // byte address of the next free slot of FIFO k
       uint32_t fl[kQ];   // fb[k] at which FIFO k holds a full drain
@@ -615,35 +631,44 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<Real
       Real xmin = 0, xmax = 0, ymin = 0, ymax = 0, zmin = 0, zmax = 0;
 #pragma unroll
       for (int k = 0; k < kQ; ++k) {
-        const bool v = k < nv;
-        const int s = sA + ib + (v ? k : 0);
+        const int s = sA + ib + min(k, nv - 1);
         const P4<Real> p = a.pos[s];
+        const P4<Real> h0 = a.hpre[2 * (int64_t)s], h1 = a.hpre[2 * (int64_t)s + 1];
         xi[k] = p.x;
         yi[k] = p.y;
         zi[k] = p.z;
-        kq[k] = kc * p.w;
-        row[k] = a.type[s] * nt;
+        ax[k] = h0.x;
+        ay[k] = h0.y;
+        az[k] = h0.z;
+        thb[k] = h0.w;
+        kq[k] = h1.x;
+        row[k] = slot_to_int(h1.y);
         xmin = k == 0 ? p.x : vmin(xmin, p.x);
         xmax = k == 0 ? p.x : vmax(xmax, p.x);
         ymin = k == 0 ? p.y : vmin(ymin, p.y);
         ymax = k == 0 ? p.y : vmax(ymax, p.y);
         zmin = k == 0 ? p.z : vmin(zmin, p.z);
         zmax = k == 0 ? p.z : vmax(zmax, p.z);
-        // prefilter in the frame of group g, with a = r_i - o (the same in every frame):
-        // |r_j - r_i|^2 = c_j - 2 a.(r_j - o_g) + |a|^2, c_j = |r_j - o_g|^2, so the test
-        // c_j + ax.r_j < rc^2 + margin - |a|^2 + ax.o_g with ax = -2a
-        const Real rx = p.x - O0, ry = p.y - O1, rz = p.z - O2;
-        ax[k] = v ? Real(-2) * rx : Real(0);
-        ay[k] = v ? Real(-2) * ry : Real(0);
-        az[k] = v ? Real(-2) * rz : Real(0);
-        // an absent atom gets -1, which c_j >= 0 never passes
-        thb[k] = v ? (rc2 + Real(kMargin)) - mad(rz, rz, mad(ry, ry, rx * rx)) +
-                         (ax[k] * O0 + ay[k] * O1 + az[k] * O2)
-                   : Real(-1);
         fx[k] = fy[k] = fz[k] = Real(0);
         fb[k] = fk0 + 2u * (uint32_t)(k * kFifo);
         fl[k] = fb[k] + 2u * (uint32_t)(64 * kDrain);
         cnt[k] = 0;
+      }
+      if (nv < kQ) {
+#pragma unroll
+        for (int k = 1; k < kQ; ++k) {
+          if (k >= nv) {
+            ax[k] = ay[k] = az[k] = Real(0);
+            thb[k] = Real(-1);
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kQ; ++k) {
+        xs[k] = xi[k];
+        ys[k] = yi[k];
+        zs[k] = zi[k];
+        thr[k] = thb[k];
       }
       Real e_lane = 0;
       // the largest |F_j| component |f dx| handed to the neighbour side (float32: as
@@ -663,7 +688,7 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<Real
         const Real gy = vmax(vmax((Real)slab.x - ymax, ymin - (Real)slab.y) - Real(kWin), Real(0));
         const Real gz = vmax(vmax((Real)slab.z - zmax, zmin - (Real)slab.w) - Real(kWin), Real(0));
         const Real w2 = mad(R, R, -mad(gz, gz, gy * gy));
-        const Real hw = w2 > Real(0) ? vsqrt(w2) : Real(-1);
+        const Real hw = w2 > Real(0) ? wsqrt(w2) : Real(-1);
         const Real hx = (sg & 1) ? L0 : Real(0);
         // a segment out of reach gets the empty window [sb, sb)
         const Real xlo = w2 > Real(0) ? (xmin - hx) - hw : Real(-INFINITY);
@@ -678,7 +703,6 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<Real
         }
       }
 
-      Real xs[kQ], ys[kQ], zs[kQ], thr[kQ];
       // entries in FIFO k
       auto fill = [&](int k) __attribute__((always_inline)) {
         return (int)((fb[k] - fk0) >> 1) - k * kFifo;
@@ -786,7 +810,7 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<Real
         }
       };
 
-      int cur_g = -1;
+      int cur_g = 0;   // the group starts in the frame of no shift
       for (int s = 0; s < n_seg; ++s) {
         int lo = __builtin_amdgcn_readlane(wlo, s);
         const int hi = max(__builtin_amdgcn_readlane(whi, split ? s + 32 : s), lo);
@@ -798,7 +822,7 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<Real
         if (lo >= hi) continue;
         const int g = __builtin_amdgcn_readlane(sg, s);
         if (g != cur_g) {
-          if (cur_g >= 0) flush();   // the home side changes frame
+          flush();   // the home side changes frame
           cur_g = g;
           const Real hx = (g & 1) ? L0 : Real(0), hy = (g & 2) ? L1 : Real(0),
                      hz = (g & 4) ? L2 : Real(0);
@@ -807,7 +831,7 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<Real
             xs[k] = xi[k] - hx;   // exact: such home atoms lie in the last cell of the axis
             ys[k] = yi[k] - hy;
             zs[k] = zi[k] - hz;
-            // ax.o_g = ax.o - ax.h
+            // ax.o_g = ax.o - ax.h (an absent atom keeps thr = -1: its ax is 0)
             thr[k] = thb[k] - (ax[k] * hx + ay[k] * hy + az[k] * hz);
           }
         }
@@ -867,7 +891,7 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<Real
           }
         }
       }
-      if (cur_g >= 0) flush();
+      flush();
 
       // per home atom and component: the 64 lane partials summed in one fixed order. The
       // two wave halves exchange the sums the other one keeps (lanes l and l ^ 32: home
@@ -983,7 +1007,7 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<Real
         // rounding), so the workgroup total does not depend on which wave took which group
         const float v = e_lane * 16777216.0f;
         if (!(fabsf(v) < 4.6116860184273879e18f)) st |= MD_STATUS_FIXED_OVERFLOW;
-        else e_fix += __float2ll_rn(v);
+        else e_fix += round_to_i64((double)v);
         if (kHalf && !(jmax < kNbrPartialMax)) st |= MD_STATUS_FIXED_OVERFLOW;
       } else {
         if (!(fabs(e_lane) < 1.0e9)) {
@@ -1035,42 +1059,52 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<Real
           }
         }
       }
-      __syncthreads();
+      // the next slice clears the accumulators; after the last one nothing waits here, so
+      // the workgroup can end while its atomics are still on their way
+      if (P0 + cap < total) __syncthreads();
     }
   }
 
-  // workgroup energy (the full shell saw each pair from both atoms), a fixed tree over
-  // 1024 lanes of exact integer sums
-  long long* sE = reinterpret_cast<long long*>(s_dyn + LL.f4);
-  if constexpr (kF32) {
-    sE[tid] = e_fix;
-    for (int e = kThreads + tid; e < 1024; e += kThreads) sE[e] = 0;   // pad the tree to 1024
-    __syncthreads();
-    for (int off = 512; off > 0; off >>= 1) {
-      if (tid < off) sE[tid] += sE[tid + off];
-      __syncthreads();
+  // workgroup energy (the full shell saw each pair from both atoms) as an exact integer
+  // sum: each wave adds its lanes, then its total into the workgroup's LDS words (integer
+  // adds: the result does not depend on their order); the last wave to do so stores the
+  // total, which the finalize kernel adds to the others as integers too. No barrier: a
+  // wave's LDS operations complete in order, so the last wave's read follows every other
+  // wave's add.
+  bool last;
+  {
+    long long v0, v1 = 0;
+    if constexpr (kF32) {
+      v0 = e_fix;
+    } else {
+      const Fix2 v = normalize2(e_fix, e_lo);   // low words below 2^52: 1024 of them fit
+      v0 = v.hi;
+      v1 = v.lo;
     }
-    // the workgroup's exact integer sum; the finalize kernel adds them as integers too
-    if (tid == 0)
-      reinterpret_cast<long long*>(a.epart)[part * a.n_cells + cellA] = sE[0];
-  } else {
-    const Fix2 v = normalize2(e_fix, e_lo);   // low words below 2^52: 1024 of them fit
-    sE[tid] = v.hi;
-    sE[1024 + tid] = v.lo;
-    for (int e = kThreads + tid; e < 1024; e += kThreads) sE[e] = sE[1024 + e] = 0;
-    __syncthreads();
-    for (int off = 512; off > 0; off >>= 1) {
-      if (tid < off) {
-        sE[tid] += sE[tid + off];
-        sE[1024 + tid] += sE[1024 + tid + off];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      v0 += __shfl_xor(v0, off);
+      if constexpr (!kF32) v1 += __shfl_xor(v1, off);
+    }
+    int rank = 0;
+    if (lane == 0) {
+      lds_add(&H.esum[0], v0);
+      if constexpr (!kF32) lds_add(&H.esum[1], v1);
+      rank = __hip_atomic_fetch_add(&H.done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    last = __builtin_amdgcn_readfirstlane(__shfl(rank, 0)) == kNW - 1;
+    if (last && lane == 0) {
+      const int64_t slot = part * a.n_cells + cellA;
+      long long* ep = reinterpret_cast<long long*>(a.epart);
+      if constexpr (kF32) {
+        ep[slot] = __hip_atomic_load(&H.esum[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      } else {
+        const Fix2 s2 = normalize2(
+            __hip_atomic_load(&H.esum[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP),
+            __hip_atomic_load(&H.esum[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+        ep[2 * slot] = s2.hi;
+        ep[2 * slot + 1] = s2.lo;
       }
-      __syncthreads();
-    }
-    if (tid == 0) {
-      long long* ep = reinterpret_cast<long long*>(a.epart) + 2 * (part * a.n_cells + cellA);
-      const Fix2 t = normalize2(sE[0], sE[1024]);
-      ep[0] = t.hi;
-      ep[1] = t.lo;
     }
   }
   if (st) atomicOr(&a.hdr->status, st);
@@ -1090,6 +1124,7 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<Real
     atomicAdd(&a.hdr->diag[3], slot_count);
     atomicAdd(&a.hdr->diag[4], lane_count);
   }
+  return last;   // this wave is the workgroup's last to finish
 }
 
 // The workgroup's time for its home cell (constant 100 MHz clock) goes to cost[cell]: the
@@ -1099,20 +1134,18 @@ __device__ __attribute__((always_inline)) inline void pair_fs(const SysArgs<Real
 // this grid.
 // The same workgroup also adds its shader-clock cycles (s_memtime) and its 100 MHz ticks
 // to the header's two clock sums: their ratio is the clock the kernel ran at, weighted by
-// workgroup time.
+// workgroup time. Called by lane 0 of the workgroup's last wave to finish.
 template <typename Real>
 __device__ inline void record_cost(const SysArgs<Real>& a, int64_t cell, int part, uint64_t t0,
                                    uint64_t c0, bool first) {
-  if (threadIdx.x == 0) {   // after the workgroup's last barrier
-    const uint64_t dc = __builtin_amdgcn_s_memtime() - c0;
-    const uint64_t dt = __builtin_amdgcn_s_memrealtime() - t0;
-    if (part == 0) a.cost[cell] = dt < 0xffffffffull ? (uint32_t)dt : 0xffffffffu;
-    atomicAdd(&a.hdr->clock[0], (unsigned long long)dc);
-    atomicAdd(&a.hdr->clock[1], (unsigned long long)dt);
-    if (first) {
-      a.hdr->cost_key = kCostKey;
-      a.hdr->cost_cells = (uint32_t)a.n_cells;
-    }
+  const uint64_t dc = __builtin_amdgcn_s_memtime() - c0;
+  const uint64_t dt = __builtin_amdgcn_s_memrealtime() - t0;
+  if (part == 0) a.cost[cell] = dt < 0xffffffffull ? (uint32_t)dt : 0xffffffffu;
+  atomicAdd(&a.hdr->clock[0], (unsigned long long)dc);
+  atomicAdd(&a.hdr->clock[1], (unsigned long long)dt);
+  if (first) {
+    a.hdr->cost_key = kCostKey;
+    a.hdr->cost_cells = (uint32_t)a.n_cells;
   }
 }
 
@@ -1125,8 +1158,8 @@ void k_pair_fs(SysArgs<Real> a, int cap) {
   // workgroup b: cell order[b % n_cells], part b / n_cells (every cell's first part first)
   const int64_t cell = a.order[blockIdx.x % a.n_cells];
   const int part = (int)(blockIdx.x / a.n_cells);
-  pair_fs<Real, kHalf, kCoul, kClamp, kDiag, kDrain>(a, cap, cell, part);
-  record_cost(a, cell, part, t0, c0, blockIdx.x == 0);
+  const bool last = pair_fs<Real, kHalf, kCoul, kClamp, kDiag, kDrain>(a, cap, cell, part);
+  if (last && (threadIdx.x & 63) == 0) record_cost(a, cell, part, t0, c0, blockIdx.x == 0);
 }
 
 // One launch for a batch: block b is cell order[b - cum[s]] of system s.
@@ -1139,8 +1172,8 @@ void k_pair_fs_batch(Batch<float> b, int cap) {
   const int s = b.pick(blockIdx.x, unit);
   const int64_t cell = b.sys[s].order[unit % b.sys[s].n_cells];
   const int part = (int)(unit / b.sys[s].n_cells);
-  pair_fs<float, kHalf, kCoul, kClamp, kDiag, kDrain>(b.sys[s], cap, cell, part);
-  record_cost(b.sys[s], cell, part, t0, c0, unit == 0);
+  const bool last = pair_fs<float, kHalf, kCoul, kClamp, kDiag, kDrain>(b.sys[s], cap, cell, part);
+  if (last && (threadIdx.x & 63) == 0) record_cost(b.sys[s], cell, part, t0, c0, unit == 0);
 }
 
 template <bool H, int S, bool C, bool D, int R>
@@ -1174,8 +1207,6 @@ hipError_t dispatch(const SysArgs<Real>& a, const Args& args, int n_types, int64
   const int drain = md_pair_drain(a.flags);
   if (drain != kDrainDefault && !(half && clamp && sizeof(Real) == 4)) return hipErrorInvalidValue;
   const int cap = fs_cap<Real>(n_types, half, diag, drain);
-  // the float64 energy tree takes 2 x 1024 int64 of the staged-atom block
-  if (sizeof(Real) == 8 && cap < 512) return hipErrorInvalidValue;
   const size_t shmem = (size_t)lds_layout<Real>(cap, n_types, half, diag, drain).total;
   const dim3 grid((unsigned)blocks), block(kThreads);
   auto go = [&](auto h, auto d) {
