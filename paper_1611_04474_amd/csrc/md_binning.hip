@@ -492,11 +492,12 @@ __device__ inline void scatter(const SysArgs<Real>& a, int64_t blk) {
 // hb = 1024 blk / bin_chunk. Thread c adds up the histogram blocks' counts of cell c, all
 // of them and those of the blocks before hb; the totals are scanned into the cells' starts
 // in LDS, and each atom goes to start[c] + (offset of block hb in cell c) + (its rank
-// within hb). Every block repeats this scan, which replaces a kernel of its own; block 0
-// also writes start[] and runs scan_tail. All loads are issued before the first is used.
+// within hb). Every block repeats this scan, which replaces a kernel of its own; one more
+// block, the last, scatters nothing: it writes start[] and runs scan_tail, alongside the
+// others. All loads are issued before the first is used.
 template <typename Real>
 __host__ __device__ inline int64_t fused_blocks(const SysArgs<Real>& a) {
-  return scan_fused(a) ? (a.n + 1023) / 1024 : 0;
+  return scan_fused(a) ? (a.n + 1023) / 1024 + 1 : 0;
 }
 
 template <typename Real>
@@ -518,11 +519,12 @@ __device__ inline void scatter_fused(const SysArgs<Real>& a, const TypeTable& tt
   const Real x = a.pos_in[3 * ic + 0], y = a.pos_in[3 * ic + 1], z = a.pos_in[3 * ic + 2];
   const Real q = a.q_in[ic];
   const int ty = a.type_in[ic];
-  const Status st_blocks = block_status(a, blk == 0);
-  // block 0: this cell's cost in the last pair kernel (loaded before it is known whether
+  const bool tail = blk == (a.n + 1023) / 1024;   // the block that ends the scan
+  const Status st_blocks = block_status(a, tail);
+  // tail block: this cell's cost in the last pair kernel (loaded before it is known whether
   // the costs are valid, so that both loads are in flight together)
-  const uint32_t cost_t = blk == 0 && t < nc ? a.cost[t] : 0u;
-  const bool by_cost = blk == 0 && have_costs(a);
+  const uint32_t cost_t = tail && t < nc ? a.cost[t] : 0u;
+  const bool by_cost = tail && have_costs(a);
   int32_t tot = 0, off = 0;
   if (t < nc) {
     for (int b0 = 0; b0 < B; b0 += 64) {
@@ -541,11 +543,11 @@ __device__ inline void scatter_fused(const SysArgs<Real>& a, const TypeTable& tt
   if (t < nc) {
     s_start[t] = start_c;
     s_off[t] = off;
-    s_cnt[t] = by_cost ? (int32_t)cost_key(cost_t) : tot;   // block 0's order key
+    s_cnt[t] = by_cost ? (int32_t)cost_key(cost_t) : tot;   // the tail block's order key
   }
   __syncthreads();
   if (i < a.n) put_atom(a, i, ci, s_start[ci] + s_off[ci] + rk, x, y, z, q, ty);
-  if (blk == 0) {
+  if (tail) {
     if (t < nc) a.start[t] = start_c;
     if (t == 0) a.start[nc] = all;
     scan_tail(a, tt, 1, s_tot, [&](int64_t cc) { return (uint32_t)s_cnt[cc]; }, st_blocks.bits());
@@ -585,27 +587,35 @@ __device__ inline void count_low(int32_t* s_low, bool low) {
   if ((threadIdx.x & 63) == 0 && b != 0ull) atomicAdd(s_low, (int32_t)__builtin_popcountll(b));
 }
 
-// The compacted kernel's constants of the atom at sorted position d of cell c as a home
-// atom (SysArgs::hpre): a = r - o with o the cell's centre, so that the kernel's
-// expanded-form prefilter |r_j - r_i|^2 = c_j - 2 a.(r_j - o) + |a|^2 becomes
+// Centre of cell c (the origin the compacted kernel's prefilter is expanded about).
+template <typename Real>
+__device__ inline P4<Real> cell_centre(const SysArgs<Real>& a, int64_t c) {
+  const int32_t cc = (int32_t)c, nx = a.nx, nxy = a.nx * a.ny;
+  const int c0 = cc % nx, c1 = (cc / nx) % a.ny, c2 = cc / nxy;
+  P4<Real> o;
+  o.x = ((Real)c0 + Real(0.5)) * (a.L[0] / (Real)a.nx);
+  o.y = ((Real)c1 + Real(0.5)) * (a.L[1] / (Real)a.ny);
+  o.z = ((Real)c2 + Real(0.5)) * (a.L[2] / (Real)a.nz);
+  o.w = Real(0);
+  return o;
+}
+
+// The compacted kernel's constants of the atom at sorted position d as a home atom
+// (SysArgs::hpre), with o its cell's centre: a = r - o, so that the kernel's expanded-form
+// prefilter |r_j - r_i|^2 = c_j - 2 a.(r_j - o) + |a|^2 becomes
 // c_j + (-2 a).r_j < rc^2 + margin - |a|^2 + (-2 a).o; and k q and the atom's row of the
 // type-pair table.
 template <typename Real>
-__device__ inline void write_hpre(const SysArgs<Real>& a, int64_t c, int32_t d, const P4<Real>& p,
-                                  int t) {
-  const int c0 = (int)(c % a.nx), c1 = (int)((c / a.nx) % a.ny),
-            c2 = (int)(c / ((int64_t)a.nx * a.ny));
-  const Real O0 = ((Real)c0 + Real(0.5)) * (a.L[0] / (Real)a.nx);
-  const Real O1 = ((Real)c1 + Real(0.5)) * (a.L[1] / (Real)a.ny);
-  const Real O2 = ((Real)c2 + Real(0.5)) * (a.L[2] / (Real)a.nz);
-  const Real rx = p.x - O0, ry = p.y - O1, rz = p.z - O2;
+__device__ inline void write_hpre(const SysArgs<Real>& a, const P4<Real>& o, int32_t d,
+                                  const P4<Real>& p, int t) {
+  const Real rx = p.x - o.x, ry = p.y - o.y, rz = p.z - o.z;
   const Real ax = Real(-2) * rx, ay = Real(-2) * ry, az = Real(-2) * rz;
   P4<Real> h0, h1;
   h0.x = ax;
   h0.y = ay;
   h0.z = az;
   h0.w = (a.rc2 + Real(kPrefilterMargin)) - fma(rz, rz, fma(ry, ry, rx * rx)) +
-         (ax * O0 + ay * O1 + az * O2);
+         (ax * o.x + ay * o.y + az * o.z);
   h1.x = a.coulomb_k * p.w;
   h1.y = int_to_slot<Real>(t * a.n_types);
   h1.z = Real(0);
@@ -622,6 +632,7 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
   __shared__ int32_t s_low;
   const int32_t s0 = a.start[c];
   const int32_t m = a.start[c + 1] - s0;
+  const P4<Real> o = cell_centre(a, c);
   if (threadIdx.x == 0) s_low = 0;
   if (m == 0) {
     if (threadIdx.x == 0) a.zsplit[c] = 0;
@@ -681,7 +692,7 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
       a.pos[d] = p;
       a.type[d] = my_t[k];
       a.perm[d] = (int32_t)(my_key[k] & 0x7fffffffull);
-      if (a.compact) write_hpre(a, c, d, p, my_t[k]);
+      if (a.compact) write_hpre(a, o, d, p, my_t[k]);
     }
     __syncthreads();
     if (threadIdx.x == 0) a.zsplit[c] = s_low;
@@ -722,7 +733,7 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
       a.pos[d] = p;
       a.type[d] = ty;
       a.perm[d] = (int32_t)(my_key[k] & 0x7fffffffull);
-      if (a.compact) write_hpre(a, c, d, p, ty);
+      if (a.compact) write_hpre(a, o, d, p, ty);
     }
   }
   __syncthreads();
