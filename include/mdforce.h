@@ -124,7 +124,8 @@ typedef struct {
   double ewald_alpha;     /* 1/A, > 0: Ewald splitting parameter (MD_COULOMB_EWALD) */
 } md_params;
 
-/* Bytes of device workspace needed by md_forces_f32 (double_precision = 0) or
+/* Library support (no passage of the paper defines it: the caller owns all device memory).
+ * Bytes of device workspace needed by md_forces_f32 (double_precision = 0) or
  * md_forces_f64 (double_precision = 1) for n_atoms atoms with p->flags (the flags
  * choose the pair kernel, whose per-atom buffers differ in size). Returns 0 when the
  * parameters are invalid. The workspace must be 256-byte aligned; its contents
@@ -145,14 +146,17 @@ size_t md_workspace_bytes(const md_params* p, int64_t n_atoms, int double_precis
  *   d_energy  [1] float64 output, total pair energy over unique pairs, kcal/mol.
  *   d_ws      workspace of at least md_workspace_bytes(p, n_atoms, 0) bytes.
  * n_atoms == 0 enqueues a zero energy only. Pair arithmetic is float32; per-atom
- * sums are 64-bit fixed point unless MD_ACCUM_F32_ATOMIC; the energy is summed in
- * float64 in a fixed order.
+ * sums are 64-bit fixed point unless MD_ACCUM_F32_ATOMIC; the energy is an exact sum of
+ * 64-bit fixed-point partials (2^-24 kcal/mol) after the compacted kernel, and a float64
+ * sum in a fixed order after the predicated one.
  */
 md_status md_forces_f32(const md_params* p, int64_t n_atoms, const float* d_pos,
                         const int32_t* d_type, const float* d_charge, float* d_force,
                         double* d_energy, void* d_ws, size_t ws_bytes, void* stream);
 
-/* Stages of one evaluation, for callers that time or interleave them:
+/* Library support (no passage of the paper: the stages are those of Section 2.1's
+ * iteration, binning, pair forces, per-atom sums, enqueued separately).
+ * Stages of one evaluation, for callers that time or interleave them:
  *   MD_STAGE_BIN       clear counters, wrap positions, counting-sort binning;
  *   MD_STAGE_PAIR      cutoff filter and force over all cell-pair tasks;
  *   MD_STAGE_FINALIZE  per-atom sums in the caller's order and the total energy.
@@ -243,7 +247,8 @@ typedef struct {
   size_t ws_bytes;
 } md_system;
 
-/* Evaluates n_sys independent systems, each in its own periodic box with its own
+/* Serving support (no passage of the paper: it evaluates one system at a time).
+ * Evaluates n_sys independent systems, each in its own periodic box with its own
  * workspace, as one launch sequence on `stream`: each kernel of the path is
  * launched once for the whole batch. Results are identical to one md_forces_f32
  * call per system. Argument errors of any system fail the whole call before
@@ -286,11 +291,15 @@ typedef struct {
 
 md_status md_copy_segments(const md_copy_segment* segs, int32_t n_segs, void* stream);
 
-/* Copies the sticky device status word of a workspace to *bits (MD_STATUS_* bits).
+/* Library support (no passage of the paper: error reporting).
+ * Copies the sticky device status word of a workspace to *bits (MD_STATUS_* bits).
  * Synchronises `stream`. */
 md_status md_read_device_status(const void* d_ws, void* stream, uint32_t* bits);
 
-/* Diagnostic counters of the last call with MD_DIAG_COUNTERS on this workspace, all
+/* Measurement support. No passage defines the call; the counters measure the quantities
+ * of Section 5 (candidates against pairs that pass the cutoff, and the force stage's
+ * utilisation that Table 7 reports for the force PE).
+ * Diagnostic counters of the last call with MD_DIAG_COUNTERS on this workspace, all
  * per unique pair:
  *   [0] candidate pairs of the cell list (every pair of atoms in neighbouring cells,
  *       Algorithm 1), the work a filter that tests them all would do;
@@ -306,7 +315,9 @@ md_status md_read_device_status(const void* d_ws, void* stream, uint32_t* bits);
  * [4] are half of its per-atom counts. Synchronises `stream`. */
 md_status md_read_diag(const void* d_ws, void* stream, uint64_t counters[5]);
 
-/* The shader clock, in GHz, at which the compacted pair kernel of the last call on this
+/* Measurement support (no passage of the paper: the clock under load that scales the
+ * roofline peak).
+ * The shader clock, in GHz, at which the compacted pair kernel of the last call on this
  * workspace ran: each of its workgroups counts shader-clock cycles and ticks of the
  * constant 100 MHz counter over its run, and *ghz is the ratio of the two sums times
  * 0.1, i.e. the clock averaged over workgroup time. Scaling a peak rate quoted at the
@@ -316,7 +327,9 @@ md_status md_read_diag(const void* d_ws, void* stream, uint64_t counters[5]);
  * MD_ERR_HIP if the copy fails. Synchronises `stream`. */
 md_status md_read_clock(const void* d_ws, void* stream, double* ghz);
 
-/* Layout of the workspace, for inspection of intermediate results. Offsets are in
+/* Library support (no passage of the paper, though the arrays are those of Section 2.2's
+ * flat cell layout).
+ * Layout of the workspace, for inspection of intermediate results. Offsets are in
  * bytes from the workspace start.
  *   cell_start: int32 [n_cells+1], first sorted index of each cell
  *   perm:       int32 [n_atoms], original index of each sorted atom
@@ -343,7 +356,8 @@ typedef struct {
 md_status md_workspace_layout(const md_params* p, int64_t n_atoms, int double_precision,
                               md_layout* out);
 
-/* Static description of a status code. */
+/* Library support (no passage of the paper: error reporting). Static description of a
+ * status code. */
 const char* md_status_string(md_status s);
 
 #ifdef __cplusplus
