@@ -34,9 +34,9 @@ namespace md {
 namespace {
 
 constexpr int kEwTile = 64;       // atoms per LDS tile of the structure-factor kernel
-constexpr int kEwRows = 16;       // rows per structure-factor workgroup (one per wave)
-constexpr int kEwZ = 32;          // mz values held in registers by the force kernel
-constexpr int kEwForceRows = 16;  // rows of G staged in LDS at a time by the force kernel
+constexpr int kEwRows = 64;       // rows per structure-factor workgroup (4 tiles of 16)
+constexpr int kEwZ = 64;          // mz values per chunk of the force kernel (A operands in
+                                  // registers), and the padding of G's rows
 constexpr int kEwMaxK = 255;      // largest kmax per axis
 
 struct EwArgs {
@@ -140,54 +140,88 @@ __global__ __launch_bounds__(256) void k_ew_tables(EwArgs a) {
   a.tab[(int64_t)t * a.n + i] = ew_phase((uint32_t)m * ua);
 }
 
-// Structure factors: workgroup = kEwRows rows x 64 values of mz x one chunk of atoms.
+// Structure factors as a complex matrix product over atoms, on the matrix cores:
+// S[r][mz] = sum_j W[r][j] Z[j][mz], W = q X[mx(r)] Y[my(r)]. A workgroup takes 64 rows x
+// 64 values of mz x one chunk of atoms; wave w owns the 16 x 16 output tile (rows
+// 16 (w / 4) .., mz 16 (w % 4) ..). Per tile of 64 atoms the workgroup writes W (computed)
+// and Z (loaded) to LDS, atom-major and padded so that both the transposing stores and the
+// operand reads spread over the banks; each wave then runs 16 steps of 4 atoms, each step
+// four v_mfma_f32_16x16x4f32 (re re, -im im, re im, im re). In a 16x16x4 f32 product, lane
+// l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds D[4 (l / 16) + i][l % 16],
+// i = 0..3. The accumulation order is fixed, so the partial sums are the same bits on every
+// run.
+typedef float ew_v4f __attribute__((ext_vector_type(4)));
+
 __global__ __launch_bounds__(1024) void k_ew_sf(EwArgs a) {
-  __shared__ float2 sW[kEwRows][kEwTile];
-  __shared__ float2 sZ[kEwTile][65];   // padded: the transposing stores spread over banks
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t r = (int64_t)blockIdx.x * kEwRows + w;
+  __shared__ float2 sW[kEwTile][kEwRows + 1];   // [atom][row]
+  __shared__ float2 sZ[kEwTile][64 + 1];        // [atom][mz]
+  const int t = threadIdx.x;
+  const int w = t >> 6, lane = t & 63;
+  const int64_t r0 = (int64_t)blockIdx.x * kEwRows;
   const int z0 = blockIdx.z * 64;
   const int64_t a0 = (int64_t)blockIdx.y * a.chunk_atoms;
   const int64_t a1 = a0 + a.chunk_atoms < a.n ? a0 + a.chunk_atoms : a.n;
-  int mx = 0, my = 0;
-  if (r < a.rows) ew_row(a, r, mx, my);
-  const float2* X = a.tab + (int64_t)mx * a.n;
-  const float2* Y = a.tab + (int64_t)(a.kx + 1 + my + a.ky) * a.n;
+  // staging roles: atom ta = t % 64 of the tile; W for rows 4 (t / 64) .. + 3, Z for mz
+  // t / 64 + 16 p (p = 0..3)
+  const int ta = t & 63, tg = t >> 6;
+  int mxs[4], mys[4];
+  bool rok[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int64_t r = r0 + 4 * tg + k;
+    rok[k] = r < a.rows;
+    mxs[k] = 0;
+    mys[k] = 0;
+    if (rok[k]) ew_row(a, r, mxs[k], mys[k]);
+  }
   const float2* Z = a.tab + (int64_t)(a.kx + 2 * a.ky + 2) * a.n;
-  float sr = 0.f, si = 0.f;
+  // this wave's output tile and its operand columns
+  const int rt = w >> 2, zt = w & 3;
+  const int ar = 16 * rt + (lane & 15);   // A row (this lane's row of W)
+  const int bz = 16 * zt + (lane & 15);   // B column (this lane's mz)
+  const int kk = lane >> 4;               // this lane's atom within a step
+  ew_v4f dre = {0.f, 0.f, 0.f, 0.f}, dim = {0.f, 0.f, 0.f, 0.f};
   for (int64_t t0 = a0; t0 < a1; t0 += kEwTile) {
     {
-      // W = q X[mx] Y[my] of atom t0 + lane for this wave's row
-      const int64_t j = t0 + lane;
-      float2 wv = make_float2(0.f, 0.f);
-      if (j < a1 && r < a.rows) {
-        const float qj = __uint_as_float(a.ups[j].w);
-        const float2 x = X[j], y = Y[j];
-        wv = make_float2(qj * (x.x * y.x - x.y * y.y), qj * (x.x * y.y + x.y * y.x));
+      const int64_t j = t0 + ta;
+      const bool jok = j < a1;
+      const float qj = jok ? __uint_as_float(a.ups[j].w) : 0.f;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        float2 wv = make_float2(0.f, 0.f);
+        if (jok && rok[k]) {
+          const float2 x = a.tab[(int64_t)mxs[k] * a.n + j];
+          const float2 y = a.tab[(int64_t)(a.kx + 1 + mys[k] + a.ky) * a.n + j];
+          wv = make_float2(qj * (x.x * y.x - x.y * y.y), qj * (x.x * y.y + x.y * y.x));
+        }
+        sW[ta][4 * tg + k] = wv;
       }
-      sW[w][lane] = wv;
-    }
-    // Z of the tile's atoms for mz = z0 .. z0 + 63: thread (k, aa) loads rows k, k + 16, ..
-    for (int zz = w; zz < 64; zz += kEwRows) {
-      const int64_t j = t0 + lane;
-      const int zi = z0 + zz;
-      sZ[lane][zz] = (j < a1 && zi < a.nzc) ? Z[(int64_t)zi * a.n + j] : make_float2(0.f, 0.f);
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const int zz = tg + 16 * p, zi = z0 + zz;
+        sZ[ta][zz] = (jok && zi < a.nzc) ? Z[(int64_t)zi * a.n + j] : make_float2(0.f, 0.f);
+      }
     }
     __syncthreads();
-    const int na = (int)(a1 - t0 < kEwTile ? a1 - t0 : kEwTile);
-    for (int aa = 0; aa < na; ++aa) {
-      const float2 wv = sW[w][aa];
-      const float2 zv = sZ[aa][lane];
-      sr = fmaf(wv.x, zv.x, sr);
-      sr = fmaf(-wv.y, zv.y, sr);
-      si = fmaf(wv.x, zv.y, si);
-      si = fmaf(wv.y, zv.x, si);
+    // atoms past the chunk's end hold W = Z = 0, so every step can run in full
+#pragma unroll 4
+    for (int s = 0; s < kEwTile / 4; ++s) {
+      const float2 av = sW[4 * s + kk][ar];
+      const float2 bv = sZ[4 * s + kk][bz];
+      dre = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.x, dre, 0, 0, 0);
+      dre = __builtin_amdgcn_mfma_f32_16x16x4f32(-av.y, bv.y, dre, 0, 0, 0);
+      dim = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.y, dim, 0, 0, 0);
+      dim = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv.x, dim, 0, 0, 0);
     }
     __syncthreads();
   }
-  const int zi = z0 + lane;
-  if (r < a.rows && zi < a.nzc)
-    a.parts[((int64_t)blockIdx.y * a.rows + r) * a.nzc + zi] = make_float2(sr, si);
+  const int zi = z0 + bz;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t r = r0 + 16 * rt + 4 * kk + i;
+    if (r < a.rows && zi < a.nzc)
+      a.parts[((int64_t)blockIdx.y * a.rows + r) * a.nzc + zi] = make_float2(dre[i], dim[i]);
+  }
 }
 
 // Per wave vector: S from the chunks (fixed order, float64), the energy term and G.
@@ -230,66 +264,99 @@ __global__ __launch_bounds__(64) void k_ew_g(EwArgs a) {
   if (threadIdx.x == 0) a.erow[r * a.zblocks + blockIdx.y] = se[0];
 }
 
-// Forces: a thread per atom, kEwZ values of mz at a time in registers.
+// Forces as complex matrix products over mz, on the matrix cores: for atoms i and rows
+// (mx, my), T[i][r] = sum_mz Z[mz][i] G[r][mz] and U[i][r] = sum_mz mz Z[mz][i] G[r][mz];
+// then F_i = q_i sum_r (kx, ky) Im(xy T) + (0, 0, kz) Im(xy U) with xy = exp(i (kx x + ky
+// y)) from the exact phase of (mx, my). A workgroup of 4 waves takes 64 atoms, a wave 16 of
+// them (rows of A, Z of its atoms for 64 values of mz in registers) against tiles of 16
+// rows of G (columns of B) staged in LDS; each step of 4 values of mz runs eight
+// v_mfma_f32_16x16x4f32 (T and U, re and im parts). A lane then holds 4 atoms x 1 row of T
+// and U: it adds that row's force terms for its 4 atoms in float32 and each tile's sums into
+// float64; the 16 lanes of a row group finally add their sums in a fixed butterfly.
 __global__ __launch_bounds__(256) void k_ew_force(EwArgs a) {
-  __shared__ float2 sG[kEwForceRows][kEwZ];
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const bool live = i < a.n;
-  const uint4 u = live ? a.ups[i] : make_uint4(0, 0, 0, 0);
-  const float qi = __uint_as_float(u.w);
+  __shared__ float2 sG[16][kEwZ + 1];   // [row][mz] of the current tile and mz chunk
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const int kk = lane >> 4, col = lane & 15;
+  const int64_t ia = (int64_t)blockIdx.x * 64 + 16 * w + col;   // this lane's A row (atom)
+  const bool aok = ia < a.n;
+  // the 4 atoms of this lane's D rows: 16 w + 4 kk + i
+  uint32_t ux[4], uy[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t id = (int64_t)blockIdx.x * 64 + 16 * w + 4 * kk + i;
+    const uint4 u = id < a.n ? a.ups[id] : make_uint4(0, 0, 0, 0);
+    ux[i] = u.x;
+    uy[i] = u.y;
+  }
   const double pi = 3.141592653589793;
   const float kxs = (float)(2.0 * pi / a.L[0]), kys = (float)(2.0 * pi / a.L[1]),
               kzs = (float)(2.0 * pi / a.L[2]);
-  double F[3] = {0.0, 0.0, 0.0};
+  double F[4][3] = {};
+  const float2* Zt = a.tab + (int64_t)(a.kx + 2 * a.ky + 2) * a.n;
   for (int zc = 0; zc < a.nzc_pad; zc += kEwZ) {
-    float2 z[kEwZ];
-    const float2* Z = a.tab + (int64_t)(a.kx + 2 * a.ky + 2 + zc) * a.n;
+    // A operands for this mz chunk: step s holds Z[zc + 4 s + kk][ia]
+    float2 z[kEwZ / 4];
 #pragma unroll
-    for (int k = 0; k < kEwZ; ++k)
-      z[k] = (live && zc + k < a.nzc) ? Z[(int64_t)k * a.n + i] : make_float2(0.f, 0.f);
-    for (int64_t r0 = 0; r0 < a.rows; r0 += kEwForceRows) {
+    for (int s = 0; s < kEwZ / 4; ++s) {
+      const int zi = zc + 4 * s + kk;
+      z[s] = (aok && zi < a.nzc) ? Zt[(int64_t)zi * a.n + ia] : make_float2(0.f, 0.f);
+    }
+    for (int64_t r0 = 0; r0 < a.rows; r0 += 16) {
       __syncthreads();
-      for (int e = threadIdx.x; e < kEwForceRows * kEwZ; e += 256) {
+      for (int e = t; e < 16 * kEwZ; e += 256) {
         const int rr = e / kEwZ, k = e % kEwZ;
-        sG[rr][k] = (r0 + rr < a.rows) ? a.g[(r0 + rr) * a.nzc_pad + zc + k] : make_float2(0.f, 0.f);
+        sG[rr][k] = r0 + rr < a.rows ? a.g[(r0 + rr) * a.nzc_pad + zc + k] : make_float2(0.f, 0.f);
       }
       __syncthreads();
-      float fx = 0.f, fy = 0.f, fz = 0.f;
-      const int nr = (int)(a.rows - r0 < kEwForceRows ? a.rows - r0 : kEwForceRows);
-      for (int rr = 0; rr < nr; ++rr) {
-        int mx, my;
-        ew_row(a, r0 + rr, mx, my);
-        // U = sum G Z, V = sum mz G Z over this chunk of mz
-        float ur = 0.f, ui = 0.f, vr = 0.f, vi = 0.f;
+      ew_v4f tre = {0.f, 0.f, 0.f, 0.f}, tim = tre, ure = tre, uim = tre;
 #pragma unroll
-        for (int k = 0; k < kEwZ; ++k) {
-          const float2 gv = sG[rr][k];
-          const float pr = fmaf(gv.x, z[k].x, -gv.y * z[k].y);
-          const float pim = fmaf(gv.x, z[k].y, gv.y * z[k].x);
-          const float mz = (float)(zc + k - a.kz);
-          ur += pr;
-          ui += pim;
-          vr = fmaf(mz, pr, vr);
-          vi = fmaf(mz, pim, vi);
-        }
-        // exp(i (kx x + ky y)) from the exact phase of (mx, my)
-        const float2 xy = ew_phase((uint32_t)mx * u.x + (uint32_t)my * u.y);
-        const float imu = fmaf(xy.x, ui, xy.y * ur);    // Im(xy U)
-        const float imv = fmaf(xy.x, vi, xy.y * vr);    // Im(xy V)
-        fx = fmaf((float)mx * kxs, imu, fx);
-        fy = fmaf((float)my * kys, imu, fy);
-        fz = fmaf(kzs, imv, fz);
+      for (int s = 0; s < kEwZ / 4; ++s) {
+        const float2 g = sG[col][4 * s + kk];
+        const float mz = (float)(zc + 4 * s + kk - a.kz);
+        const float2 gm = make_float2(mz * g.x, mz * g.y);
+        tre = __builtin_amdgcn_mfma_f32_16x16x4f32(z[s].x, g.x, tre, 0, 0, 0);
+        tre = __builtin_amdgcn_mfma_f32_16x16x4f32(-z[s].y, g.y, tre, 0, 0, 0);
+        tim = __builtin_amdgcn_mfma_f32_16x16x4f32(z[s].x, g.y, tim, 0, 0, 0);
+        tim = __builtin_amdgcn_mfma_f32_16x16x4f32(z[s].y, g.x, tim, 0, 0, 0);
+        ure = __builtin_amdgcn_mfma_f32_16x16x4f32(z[s].x, gm.x, ure, 0, 0, 0);
+        ure = __builtin_amdgcn_mfma_f32_16x16x4f32(-z[s].y, gm.y, ure, 0, 0, 0);
+        uim = __builtin_amdgcn_mfma_f32_16x16x4f32(z[s].x, gm.y, uim, 0, 0, 0);
+        uim = __builtin_amdgcn_mfma_f32_16x16x4f32(z[s].y, gm.x, uim, 0, 0, 0);
       }
-      F[0] += (double)fx;
-      F[1] += (double)fy;
-      F[2] += (double)fz;
+      // this lane's row r0 + col against its 4 atoms (rows past the end hold T = U = 0)
+      const int64_t r = r0 + col;
+      int mx = 0, my = 0;
+      if (r < a.rows) ew_row(a, r, mx, my);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float2 xy = ew_phase((uint32_t)mx * ux[i] + (uint32_t)my * uy[i]);
+        const float imt = fmaf(xy.x, tim[i], xy.y * tre[i]);   // Im(xy T)
+        const float imu = fmaf(xy.x, uim[i], xy.y * ure[i]);   // Im(xy U)
+        F[i][0] += (double)((float)mx * kxs * imt);
+        F[i][1] += (double)((float)my * kys * imt);
+        F[i][2] += (double)(kzs * imu);
+      }
     }
   }
-  if (!live) return;
-  float* out = a.force + 3 * i;
-  for (int d = 0; d < 3; ++d) {
-    const float v = (float)((double)qi * F[d]);
-    out[d] = a.accumulate ? out[d] + v : v;
+  // sum over the 16 lanes of each row group (fixed butterfly), then lane 16 kk + 0 writes
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int sft = 1; sft < 16; sft <<= 1) F[i][d] += __shfl_xor(F[i][d], sft);
+  if (col == 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t id = (int64_t)blockIdx.x * 64 + 16 * w + 4 * kk + i;
+      if (id >= a.n) continue;
+      const float qi = __uint_as_float(a.ups[id].w);
+      float* out = a.force + 3 * id;
+      for (int d = 0; d < 3; ++d) {
+        const float v = (float)((double)qi * F[i][d]);
+        out[d] = a.accumulate ? out[d] + v : v;
+      }
+    }
   }
 }
 
@@ -353,7 +420,7 @@ md_status ew_plan(const md_params* p, int64_t n, const int32_t kmax[3], EwPlan* 
   // atom chunks: enough workgroups to fill the chip, chunks of whole tiles
   const int64_t rb = (pl->rows + kEwRows - 1) / kEwRows;
   const int64_t tiles = (n + kEwTile - 1) / kEwTile > 0 ? (n + kEwTile - 1) / kEwTile : 1;
-  int64_t chunks = (2048 + rb * pl->zblocks - 1) / (rb * pl->zblocks);
+  int64_t chunks = (512 + rb * pl->zblocks - 1) / (rb * pl->zblocks);   // two per compute unit
   chunks = chunks < 1 ? 1 : chunks > tiles ? tiles : chunks;
   pl->chunk_atoms = (tiles + chunks - 1) / chunks * kEwTile;
   pl->chunks = n > 0 ? (n + pl->chunk_atoms - 1) / pl->chunk_atoms : 1;
@@ -433,7 +500,7 @@ md_status md_ewald_recip_f32(const md_params* p, int64_t n_atoms, const float* d
                             (unsigned)pl.chunks, (unsigned)pl.zblocks),
                        dim3(1024), 0, st, a);
     hipLaunchKernelGGL(md::k_ew_g, dim3((unsigned)pl.rows, (unsigned)pl.zblocks), dim3(64), 0, st, a);
-    hipLaunchKernelGGL(md::k_ew_force, dim3(nb), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(md::k_ew_force, dim3((unsigned)((n_atoms + 63) / 64)), dim3(256), 0, st, a);
   } else {
     // no atoms: every term is zero
     a.qblocks = 0;
