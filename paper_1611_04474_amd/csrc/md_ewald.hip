@@ -152,7 +152,7 @@ __global__ __launch_bounds__(256) void k_ew_tables(EwArgs a) {
 // run.
 typedef float ew_v4f __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(1024) void k_ew_sf(EwArgs a) {
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_ew_sf(EwArgs a) {
   __shared__ float2 sW[kEwTile][kEwRows + 1];   // [atom][row]
   __shared__ float2 sZ[kEwTile][64 + 1];        // [atom][mz]
   const int t = threadIdx.x;
@@ -181,28 +181,36 @@ __global__ __launch_bounds__(1024) void k_ew_sf(EwArgs a) {
   const int bz = 16 * zt + (lane & 15);   // B column (this lane's mz)
   const int kk = lane >> 4;               // this lane's atom within a step
   ew_v4f dre = {0.f, 0.f, 0.f, 0.f}, dim = {0.f, 0.f, 0.f, 0.f};
-  for (int64_t t0 = a0; t0 < a1; t0 += kEwTile) {
-    {
-      const int64_t j = t0 + ta;
-      const bool jok = j < a1;
-      const float qj = jok ? __uint_as_float(a.ups[j].w) : 0.f;
+  // this thread's staging values of one tile, loaded a tile ahead of their use
+  float2 wn[4], zn[4];
+  auto load_tile = [&](int64_t t0) __attribute__((always_inline)) {
+    const int64_t j = t0 + ta;
+    const bool jok = j < a1;
+    const float qj = jok ? __uint_as_float(a.ups[j].w) : 0.f;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        float2 wv = make_float2(0.f, 0.f);
-        if (jok && rok[k]) {
-          const float2 x = a.tab[(int64_t)mxs[k] * a.n + j];
-          const float2 y = a.tab[(int64_t)(a.kx + 1 + mys[k] + a.ky) * a.n + j];
-          wv = make_float2(qj * (x.x * y.x - x.y * y.y), qj * (x.x * y.y + x.y * y.x));
-        }
-        sW[ta][4 * tg + k] = wv;
+    for (int k = 0; k < 4; ++k) {
+      float2 wv = make_float2(0.f, 0.f);
+      if (jok && rok[k]) {
+        const float2 x = a.tab[(int64_t)mxs[k] * a.n + j];
+        const float2 y = a.tab[(int64_t)(a.kx + 1 + mys[k] + a.ky) * a.n + j];
+        wv = make_float2(qj * (x.x * y.x - x.y * y.y), qj * (x.x * y.y + x.y * y.x));
       }
-#pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        const int zz = tg + 16 * p, zi = z0 + zz;
-        sZ[ta][zz] = (jok && zi < a.nzc) ? Z[(int64_t)zi * a.n + j] : make_float2(0.f, 0.f);
-      }
+      wn[k] = wv;
     }
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const int zi = z0 + tg + 16 * p;
+      zn[p] = (jok && zi < a.nzc) ? Z[(int64_t)zi * a.n + j] : make_float2(0.f, 0.f);
+    }
+  };
+  if (a0 < a1) load_tile(a0);
+  for (int64_t t0 = a0; t0 < a1; t0 += kEwTile) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sW[ta][4 * tg + k] = wn[k];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) sZ[ta][tg + 16 * p] = zn[p];
     __syncthreads();
+    if (t0 + kEwTile < a1) load_tile(t0 + kEwTile);
     // atoms past the chunk's end hold W = Z = 0, so every step can run in full
 #pragma unroll 4
     for (int s = 0; s < kEwTile / 4; ++s) {
@@ -294,7 +302,9 @@ __global__ __launch_bounds__(256) void k_ew_force(EwArgs a) {
   double F[4][3] = {};
   const float2* Zt = a.tab + (int64_t)(a.kx + 2 * a.ky + 2) * a.n;
   for (int zc = 0; zc < a.nzc_pad; zc += kEwZ) {
-    // A operands for this mz chunk: step s holds Z[zc + 4 s + kk][ia]
+    // A operands for this mz chunk: step s holds Z[zc + 4 s + kk][ia]; ns steps cover the
+    // chunk's mz values below nzc
+    const int ns = (min(kEwZ, a.nzc - zc) + 3) / 4;
     float2 z[kEwZ / 4];
 #pragma unroll
     for (int s = 0; s < kEwZ / 4; ++s) {
@@ -311,17 +321,19 @@ __global__ __launch_bounds__(256) void k_ew_force(EwArgs a) {
       ew_v4f tre = {0.f, 0.f, 0.f, 0.f}, tim = tre, ure = tre, uim = tre;
 #pragma unroll
       for (int s = 0; s < kEwZ / 4; ++s) {
-        const float2 g = sG[col][4 * s + kk];
-        const float mz = (float)(zc + 4 * s + kk - a.kz);
-        const float2 gm = make_float2(mz * g.x, mz * g.y);
-        tre = __builtin_amdgcn_mfma_f32_16x16x4f32(z[s].x, g.x, tre, 0, 0, 0);
-        tre = __builtin_amdgcn_mfma_f32_16x16x4f32(-z[s].y, g.y, tre, 0, 0, 0);
-        tim = __builtin_amdgcn_mfma_f32_16x16x4f32(z[s].x, g.y, tim, 0, 0, 0);
-        tim = __builtin_amdgcn_mfma_f32_16x16x4f32(z[s].y, g.x, tim, 0, 0, 0);
-        ure = __builtin_amdgcn_mfma_f32_16x16x4f32(z[s].x, gm.x, ure, 0, 0, 0);
-        ure = __builtin_amdgcn_mfma_f32_16x16x4f32(-z[s].y, gm.y, ure, 0, 0, 0);
-        uim = __builtin_amdgcn_mfma_f32_16x16x4f32(z[s].x, gm.y, uim, 0, 0, 0);
-        uim = __builtin_amdgcn_mfma_f32_16x16x4f32(z[s].y, gm.x, uim, 0, 0, 0);
+        if (s < ns) {   // steps past the chunk's last mz are skipped (uniform)
+          const float2 g = sG[col][4 * s + kk];
+          const float mz = (float)(zc + 4 * s + kk - a.kz);
+          const float2 gm = make_float2(mz * g.x, mz * g.y);
+          tre = __builtin_amdgcn_mfma_f32_16x16x4f32(z[s].x, g.x, tre, 0, 0, 0);
+          tre = __builtin_amdgcn_mfma_f32_16x16x4f32(-z[s].y, g.y, tre, 0, 0, 0);
+          tim = __builtin_amdgcn_mfma_f32_16x16x4f32(z[s].x, g.y, tim, 0, 0, 0);
+          tim = __builtin_amdgcn_mfma_f32_16x16x4f32(z[s].y, g.x, tim, 0, 0, 0);
+          ure = __builtin_amdgcn_mfma_f32_16x16x4f32(z[s].x, gm.x, ure, 0, 0, 0);
+          ure = __builtin_amdgcn_mfma_f32_16x16x4f32(-z[s].y, gm.y, ure, 0, 0, 0);
+          uim = __builtin_amdgcn_mfma_f32_16x16x4f32(z[s].x, gm.y, uim, 0, 0, 0);
+          uim = __builtin_amdgcn_mfma_f32_16x16x4f32(z[s].y, gm.x, uim, 0, 0, 0);
+        }
       }
       // this lane's row r0 + col against its 4 atoms (rows past the end hold T = U = 0)
       const int64_t r = r0 + col;
