@@ -71,7 +71,10 @@ def test_real_space_term(gpu, flags, double):
 
 @pytest.mark.parametrize("box,n,seed,net", [((30.0, 30.0, 30.0), 3000, 1, 0.0),
                                             ((40.0, 43.0, 47.0), 8000, 3, 0.0),
-                                            ((26.0, 31.0, 29.0), 2000, 5, 2.5)])
+                                            ((26.0, 31.0, 29.0), 2000, 5, 2.5),
+                                            # 87 values of mz: two mz chunks of the force
+                                            # kernel and two mz blocks of the structure factors
+                                            ((26.0, 27.0, 120.0), 2000, 6, 0.0)])
 def test_reciprocal_sum(gpu, box, n, seed, net):
     """Reciprocal forces and energy against the oracle's plain sum over wave vectors, on a
     cube, a non-cubic box (its axes' wave numbers differ) and a system with net charge."""
