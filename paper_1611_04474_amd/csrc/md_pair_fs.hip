@@ -238,8 +238,8 @@ __device__ inline long long round_prod_2m24(double a, float b) {
 }
 
 // Two-word fixed point of the float64 path: v = hi 2^-20 + lo 2^-72 with hi = round(v 2^20)
-// and lo = round((v 2^20 - hi) 2^52), for |v| < 2^31. Both roundings go through the
-// 1.5 * 2^52 add of round_to_i64; v 2^20 - hi is exact (Sterbenz, or hi = 0), so the pair
+// and lo = round((v 2^20 - hi) 2^52), for |v| < 2^31. Both roundings are adds of
+// 1.5 * 2^52, as in round_to_i64; v 2^20 - hi is exact (Sterbenz, or hi = 0), so the pair
 // holds v exactly whenever |v| >= 2^-20, and to 2^-73 otherwise.
 struct Fix2 {
   long long hi, lo;
