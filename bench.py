@@ -34,7 +34,9 @@ PEAK_FP32_TFLOPS = 157.3       # MI355X published float32 vector peak
 CLOCK_NOMINAL_GHZ = 2.4        # the clock that peak is quoted at
 FLOP_PER_CANDIDATE = 8         # filter: 3 sub, 1 mul, 2 fma (fma = 2)
 FLOP_PER_PAIR = 40             # force, switch, accumulation
-BIN_BYTES_PER_ATOM = 20 + 24 + 24
+# binning: x, y, z, q and type in; sorted (x, y, z, q), type and permutation out; the per-atom
+# sums cleared; the pair kernel's prefilter constants out
+BIN_BYTES_PER_ATOM = 20 + 24 + 24 + 32
 METRIC = "within-cutoff pair-interactions/s @92k atoms; p50/p99 latency mixed batch"
 # HBM bytes per launch of the pair kernel at 92,224 atoms, from the FETCH_SIZE and
 # WRITE_SIZE counters scaled by a copy of known size (profiles/traffic_pair_fs_92k.md);
