@@ -141,7 +141,7 @@ md_status make_plan(const md_params* p, int64_t n, int real_bytes, Plan* pl) {
     pl->bin_chunk = chunk;
     pl->bin_blocks = (int)((n + chunk - 1) / chunk);
   }
-  pl->off_bhist = o;     o = align_up(o + sizeof(int32_t) * (size_t)pl->bin_blocks * cells);
+  pl->off_bhist = o;     o = align_up(o + sizeof(int32_t) * (size_t)pl->bin_blocks * (cells + 1));
   pl->off_bstat = o;     o = align_up(o + sizeof(uint32_t) * (size_t)(pl->bin_blocks + 1));
   pl->off_order = o;     o = align_up(o + sizeof(int32_t) * cells);
   pl->off_cost = o;      o = align_up(o + sizeof(uint32_t) * cells);

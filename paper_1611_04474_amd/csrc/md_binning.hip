@@ -11,11 +11,10 @@
 //                    return value is the atom's slot among the block's atoms of that cell);
 //                    the histogram and the block's status bits go to the workspace, so no
 //                    global atomics are needed;
-// then, for grids of at most 1024 cells,
-//   k_scatter_fused  every block derives the cells' starts and its own offset within each
-//                    cell from the histograms and scatters its atoms; block 0 also writes
-//                    cell_start, the launch order, the mixed Lennard-Jones table
-//                    (Lorentz-Berthelot) and the status word;
+// then, for grids of at most 1024 cells, the same block also scans its histogram into the
+//                    block's start of each cell and writes its atoms in cell order within
+//                    its own range of the arrays (so binning is two kernels: this one and
+//                    k_cell_sort, which gathers each cell's atoms from the blocks' ranges);
 // and for larger grids
 //   k_bin_colscan    per cell, the blocks' exclusive offsets and the total (64 cells per
 //                    workgroup);
@@ -29,10 +28,14 @@
 //                    in a reproducible order, and each half of a row of cells along x is
 //                    sorted in x, which lets the pair kernel bound the candidates of a group
 //                    of home atoms by an x-window per half-row -- writes the sorted arrays
-//                    and the number of atoms in the lower z half.
-// The scatter puts atoms in arbitrary order within a cell's range (the LDS atomics' order);
-// the launch order puts the cells longest first (atom counts, or the last pair kernel's
-// measured times on small grids), so that the last workgroups to run are short ones.
+//                    and the number of atoms in the lower z half. On grids of at most 1024
+//                    cells its workgroups first gather the cell's atoms (their start is the
+//                    sum of the blocks' starts of the cell), and one more workgroup, the
+//                    first, writes the launch order, the mixed Lennard-Jones table
+//                    (Lorentz-Berthelot) and the status word.
+// Within a cell's range the atoms come in arbitrary order (the LDS atomics' order) until the
+// in-cell sort; the launch order puts the cells longest first (atom counts, or the last pair
+// kernel's measured times on small grids), so that the last workgroups to run are short ones.
 #include "md_common.hpp"
 
 namespace md {
@@ -80,6 +83,81 @@ __device__ inline int cell_of(const SysArgs<Real>& a, int64_t i, uint32_t& st) {
                    a.type_in[i], st);
 }
 
+// Exclusive prefix sum of one value per thread over a workgroup of kWaves waves: a scan
+// within each wave, then the wave totals through LDS (s_tot holds kWaves values). *total
+// gets the sum of all.
+template <int kWaves>
+__device__ inline int32_t block_scan_excl_w(int32_t v, int32_t* s_tot, int32_t* total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int32_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) s_tot[w] = x;
+  __syncthreads();
+  int32_t before = 0, all = 0;
+#pragma unroll
+  for (int k = 0; k < kWaves; ++k) {
+    const int32_t tk = s_tot[k];
+    before += k < w ? tk : 0;
+    all += tk;
+  }
+  __syncthreads();   // s_tot may be reused after this
+  *total = all;
+  return before + x - v;
+}
+
+// The same over a 1024-thread workgroup.
+__device__ inline int32_t block_scan_excl(int32_t v, int32_t* s_tot, int32_t* total) {
+  return block_scan_excl_w<16>(v, s_tot, total);
+}
+
+// Grids of at most kScanFused cells binned with per-block histograms skip the scan
+// kernels: each histogram block scans its own counts and writes its atoms in cell order
+// within its range, and the in-cell sort gathers every cell from the blocks' ranges.
+// Larger grids go through k_bin_colscan, k_bin_scan and k_scatter.
+constexpr int kScanFused = 1024;
+
+template <typename Real>
+__host__ __device__ inline bool scan_fused(const SysArgs<Real>& a) {
+  return a.bin_blocks > 0 && a.n_cells <= kScanFused;
+}
+
+// z half of an atom in its cell: 1 if 2 z n_z / L_z reaches the cell's middle.
+template <typename Real>
+__device__ inline int z_half(const SysArgs<Real>& a, Real z, int cz) {
+  return (int)(z * a.inv_w[2] * Real(2)) >= 2 * cz + 1 ? 1 : 0;
+}
+
+// Sort key of atom i of cell cz (z index) with wrapped x and z: (z half, x as float32
+// bits, original index) in bits 63, 62..31 and 30..0. Wrapped x is >= +0, where the bits
+// of a float order as its value (31 bits: the sign bit is 0).
+template <typename Real>
+__device__ inline unsigned long long sort_key(const SysArgs<Real>& a, int32_t i, float x, Real z,
+                                              int cz) {
+  return ((unsigned long long)z_half(a, z, cz) << 63) |
+         ((unsigned long long)__builtin_bit_cast(uint32_t, x + 0.f) << 31) | (uint32_t)i;
+}
+
+// Atom i (of cell c) goes to slot `slot` of the cell-major arrays that precede the in-cell
+// sort: its sort key and type as one 16-byte record, and its wrapped (x, y, z, q).
+template <typename Real>
+__device__ inline void put_atom(const SysArgs<Real>& a, int64_t i, int c, int32_t slot, Real x,
+                                Real y, Real z, Real q, int t) {
+  const int cz = (int)(c / ((int64_t)a.nx * a.ny));
+  uint32_t st = 0;
+  P4<Real> p;
+  p.x = wrap_coord(x, a.L[0], st);
+  p.y = wrap_coord(y, a.L[1], st);
+  p.z = wrap_coord(z, a.L[2], st);
+  p.w = q;
+  if (t < 0 || t >= a.n_types) t = 0;
+  a.ukey[slot] = UKey{sort_key(a, (int32_t)i, (float)p.x, p.z, cz), t, 0};
+  a.upos[slot] = p;
+}
+
 // Clears the per-atom accumulators that the pair kernels add into.
 template <typename Real>
 __device__ inline void clear_atom(const SysArgs<Real>& a, int64_t i) {
@@ -100,19 +178,30 @@ __device__ inline void clear_atom(const SysArgs<Real>& a, int64_t i) {
 // kBinThreads kHistPer atoms).
 constexpr int kHistPer = kBinChunkUnit / kBinThreads;
 
+// Grids of at most kScanFused cells (scan_fused): after counting, the block scans its
+// counts into its start of each cell, bhist[blk][0 .. n_cells] (row n_cells + 1 long, the
+// last entry the block's atom count), and writes each of its atoms with its sort key to
+// position blk bin_chunk + (block's start of its cell) + (its slot in the cell) of the
+// unsorted arrays. A block of one round keeps its atoms in registers meanwhile; longer
+// blocks store each atom's cell and slot and read them back. The per-atom sums are cleared
+// by the in-cell sort then. Larger grids: the histogram goes to bhist[blk][0 .. n_cells - 1]
+// and the cell and slot of each atom to cell[] and rank[].
 template <typename Real>
 __device__ inline void bin_hist(const SysArgs<Real>& a, int64_t blk) {
   extern __shared__ int32_t s_h[];   // [n_cells] counts, then the status bits
+  __shared__ int32_t s_tot[kBinThreads / 64];
   const int nc = (int)a.n_cells;
   const int tid = threadIdx.x;
+  const bool local = scan_fused(a);
+  const bool regs = local && a.bin_chunk == (int64_t)kBinThreads * kHistPer;
   for (int c = tid; c <= nc; c += kBinThreads) s_h[c] = 0;
   __syncthreads();
   const int64_t i0 = blk * a.bin_chunk;
   const int64_t i1 = i0 + a.bin_chunk < a.n ? i0 + a.bin_chunk : a.n;
   uint32_t st = 0;
+  Real x[kHistPer], y[kHistPer], z[kHistPer], q[kHistPer];
+  int ty[kHistPer], c[kHistPer], rk[kHistPer];
   for (int64_t r0 = i0; r0 < i1; r0 += kBinThreads * kHistPer) {
-    Real x[kHistPer], y[kHistPer], z[kHistPer];
-    int ty[kHistPer], c[kHistPer];
 #pragma unroll
     for (int u = 0; u < kHistPer; ++u) {
       // past the end: a repeat of the block's last atom, whose cell and status bits are
@@ -123,6 +212,7 @@ __device__ inline void bin_hist(const SysArgs<Real>& a, int64_t blk) {
       y[u] = a.pos_in[3 * i + 1];
       z[u] = a.pos_in[3 * i + 2];
       ty[u] = a.type_in[i];
+      if (regs) q[u] = a.q_in[i];
     }
 #pragma unroll
     for (int u = 0; u < kHistPer; ++u) c[u] = cell_from(a, x[u], y[u], z[u], ty[u], st);
@@ -130,17 +220,57 @@ __device__ inline void bin_hist(const SysArgs<Real>& a, int64_t blk) {
     for (int u = 0; u < kHistPer; ++u) {
       const int64_t i = r0 + u * kBinThreads + tid;
       if (i < i1) {
-        a.cell[i] = c[u];
-        a.rank[i] = atomicAdd(&s_h[c[u]], 1);
-        clear_atom(a, i);
+        rk[u] = atomicAdd(&s_h[c[u]], 1);
+        if (!regs) {
+          a.cell[i] = c[u];
+          a.rank[i] = rk[u];
+        }
+        if (!local) clear_atom(a, i);
       }
     }
   }
   if (st) atomicOr(reinterpret_cast<uint32_t*>(&s_h[nc]), st);
   __syncthreads();
-  int32_t* hb = a.bhist + blk * nc;
-  for (int c = tid; c < nc; c += kBinThreads) hb[c] = s_h[c];
-  if (tid == 0) a.bstat[blk] = (uint32_t)s_h[nc];
+  if (!local) {
+    int32_t* hb = a.bhist + blk * nc;
+    for (int cc = tid; cc < nc; cc += kBinThreads) hb[cc] = s_h[cc];
+    if (tid == 0) a.bstat[blk] = (uint32_t)s_h[nc];
+    return;
+  }
+  // the block's start of each cell: cells 2 tid and 2 tid + 1 per thread (nc <= 1024)
+  static_assert(kScanFused <= 2 * kBinThreads, "two cells per thread");
+  const uint32_t stb = (uint32_t)s_h[nc];
+  const int c0 = 2 * tid;
+  const int32_t v0 = c0 < nc ? s_h[c0] : 0, v1 = c0 + 1 < nc ? s_h[c0 + 1] : 0;
+  int32_t all;
+  const int32_t ex = block_scan_excl_w<kBinThreads / 64>(v0 + v1, s_tot, &all);
+  int32_t* lrow = a.bhist + blk * (int64_t)(nc + 1);
+  if (c0 < nc) {
+    s_h[c0] = ex;
+    lrow[c0] = ex;
+  }
+  if (c0 + 1 < nc) {
+    s_h[c0 + 1] = ex + v0;
+    lrow[c0 + 1] = ex + v0;
+  }
+  if (tid == 0) {
+    lrow[nc] = all;
+    a.bstat[blk] = stb;
+  }
+  __syncthreads();
+  if (regs) {
+#pragma unroll
+    for (int u = 0; u < kHistPer; ++u) {
+      const int64_t i = i0 + u * kBinThreads + tid;
+      if (i < i1) put_atom(a, i, c[u], (int32_t)(i0 + s_h[c[u]] + rk[u]), x[u], y[u], z[u], q[u], ty[u]);
+    }
+    return;
+  }
+  for (int64_t i = i0 + tid; i < i1; i += kBinThreads) {
+    const int ci = a.cell[i];
+    put_atom(a, i, ci, (int32_t)(i0 + s_h[ci] + a.rank[i]), a.pos_in[3 * i + 0],
+             a.pos_in[3 * i + 1], a.pos_in[3 * i + 2], a.q_in[i], a.type_in[i]);
+  }
 }
 
 template <typename Real>
@@ -176,40 +306,6 @@ __global__ void k_bin_count(SysArgs<Real> a) {
   a.cell[i] = c;
   a.rank[i] = atomicAdd(&a.count[c], 1);
   if (st) atomicOr(&a.hdr->status, st);
-}
-
-// Exclusive prefix sum of one value per thread over a 1024-thread workgroup: a scan
-// within each wave, then the 16 wave totals through LDS. *total gets the sum of all.
-__device__ inline int32_t block_scan_excl(int32_t v, int32_t* s_tot, int32_t* total) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  int32_t x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int32_t y = __shfl_up(x, o);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) s_tot[w] = x;
-  __syncthreads();
-  int32_t before = 0, all = 0;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int32_t tk = s_tot[k];
-    before += k < w ? tk : 0;
-    all += tk;
-  }
-  __syncthreads();   // s_tot may be reused after this
-  *total = all;
-  return before + x - v;
-}
-
-// Grids of at most kScanFused cells binned with per-block histograms skip the scan
-// kernels: every block of k_scatter_fused scans the histograms itself (one thread per
-// cell). Larger grids go through k_bin_colscan, k_bin_scan and k_scatter.
-constexpr int kScanFused = 1024;
-
-template <typename Real>
-__host__ __device__ inline bool scan_fused(const SysArgs<Real>& a) {
-  return a.bin_blocks > 0 && a.n_cells <= kScanFused;
 }
 
 // Workgroups of k_bin_colscan for one system (0 when the scatter does the scan).
@@ -286,11 +382,11 @@ __device__ inline bool have_costs(const SysArgs<Real>& a) {
 __device__ inline uint32_t cost_key(uint32_t ticks) { return ticks >> 4; }
 
 // The cells' launch order for the pair kernel, the mixed LJ table and (own_header) the
-// status word: the end of the scan, by one workgroup of 1024 threads. key(c) is cell c's
-// expected cost: its atom count, or (grids of at most kScanFused cells) its time in the
-// last pair kernel when known; st_lane (threads 0 .. 63) carries the histogram blocks'
-// status bits from block_status.
-template <typename Real, typename Key>
+// status word: the end of the scan, by one workgroup of kThreads threads (s_tot holds
+// kThreads / 64 values). key(c) is cell c's expected cost: its atom count, or (grids of at
+// most kScanFused cells) its time in the last pair kernel when known; st_lane (threads
+// 0 .. 63) carries the histogram blocks' status bits from block_status.
+template <int kThreads, typename Real, typename Key>
 __device__ inline void scan_tail(const SysArgs<Real>& a, const TypeTable& tt, int own_header,
                                  int32_t* s_tot, Key key, uint32_t st_lane) {
   const int t = threadIdx.x;
@@ -299,27 +395,38 @@ __device__ inline void scan_tail(const SysArgs<Real>& a, const TypeTable& tt, in
   // order within a bin is arbitrary, which only changes which compute unit takes a cell,
   // never a result. Longest first lets the short cells fill the tail.
   constexpr int kOrderBins = 1024;
+  constexpr int kPerT = kOrderBins / kThreads;   // bins per thread, consecutive
   __shared__ int32_t s_bin[kOrderBins];
-  s_bin[t] = 0;
+#pragma unroll
+  for (int k = 0; k < kPerT; ++k) s_bin[kPerT * t + k] = 0;
   __syncthreads();
   auto bin = [&](int64_t c) {
     const uint32_t v = key(c);
     return kOrderBins - 1 - (int)(v < kOrderBins - 1 ? v : kOrderBins - 1);
   };
-  for (int64_t c = t; c < nc; c += 1024) atomicAdd(&s_bin[bin(c)], 1);
+  for (int64_t c = t; c < nc; c += kThreads) atomicAdd(&s_bin[bin(c)], 1);
   __syncthreads();
   {
-    int32_t all;
-    const int32_t excl = block_scan_excl(s_bin[t], s_tot, &all);
-    s_bin[t] = excl;   // each thread rewrites only its own bin, read above
+    int32_t v[kPerT], sum = 0, all;
+#pragma unroll
+    for (int k = 0; k < kPerT; ++k) {
+      v[k] = s_bin[kPerT * t + k];
+      sum += v[k];
+    }
+    int32_t excl = block_scan_excl_w<kThreads / 64>(sum, s_tot, &all);
+#pragma unroll
+    for (int k = 0; k < kPerT; ++k) {
+      s_bin[kPerT * t + k] = excl;   // each thread rewrites only its own bins, read above
+      excl += v[k];
+    }
     __syncthreads();
   }
-  for (int64_t c = t; c < nc; c += 1024) {
+  for (int64_t c = t; c < nc; c += kThreads) {
     const int32_t pos = atomicAdd(&s_bin[bin(c)], 1);
     a.order[pos] = (int32_t)c;
   }
   const int nt = a.n_types;
-  for (int e = t; e < nt * nt; e += 1024) {
+  for (int e = t; e < nt * nt; e += kThreads) {
     const int ti = e / nt, tj = e % nt;
     const double sg = 0.5 * (tt.sigma[ti] + tt.sigma[tj]);
     const double ep = sqrt(tt.eps[ti] * tt.eps[tj]);
@@ -414,7 +521,7 @@ __device__ inline void bin_scan(const SysArgs<Real>& a, const TypeTable& tt, int
   if (t == 0) a.start[nc] = carry;
   // launch order by atom count: with more than 1024 cells there are several workgroups
   // per compute unit, and the short cells already fill the tail
-  scan_tail(a, tt, own_header, s_tot, [&](int64_t c) { return (uint32_t)count(c); },
+  scan_tail<1024>(a, tt, own_header, s_tot, [&](int64_t c) { return (uint32_t)count(c); },
             st_blocks.bits());
 }
 
@@ -428,39 +535,6 @@ __global__ __launch_bounds__(1024) void k_bin_scan_batch(Batch<float> b, TypeTab
   int64_t blk;
   const int s = b.pick(blockIdx.x, blk);
   bin_scan(b.sys[s], tt, 1);
-}
-
-// z half of an atom in its cell: 1 if 2 z n_z / L_z reaches the cell's middle.
-template <typename Real>
-__device__ inline int z_half(const SysArgs<Real>& a, Real z, int cz) {
-  return (int)(z * a.inv_w[2] * Real(2)) >= 2 * cz + 1 ? 1 : 0;
-}
-
-// Sort key of atom i of cell cz (z index) with wrapped x and z: (z half, x as float32
-// bits, original index) in bits 63, 62..31 and 30..0. Wrapped x is >= +0, where the bits
-// of a float order as its value (31 bits: the sign bit is 0).
-template <typename Real>
-__device__ inline unsigned long long sort_key(const SysArgs<Real>& a, int32_t i, float x, Real z,
-                                              int cz) {
-  return ((unsigned long long)z_half(a, z, cz) << 63) |
-         ((unsigned long long)__builtin_bit_cast(uint32_t, x + 0.f) << 31) | (uint32_t)i;
-}
-
-// Atom i (of cell c) goes to slot `slot` of the cell-major arrays that precede the in-cell
-// sort: its sort key and type as one 16-byte record, and its wrapped (x, y, z, q).
-template <typename Real>
-__device__ inline void put_atom(const SysArgs<Real>& a, int64_t i, int c, int32_t slot, Real x,
-                                Real y, Real z, Real q, int t) {
-  const int cz = (int)(c / ((int64_t)a.nx * a.ny));
-  uint32_t st = 0;
-  P4<Real> p;
-  p.x = wrap_coord(x, a.L[0], st);
-  p.y = wrap_coord(y, a.L[1], st);
-  p.z = wrap_coord(z, a.L[2], st);
-  p.w = q;
-  if (t < 0 || t >= a.n_types) t = 0;
-  a.ukey[slot] = UKey{sort_key(a, (int32_t)i, (float)p.x, p.z, cz), t, 0};
-  a.upos[slot] = p;
 }
 
 // Each atom goes to its cell's range (in arbitrary order) with its sort key, its wrapped
@@ -487,73 +561,6 @@ __device__ inline void scatter(const SysArgs<Real>& a, int64_t blk) {
            a.q_in[i], a.type_in[i]);
 }
 
-// Grids of at most kScanFused cells with per-block histograms: block blk (1024 threads)
-// takes atoms 1024 blk .. 1024 blk + 1023, which lie in histogram block
-// hb = 1024 blk / bin_chunk. Thread c adds up the histogram blocks' counts of cell c, all
-// of them and those of the blocks before hb; the totals are scanned into the cells' starts
-// in LDS, and each atom goes to start[c] + (offset of block hb in cell c) + (its rank
-// within hb). Every block repeats this scan, which replaces a kernel of its own; one more
-// block, the last, scatters nothing: it writes start[] and runs scan_tail, alongside the
-// others. All loads are issued before the first is used.
-template <typename Real>
-__host__ __device__ inline int64_t fused_blocks(const SysArgs<Real>& a) {
-  return scan_fused(a) ? (a.n + 1023) / 1024 + 1 : 0;
-}
-
-template <typename Real>
-__device__ inline void scatter_fused(const SysArgs<Real>& a, const TypeTable& tt, int64_t blk) {
-  static_assert(kScanFused <= 1024, "one cell per thread");
-  static_assert(kBinChunkUnit % 1024 == 0, "a block's atoms lie in one histogram block");
-  __shared__ int32_t s_tot[16];
-  __shared__ int32_t s_start[kScanFused];
-  __shared__ int32_t s_off[kScanFused];
-  __shared__ int32_t s_cnt[kScanFused];
-  const int t = threadIdx.x;
-  const int nc = (int)a.n_cells;
-  const int B = a.bin_blocks;
-  const int64_t i = blk * 1024 + t;
-  const int64_t hb = blk * 1024 / a.bin_chunk;
-  // this thread's atom (a repeat of the last one past the end: nothing is stored for it)
-  const int64_t ic = i < a.n ? i : a.n - 1;
-  const int ci = a.cell[ic], rk = a.rank[ic];
-  const Real x = a.pos_in[3 * ic + 0], y = a.pos_in[3 * ic + 1], z = a.pos_in[3 * ic + 2];
-  const Real q = a.q_in[ic];
-  const int ty = a.type_in[ic];
-  const bool tail = blk == (a.n + 1023) / 1024;   // the block that ends the scan
-  const Status st_blocks = block_status(a, tail);
-  // tail block: this cell's cost in the last pair kernel (loaded before it is known whether
-  // the costs are valid, so that both loads are in flight together)
-  const uint32_t cost_t = tail && t < nc ? a.cost[t] : 0u;
-  const bool by_cost = tail && have_costs(a);
-  int32_t tot = 0, off = 0;
-  if (t < nc) {
-    for (int b0 = 0; b0 < B; b0 += 64) {
-      int32_t v[64];
-#pragma unroll
-      for (int r = 0; r < 64; ++r) v[r] = b0 + r < B ? a.bhist[(int64_t)(b0 + r) * nc + t] : 0;
-#pragma unroll
-      for (int r = 0; r < 64; ++r) {
-        tot += v[r];
-        off += b0 + r < hb ? v[r] : 0;
-      }
-    }
-  }
-  int32_t all;
-  const int32_t start_c = block_scan_excl(tot, s_tot, &all);
-  if (t < nc) {
-    s_start[t] = start_c;
-    s_off[t] = off;
-    s_cnt[t] = by_cost ? (int32_t)cost_key(cost_t) : tot;   // the tail block's order key
-  }
-  __syncthreads();
-  if (i < a.n) put_atom(a, i, ci, s_start[ci] + s_off[ci] + rk, x, y, z, q, ty);
-  if (tail) {
-    if (t < nc) a.start[t] = start_c;
-    if (t == 0) a.start[nc] = all;
-    scan_tail(a, tt, 1, s_tot, [&](int64_t cc) { return (uint32_t)s_cnt[cc]; }, st_blocks.bits());
-  }
-}
-
 template <typename Real>
 __global__ __launch_bounds__(256) void k_scatter(SysArgs<Real> a) {
   scatter(a, xcd_contiguous(blockIdx.x, gridDim.x));
@@ -563,17 +570,6 @@ __global__ __launch_bounds__(256) void k_scatter_batch(Batch<float> b) {
   int64_t blk;
   const int s = b.pick(blockIdx.x, blk);
   scatter(b.sys[s], blk);
-}
-
-template <typename Real>
-__global__ __launch_bounds__(1024) void k_scatter_fused(SysArgs<Real> a, TypeTable tt) {
-  scatter_fused(a, tt, blockIdx.x);
-}
-
-__global__ __launch_bounds__(1024) void k_scatter_fused_batch(Batch<float> b, TypeTable tt) {
-  int64_t blk;
-  const int s = b.pick(blockIdx.x, blk);
-  scatter_fused(b.sys[s], tt, blk);
 }
 
 // One workgroup per cell. Each member's position in the cell is the number of members
@@ -624,35 +620,87 @@ __device__ inline void write_hpre(const SysArgs<Real>& a, const P4<Real>& o, int
   a.hpre[2 * (int64_t)d + 1] = h1;
 }
 
+// Threads of a workgroup of k_cell_sort.
+constexpr int kSortThreads = 256;
+
 template <typename Real>
 __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
   constexpr int kChunk = 1024;
-  constexpr int kPer = kChunk / 256;
+  constexpr int kPer = kChunk / kSortThreads;
   __shared__ unsigned long long s_key[kChunk];
+  __shared__ int32_t s_src[kChunk];
+  __shared__ int32_t s_tot[kSortThreads / 64];
   __shared__ int32_t s_low;
-  const int32_t s0 = a.start[c];
-  const int32_t m = a.start[c + 1] - s0;
+  const bool fused = scan_fused(a);
+  const int t = threadIdx.x;
+  int32_t s0, m;
+  if (fused) {
+    // block b's atoms of this cell are bhist[b][c + 1] - bhist[b][c] of its range, from
+    // position b bin_chunk + bhist[b][c]; the cell starts at the sum over the blocks of
+    // bhist[b][c] (the atoms in earlier cells)
+    constexpr int kBPer = kBinMaxBlocks / kSortThreads;
+    const int B = a.bin_blocks;
+    const int64_t row = a.n_cells + 1;
+    int32_t ls[kBPer], cb[kBPer];
+    int32_t sl = 0, sc = 0;
+#pragma unroll
+    for (int k = 0; k < kBPer; ++k) {
+      const int b = t + kSortThreads * k;
+      ls[k] = cb[k] = 0;
+      if (b < B) {
+        const int32_t* r = a.bhist + b * row + c;
+        ls[k] = r[0];
+        cb[k] = r[1] - ls[k];
+      }
+      sl += ls[k];
+      sc += cb[k];
+    }
+    block_scan_excl_w<kSortThreads / 64>(sl, s_tot, &s0);
+    int32_t off = block_scan_excl_w<kSortThreads / 64>(sc, s_tot, &m);
+    if (t == 0) a.start[c] = s0;
+    // the members' positions in the unsorted arrays, in LDS, or for a cell of more than
+    // kChunk atoms in rank[s0 .. s0 + m) (read back by this workgroup only)
+#pragma unroll
+    for (int k = 0; k < kBPer; ++k) {
+      const int32_t p0 = (int32_t)((int64_t)(t + kSortThreads * k) * a.bin_chunk) + ls[k];
+      for (int32_t r = 0; r < cb[k]; ++r) {
+        if (m <= kChunk)
+          s_src[off + r] = p0 + r;
+        else
+          a.rank[s0 + off + r] = p0 + r;
+      }
+      off += cb[k];
+    }
+    __syncthreads();
+  } else {
+    s0 = a.start[c];
+    m = a.start[c + 1] - s0;
+  }
+  // position of member e in the unsorted arrays
+  auto src = [&](int32_t e) -> int32_t {
+    return !fused ? s0 + e : m <= kChunk ? s_src[e] : a.rank[s0 + e];
+  };
   const P4<Real> o = cell_centre(a, c);
-  if (threadIdx.x == 0) s_low = 0;
+  if (t == 0) s_low = 0;
   if (m == 0) {
-    if (threadIdx.x == 0) a.zsplit[c] = 0;
+    if (t == 0) a.zsplit[c] = 0;
     return;
   }
   if (m <= kChunk) {
     // the whole cell in one LDS chunk: each member's key, position and type are loaded
     // once, together, and the keys go to LDS from registers
-    const int kk = (m + 255) / 256;   // member slots in use (uniform)
+    const int kk = (m + kSortThreads - 1) / kSortThreads;   // member slots in use (uniform)
     unsigned long long my_key[kPer];
     Real px[kPer], py[kPer], pz[kPer], pq[kPer];
     int32_t my_t[kPer], my_rank[kPer];
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
-      const int32_t e = (int32_t)threadIdx.x + 256 * k;
+      const int32_t e = t + kSortThreads * k;
       const bool in = k < kk && e < m;
-      const int32_t src = s0 + (in ? e : 0);   // m >= 1 here: a valid member
-      const UKey u = a.ukey[src];
+      const int32_t sp = src(in ? e : 0);   // m >= 1 here: a valid member
+      const UKey u = a.ukey[sp];
       my_key[k] = in ? u.key : ~0ull;
-      const P4<Real> p = a.upos[src];
+      const P4<Real> p = a.upos[sp];
       px[k] = p.x;
       py[k] = p.y;
       pz[k] = p.z;
@@ -660,10 +708,10 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
       my_t[k] = u.type;
       my_rank[k] = 0;
     }
-    // slots m .. 256 kk - 1 (a multiple of 8) hold ~0, which is below no key
+    // slots m .. kSortThreads kk - 1 (a multiple of 8) hold ~0, which is below no key
 #pragma unroll
     for (int k = 0; k < kPer; ++k)
-      if (k < kk) s_key[threadIdx.x + 256 * k] = my_key[k];
+      if (k < kk) s_key[t + kSortThreads * k] = my_key[k];
     __syncthreads();
     for (int32_t e = 0; e < m; e += 8) {
       unsigned long long kx[8];
@@ -679,7 +727,7 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
     }
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
-      const int32_t e = (int32_t)threadIdx.x + 256 * k;
+      const int32_t e = t + kSortThreads * k;
       const bool in = k < kk && e < m;
       count_low(&s_low, in && !(my_key[k] >> 63));
       if (!in) continue;
@@ -693,25 +741,26 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
       a.type[d] = my_t[k];
       a.perm[d] = (int32_t)(my_key[k] & 0x7fffffffull);
       if (a.compact) write_hpre(a, o, d, p, my_t[k]);
+      if (fused) clear_atom(a, d);
     }
     __syncthreads();
-    if (threadIdx.x == 0) a.zsplit[c] = s_low;
+    if (t == 0) a.zsplit[c] = s_low;
     return;
   }
   for (int32_t a0 = 0; a0 < m; a0 += kChunk) {
-    const int kk = min(kPer, (m - a0 + 255) / 256);   // member slots in use (uniform)
+    const int kk = min(kPer, (m - a0 + kSortThreads - 1) / kSortThreads);   // slots in use
     unsigned long long my_key[kPer];
     int32_t my_rank[kPer];
     for (int k = 0; k < kPer; ++k) {
-      const int32_t e = a0 + (int32_t)threadIdx.x + 256 * k;
-      my_key[k] = (k < kk && e < m) ? a.ukey[s0 + e].key : ~0ull;
+      const int32_t e = a0 + t + kSortThreads * k;
+      my_key[k] = (k < kk && e < m) ? a.ukey[src(e)].key : ~0ull;
       my_rank[k] = 0;
     }
     for (int32_t b0 = 0; b0 < m; b0 += kChunk) {
       const int32_t mb = min(kChunk, m - b0);
       __syncthreads();
-      for (int32_t e = threadIdx.x; e < mb; e += 256) s_key[e] = a.ukey[s0 + b0 + e].key;
-      for (int32_t e = mb + (int32_t)threadIdx.x; e < ((mb + 3) & ~3); e += 256) s_key[e] = ~0ull;
+      for (int32_t e = t; e < mb; e += kSortThreads) s_key[e] = a.ukey[src(b0 + e)].key;
+      for (int32_t e = mb + t; e < ((mb + 3) & ~3); e += kSortThreads) s_key[e] = ~0ull;
       __syncthreads();
       for (int32_t e = 0; e < mb; e += 4) {
         const unsigned long long k0 = s_key[e], k1 = s_key[e + 1], k2 = s_key[e + 2],
@@ -723,30 +772,88 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
       }
     }
     for (int k = 0; k < kPer; ++k) {
-      const int32_t e = a0 + (int32_t)threadIdx.x + 256 * k;
+      const int32_t e = a0 + t + kSortThreads * k;
       const bool in = k < kk && e < m;
       count_low(&s_low, in && !(my_key[k] >> 63));
       if (!in) continue;
       const int32_t d = s0 + my_rank[k];
-      const P4<Real> p = a.upos[s0 + e];
-      const int32_t ty = a.ukey[s0 + e].type;
+      const int32_t sp = src(e);
+      const P4<Real> p = a.upos[sp];
+      const int32_t ty = a.ukey[sp].type;
       a.pos[d] = p;
       a.type[d] = ty;
       a.perm[d] = (int32_t)(my_key[k] & 0x7fffffffull);
       if (a.compact) write_hpre(a, o, d, p, ty);
+      if (fused) clear_atom(a, d);
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) a.zsplit[c] = s_low;
+  if (t == 0) a.zsplit[c] = s_low;
+}
+
+// The end of the binning on grids of at most kScanFused cells, by the first workgroup of
+// k_cell_sort alongside the cells' (which write their own starts): start[n_cells], then
+// scan_tail with each cell's order key, its time in the last pair kernel when known, else
+// its atom count summed over the histogram blocks.
+template <typename Real>
+__device__ inline void bin_tail(const SysArgs<Real>& a, const TypeTable& tt) {
+  __shared__ uint32_t s_k[kScanFused];
+  __shared__ int32_t s_tot[kSortThreads / 64];
+  const int t = threadIdx.x;
+  const int nc = (int)a.n_cells, B = a.bin_blocks;
+  const int64_t row = nc + 1;
+  const Status st_blocks = block_status(a, true);
+  const bool by_cost = have_costs(a);
+  if (t == 0) a.start[nc] = (int32_t)a.n;
+  for (int c = t; c < nc; c += kSortThreads) {
+    uint32_t key = 0;
+    if (by_cost) {
+      key = cost_key(a.cost[c]);
+    } else {
+      for (int b0 = 0; b0 < B; b0 += 32) {
+        int32_t v[32];
+#pragma unroll
+        for (int r = 0; r < 32; ++r) {
+          const int32_t* p = a.bhist + (b0 + r) * row + c;
+          v[r] = b0 + r < B ? p[1] - p[0] : 0;
+        }
+#pragma unroll
+        for (int r = 0; r < 32; ++r) key += (uint32_t)v[r];
+      }
+    }
+    s_k[c] = key;
+  }
+  __syncthreads();
+  scan_tail<kSortThreads>(a, tt, 1, s_tot, [&](int64_t c) { return s_k[c]; }, st_blocks.bits());
+}
+
+// Block blk of k_cell_sort: with the fused scan, block 0 ends the binning and block c + 1
+// sorts cell c; otherwise block c sorts cell c.
+template <typename Real>
+__device__ inline void cell_sort_or_tail(const SysArgs<Real>& a, const TypeTable& tt, int64_t blk) {
+  if (!scan_fused(a)) {
+    cell_sort(a, blk);
+  } else if (blk == 0) {
+    bin_tail(a, tt);
+  } else {
+    cell_sort(a, blk - 1);
+  }
 }
 
 template <typename Real>
-__global__ __launch_bounds__(256) void k_cell_sort(SysArgs<Real> a) { cell_sort(a, blockIdx.x); }
+__host__ __device__ inline int64_t sort_blocks(const SysArgs<Real>& a) {
+  return a.n_cells + (scan_fused(a) ? 1 : 0);
+}
 
-__global__ __launch_bounds__(256) void k_cell_sort_batch(Batch<float> b) {
+template <typename Real>
+__global__ __launch_bounds__(kSortThreads) void k_cell_sort(SysArgs<Real> a, TypeTable tt) {
+  cell_sort_or_tail(a, tt, blockIdx.x);
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_cell_sort_batch(Batch<float> b, TypeTable tt) {
   int64_t blk;
   const int s = b.pick(blockIdx.x, blk);
-  cell_sort(b.sys[s], blk);
+  cell_sort_or_tail(b.sys[s], tt, blk);
 }
 
 }  // namespace
@@ -784,10 +891,7 @@ hipError_t launch_binning(const SysArgs<Real>& a, const TypeTable& tt, hipStream
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(k_setup<Real>, dim3((unsigned)blocks), dim3(256), 0, stream, as);
   }
-  if (scan_fused(as)) {
-    hipLaunchKernelGGL(k_scatter_fused<Real>, dim3((unsigned)fused_blocks(as)), dim3(1024), 0,
-                       stream, as, tt);
-  } else {
+  if (!scan_fused(as)) {
     if (colscan_blocks(as) > 0)
       hipLaunchKernelGGL(k_bin_colscan<Real>, dim3((unsigned)colscan_blocks(as)), dim3(1024), 0,
                          stream, as);
@@ -796,7 +900,8 @@ hipError_t launch_binning(const SysArgs<Real>& a, const TypeTable& tt, hipStream
     hipLaunchKernelGGL(k_scatter<Real>, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, stream,
                        a);
   }
-  hipLaunchKernelGGL(k_cell_sort<Real>, dim3((unsigned)a.n_cells), dim3(256), 0, stream, a);
+  hipLaunchKernelGGL(k_cell_sort<Real>, dim3((unsigned)sort_blocks(a)), dim3(kSortThreads), 0,
+                     stream, a, tt);
   return hipGetLastError();
 }
 
@@ -817,10 +922,7 @@ hipError_t launch_binning_batch(const Batch<float>& b0, const TypeTable& tt, hip
   }
   int64_t nb = batch_blocks(b, [](const SysArgs<float>& a) { return (int64_t)a.bin_blocks; });
   hipLaunchKernelGGL(k_bin_hist_batch, dim3((unsigned)nb), dim3(kBinThreads), shmem, stream, b);
-  // grids of at most kScanFused cells: scan and scatter in one kernel
-  nb = batch_blocks(b, [](const SysArgs<float>& a) { return fused_blocks(a); });
-  if (nb > 0) hipLaunchKernelGGL(k_scatter_fused_batch, dim3((unsigned)nb), dim3(1024), 0, stream, b, tt);
-  // larger grids
+  // grids of more than kScanFused cells (the others need no scan kernels)
   nb = batch_blocks(b, [](const SysArgs<float>& a) { return colscan_blocks(a); });
   if (nb > 0) hipLaunchKernelGGL(k_bin_colscan_batch, dim3((unsigned)nb), dim3(1024), 0, stream, b);
   nb = batch_blocks(b, [](const SysArgs<float>& a) { return scan_fused(a) ? (int64_t)0 : (int64_t)1; });
@@ -831,8 +933,8 @@ hipError_t launch_binning_batch(const Batch<float>& b0, const TypeTable& tt, hip
     });
     hipLaunchKernelGGL(k_scatter_batch, dim3((unsigned)nb), dim3(256), 0, stream, b);
   }
-  nb = batch_blocks(b, [](const SysArgs<float>& a) { return a.n_cells; });
-  hipLaunchKernelGGL(k_cell_sort_batch, dim3((unsigned)nb), dim3(256), 0, stream, b);
+  nb = batch_blocks(b, [](const SysArgs<float>& a) { return sort_blocks(a); });
+  hipLaunchKernelGGL(k_cell_sort_batch, dim3((unsigned)nb), dim3(kSortThreads), 0, stream, b, tt);
   return hipGetLastError();
 }
 

@@ -115,9 +115,11 @@ struct SysArgs {
   int32_t* count;              // [n_cells]
   int32_t* start;              // [n_cells+1]
   int32_t* cell;               // [n]
-  int32_t* rank;               // [n]
+  int32_t* rank;               // [n] (also the in-cell sort's member list of a cell of more
+                               // than 1024 atoms, with the fused scan)
   UKey* ukey;                  // [n] in-cell sort keys and types, in cell order before the
-                               // in-cell sort
+                               // in-cell sort (with the fused scan: in cell order within
+                               // each histogram block's range)
   P4<Real>* upos;              // [n] wrapped (x, y, z, q), same order
   P4<Real>* pos;               // [n] sorted (x,y,z,q)
   P4<Real>* hpre;              // [2n] sorted, for the compacted kernel (written by the
@@ -135,8 +137,10 @@ struct SysArgs {
   long long* acc64;            // per-atom fixed-point sums of the compacted kernel: float32
                                // [3][n] (2^-28 kcal/mol/A); float64 [2][3][n], the high
                                // words (2^-20) then the low words (2^-72)
-  int32_t* bhist;              // [bin_blocks][n_cells] per-block cell counts (offsets in place
-                               // after k_bin_colscan, for grids of more than 1024 cells)
+  int32_t* bhist;              // grids of at most 1024 cells: [bin_blocks][n_cells + 1] each
+                               // block's start of every cell within its range (then its
+                               // atom count); larger grids: [bin_blocks][n_cells] per-block
+                               // cell counts (offsets in place after k_bin_colscan)
   uint32_t* bstat;             // [bin_blocks] per-block status bits
   int32_t* order;              // [n_cells] launch order of the home cells, longest first
   uint32_t* cost;              // [n_cells] each home cell's time in the last pair kernel

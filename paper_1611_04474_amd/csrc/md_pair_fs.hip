@@ -281,21 +281,24 @@ constexpr int kCoulSwitched = 0, kCoulPlain = 1, kCoulEwald = 2;
 
 // Pair force factor f (F_i = f r_ij) and pair energy e at squared distance u.
 // c12 = 4 eps s^12, c6 = 4 eps s^6 (Eq. 1: A = 12 c12, B = 6 c6); qq = k q_i q_j (Eq. 2).
-// The switch t = clamp((u - rs^2)/(rc^2 - rs^2), 0, 1), S = (1-t)^2 (1+2t), and
-// g = 12 t (1-t) / (rc^2 - rs^2) = -2 dS/du. With the whole energy switched, at t = 1 both
-// f and e are exactly zero. Ewald: e_C = qq erfc(a r)/r and -(1/r) de_C/dr =
+// The switch in s = 1 - t = clamp((rc^2 - u)/(rc^2 - rs^2), 0, 1): S = s^2 (3 - 2s) =
+// (1-t)^2 (1+2t), and g = 12 s (1-s) / (rc^2 - rs^2) = -2 dS/du. rc^2 - u is exact near the
+// cutoff (Sterbenz), so s, S and g keep their relative accuracy where they are small; and
+// rc^2 - u <= 0 exactly for u >= rc^2, so with the whole energy switched a pair at or past
+// the cutoff gets s = 0 and adds exactly zero force and energy. inv_sw is
+// 1/(rc^2 - rs^2), or with the switch off 2^100 (s = 1 for every u < rc^2; sw12 = 0).
+// Ewald: e_C = qq erfc(a r)/r and -(1/r) de_C/dr =
 // qq (erfc(a r)/r + (2a/sqrt(pi)) exp(-a^2 u)) / u, with ew = (a, 2a/sqrt(pi)).
 template <int kCoul, typename Real>
-__device__ inline Real pair_f(Real u, Real c12, Real c6, Real qq, Real rs2, Real inv_sw,
+__device__ inline Real pair_f(Real u, Real c12, Real c6, Real qq, Real rc2, Real inv_sw,
                               Real sw12, Real& e, V2<Real> ew = {}) {
-  // u - rs2 is exact near the cutoff (Sterbenz), so t keeps its accuracy where S is small
-  Real rinv, t;
+  Real rinv, s;
   if constexpr (sizeof(Real) == 4) {
     rinv = __builtin_amdgcn_rsqf(u);
-    t = __builtin_amdgcn_fmed3f((u - rs2) * inv_sw, 0.f, 1.f);
+    s = __builtin_amdgcn_fmed3f((rc2 - u) * inv_sw, 0.f, 1.f);
   } else {
     rinv = 1.0 / sqrt(u);
-    t = fmin(fmax((u - rs2) * inv_sw, 0.0), 1.0);
+    s = fmin(fmax((rc2 - u) * inv_sw, 0.0), 1.0);
   }
   const Real r2 = rinv * rinv;
   const Real r6 = r2 * r2 * r2;
@@ -303,9 +306,9 @@ __device__ inline Real pair_f(Real u, Real c12, Real c6, Real qq, Real rs2, Real
   const Real elj = mad(c12 * r6, r6, -c6r6);        // c12/r^12 - c6/r^6
   const Real x6 = mad(Real(2), elj, c6r6);          // (12 c12/r^12 - 6 c6/r^6) / 6
   const Real ec = qq * rinv;
-  const Real t2 = t * t;
-  const Real S = mad(t2, mad(Real(2), t, Real(-3)), Real(1));   // (1-t)^2 (1+2t)
-  const Real g = (t - t2) * sw12;
+  const Real s2 = s * s;
+  const Real S = s2 * mad(Real(-2), s, Real(3));   // (1-t)^2 (1+2t)
+  const Real g = (s - s2) * sw12;                  // 12 t (1-t) / (rc^2 - rs^2)
   if (kCoul == kCoulSwitched) {
     const Real et = elj + ec;
     e = S * et;
@@ -364,7 +367,7 @@ __device__ inline void lds_store_u16_lanes4(uint32_t a0, uint32_t a1, uint32_t a
 
 // kClamp: the whole energy is switched and the switch is on, so lanes that must add
 // nothing (a partial batch, the home atom itself) get u = kBigU instead of masks on f
-// and e, and pairs beyond the cutoff need no test (t clamps to 1).
+// and e, and pairs beyond the cutoff need no test (the switch variable s clamps to 0).
 // kDiag: count filter passes, cutoff passes and filtered slots (MD_DIAG_COUNTERS).
 // kHalf: the half shell (64-bit fixed-point sums only). kDrain: force batches per drain.
 template <typename Real, bool kHalf, int kCoul, bool kClamp, bool kDiag, int kDrain>
@@ -397,7 +400,8 @@ __device__ __attribute__((always_inline)) inline bool pair_fs(const SysArgs<Real
       nt > 1 ? (2u << (31 - __builtin_clz((unsigned)(nt - 1)))) - 1u : 0u;
   constexpr bool diag = kDiag;
   const bool f32 = kF32 && !kHalf && (a.flags & MD_ACCUM_F32_ATOMIC) != 0;
-  const Real rc2 = a.rc2, rs2 = a.rs2, inv_sw = a.inv_sw, sw12 = Real(12) * a.inv_sw;
+  const Real rc2 = a.rc2, sw12 = Real(12) * a.inv_sw;
+  const Real inv_sw = a.inv_sw > Real(0) ? a.inv_sw : Real(0x1p100);   // off: s = 1 below rc^2
   const R2 ew = mk2<Real>(a.ewald_alpha, a.ewald_alpha * Real(1.1283791670955126));   // 2/sqrt(pi)
   const Real L0 = a.L[0], L1 = a.L[1], L2 = a.L[2];
   const int ac0 = (int)(cellA % a.nx), ac1 = (int)((cellA / a.nx) % a.ny),
@@ -725,12 +729,12 @@ __device__ __attribute__((always_inline)) inline bool pair_fs(const SysArgs<Real
         Real e, f;
         if (kClamp) {
           u = (in && (kHalf || u > Real(0))) ? u : Real(kBigU);
-          f = pair_f<kCoul>(u, lj.x, lj.y, kq[k] * qj, rs2, inv_sw, sw12, e, ew);
+          f = pair_f<kCoul>(u, lj.x, lj.y, kq[k] * qj, rc2, inv_sw, sw12, e, ew);
           if (diag) cnt[k] += __builtin_popcountll(__builtin_amdgcn_ballot_w64(u < rc2));
           if (kHalf && diag && u < rc2) atomicAdd(&sJn[jl], 1);
         } else {
           const bool lv = in && u < rc2 && u > Real(0);
-          f = pair_f<kCoul>(u, lj.x, lj.y, kq[k] * qj, rs2, inv_sw, sw12, e, ew);
+          f = pair_f<kCoul>(u, lj.x, lj.y, kq[k] * qj, rc2, inv_sw, sw12, e, ew);
           f = lv ? f : Real(0);
           e = lv ? e : Real(0);
           if (diag) cnt[k] += __builtin_popcountll(__builtin_amdgcn_ballot_w64(lv));

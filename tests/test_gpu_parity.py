@@ -173,6 +173,38 @@ def test_binning_many_blocks(gpu):
     torch.cuda.empty_cache()
 
 
+def test_binning_fused_several_rounds(gpu):
+    """2,200,000 atoms, uniform in a 120 A cube of 9^3 cells (at most 1,024: each histogram
+    block writes its atoms in cell order within its range and the in-cell sort gathers the
+    cells): 538 blocks of 4,096 atoms, two rounds each, so the blocks read their atoms' cells
+    and slots back, and every cell holds more than 1,024 atoms, so the sort keeps its member
+    list in the workspace. Binning stage only (the pair stage of a cell this dense is not
+    the point here), from a workspace filled with a byte pattern."""
+    _say("case: binning of 2,200,000 atoms, 120 A cube, 9^3 cells")
+    import torch
+    from _gpu import to_dev
+    rng = np.random.default_rng(33)
+    n = 2_200_000
+    pos = rng.uniform(0.0, 120.0, (n, 3)).astype(np.float32).astype(np.float64)
+    types = rng.integers(0, 2, n).astype(np.int32)
+    q = rng.normal(0, 0.2, n)
+    p = dict(box=(120.0, 120.0, 120.0), r_cut=12.0, r_switch=10.0, coulomb_k=W.COULOMB_K,
+             sigma=np.array([0.8, 0.9]), epsilon=np.array([0.05, 0.1]), flags=0)
+    lay = api.workspace_layout(p, n)
+    assert lay["n_cells"] == 9 ** 3
+    d = to_dev((pos, types, q), gpu)
+    ws = api.alloc_workspace(p, n, gpu)
+    ws.fill_(0xAB)
+    force = torch.empty((n, 3), dtype=torch.float32, device=gpu)
+    energy = torch.empty(1, dtype=torch.float64, device=gpu)
+    api.forces_stages(p, *d, force, energy, ws, api.STAGE_BIN)
+    torch.cuda.synchronize()
+    assert api.read_status(ws) == 0
+    _check_binning(p, pos, ws, n)
+    del ws
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("flags", [0, api.PAIR_FULL_SHELL])
 def test_fixed64_bitwise_reproducible(gpu, flags):
     """Ten calls on one workspace give the same bits. The first call (workspace filled with
@@ -687,11 +719,19 @@ def _cutoff_pairs():
     return pos, t, q
 
 
-@pytest.mark.parametrize("switch", [10.0, 12.0])
+@pytest.mark.parametrize("switch", [10.0, 11.5, 12.0])
 def test_exact_cutoff_pairs(gpu, switch):
     """Algorithm 1's strict cutoff on pairs exactly r_cut apart and one float32 step
     inside, with the switch on and off, in both shells of the float32 kernel and in
-    float64: partner counts 0 / 1 exactly, zero force on the excluded pairs."""
+    float64: partner counts 0 / 1 exactly, zero force on the excluded pairs. At
+    r_switch = 11.5 A the float32 product (rc^2 - rs^2) * fl(1/(rc^2 - rs^2)) rounds to
+    just below 1, so a switch variable t = (u - rs^2) / (rc^2 - rs^2) would stop short of 1
+    at the cutoff; and 1 - t near the cutoff is a few ulps of 1, where the switch's force
+    term, which dominates there, is proportional to it.
+    The float32 kernel's u of a pair just inside is rc^2 less one to three ulps (1.5e-5 A^2
+    each), so u itself fixes rc^2 - u only to about a third for the first pair. Its forces
+    are compared with the oracle's pair terms at that float32 u, float64's with the oracle's
+    exact forces."""
     _say("case: pairs at and just inside r_cut, r_switch", switch)
     pos, t, q = _cutoff_pairs()
     p = dict(box=(40.0, 40.0, 40.0), r_cut=12.0, r_switch=switch, coulomb_k=W.COULOMB_K,
@@ -699,6 +739,15 @@ def test_exact_cutoff_pairs(gpu, switch):
     r = oracle.forces(p, pos, t, q, "bruteforce")
     scale = oracle.forces(dict(p, r_switch=12.0), pos, t, q, "bruteforce")
     assert list(r.count) == [0, 0, 1, 1, 0, 0, 1, 1]
+    # the pairs just inside: displacement (exact in float32) and the float32 u = fl(dx^2)
+    ref32 = np.zeros((8, 3))
+    q32 = q.astype(np.float32).astype(np.float64)
+    for i, j in ((2, 3), (6, 7)):
+        dx = pos[i, 0] - pos[j, 0]
+        dx -= 40.0 * np.round(dx / 40.0)
+        u32 = float(np.float32(dx) * np.float32(dx))
+        fij = oracle.pair_terms(p, t[i], t[j], q32[i], q32[j], u32)[1]
+        ref32[i, 0], ref32[j, 0] = fij * dx, -fij * dx
     for flags, double in ((0, False), (api.PAIR_FULL_SHELL, False), (0, True)):
         f, e, ws, cnt = run(p, pos, t, q, gpu, double=double, flags=flags | api.DIAG_COUNTERS)
         _say("flags", flags, "double", double, "counts", cnt.tolist())
@@ -706,8 +755,9 @@ def test_exact_cutoff_pairs(gpu, switch):
         assert np.all(f[[0, 1, 4, 5]] == 0.0), (flags, double)
         # errors on the scale of the unswitched pair (the switch is near 0 at r_cut)
         tol = 1e-12 if double else 1e-5
+        ref = r.force if double else ref32
         for i in (2, 3, 6, 7):
-            assert np.linalg.norm(f[i] - r.force[i]) <= tol * np.linalg.norm(scale.force[i]), (i, flags)
+            assert np.linalg.norm(f[i] - ref[i]) <= tol * np.linalg.norm(scale.force[i]), (i, flags)
         assert abs(e - r.energy) <= tol * abs(scale.energy), (flags, double)
         assert api.read_diag(ws)[2] == 2
 
