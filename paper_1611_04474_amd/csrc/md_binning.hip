@@ -146,7 +146,7 @@ __device__ inline unsigned long long sort_key(const SysArgs<Real>& a, int32_t i,
 template <typename Real>
 __device__ inline void put_atom(const SysArgs<Real>& a, int64_t i, int c, int32_t slot, Real x,
                                 Real y, Real z, Real q, int t) {
-  const int cz = (int)(c / ((int64_t)a.nx * a.ny));
+  const int cz = c / (a.nx * a.ny);   // fewer than 2^24 cells
   uint32_t st = 0;
   P4<Real> p;
   p.x = wrap_coord(x, a.L[0], st);
@@ -627,17 +627,22 @@ template <typename Real>
 __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
   constexpr int kChunk = 1024;
   constexpr int kPer = kChunk / kSortThreads;
+  // buckets of the rank count: kHalfB per z half, in x order, at most kBucketMax members each
+  constexpr int kHalfB = kSortThreads / 2, kBucketMax = 8;
   __shared__ unsigned long long s_key[kChunk];
   __shared__ int32_t s_src[kChunk];
   __shared__ int32_t s_tot[kSortThreads / 64];
-  __shared__ int32_t s_low;
+  __shared__ int32_t s_bcnt[2 * kHalfB], s_bstart[2 * kHalfB];
+  __shared__ uint16_t s_blist[2 * kHalfB * kBucketMax];
+  __shared__ int32_t s_low, s_over;
   const bool fused = scan_fused(a);
   const int t = threadIdx.x;
   int32_t s0, m;
   if (fused) {
     // block b's atoms of this cell are bhist[b][c + 1] - bhist[b][c] of its range, from
     // position b bin_chunk + bhist[b][c]; the cell starts at the sum over the blocks of
-    // bhist[b][c] (the atoms in earlier cells)
+    // bhist[b][c] (the atoms in earlier cells). Each thread takes blocks t, t + 256, ...;
+    // with at most 64 blocks the first wave does it all with lane sums and scans.
     constexpr int kBPer = kBinMaxBlocks / kSortThreads;
     const int B = a.bin_blocks;
     const int64_t row = a.n_cells + 1;
@@ -655,21 +660,42 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
       sl += ls[k];
       sc += cb[k];
     }
-    block_scan_excl_w<kSortThreads / 64>(sl, s_tot, &s0);
-    int32_t off = block_scan_excl_w<kSortThreads / 64>(sc, s_tot, &m);
+    int32_t off;
+    if (B <= 64) {
+      if (t < 64) {
+        int32_t inc = sc;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const int32_t y = __shfl_up(inc, o);
+          if (t >= o) inc += y;
+          sl += __shfl_xor(sl, o);
+        }
+        off = inc - sc;
+        if (t == 63) s_bstart[0] = inc;   // the cell's atom count
+        if (t == 0) s_bstart[1] = sl;     // its start
+      }
+      __syncthreads();
+      m = s_bstart[0];
+      s0 = s_bstart[1];
+    } else {
+      block_scan_excl_w<kSortThreads / 64>(sl, s_tot, &s0);
+      off = block_scan_excl_w<kSortThreads / 64>(sc, s_tot, &m);
+    }
     if (t == 0) a.start[c] = s0;
     // the members' positions in the unsorted arrays, in LDS, or for a cell of more than
     // kChunk atoms in rank[s0 .. s0 + m) (read back by this workgroup only)
+    if (B > 64 || t < 64) {
 #pragma unroll
-    for (int k = 0; k < kBPer; ++k) {
-      const int32_t p0 = (int32_t)((int64_t)(t + kSortThreads * k) * a.bin_chunk) + ls[k];
-      for (int32_t r = 0; r < cb[k]; ++r) {
-        if (m <= kChunk)
-          s_src[off + r] = p0 + r;
-        else
-          a.rank[s0 + off + r] = p0 + r;
+      for (int k = 0; k < kBPer; ++k) {
+        const int32_t p0 = (int32_t)((int64_t)(t + kSortThreads * k) * a.bin_chunk) + ls[k];
+        for (int32_t r = 0; r < cb[k]; ++r) {
+          if (m <= kChunk)
+            s_src[off + r] = p0 + r;
+          else
+            a.rank[s0 + off + r] = p0 + r;
+        }
+        off += cb[k];
       }
-      off += cb[k];
     }
     __syncthreads();
   } else {
@@ -681,6 +707,9 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
     return !fused ? s0 + e : m <= kChunk ? s_src[e] : a.rank[s0 + e];
   };
   const P4<Real> o = cell_centre(a, c);
+  // the cell's x range (its lower face and width), for the rank count's buckets
+  const Real cell_w = a.L[0] / (Real)a.nx;
+  const Real cell_x0 = o.x - Real(0.5) * cell_w;
   if (t == 0) s_low = 0;
   if (m == 0) {
     if (t == 0) a.zsplit[c] = 0;
@@ -712,16 +741,58 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
 #pragma unroll
     for (int k = 0; k < kPer; ++k)
       if (k < kk) s_key[t + kSortThreads * k] = my_key[k];
+    s_bcnt[t] = 0;
+    if (t == 0) s_over = 0;
     __syncthreads();
-    for (int32_t e = 0; e < m; e += 8) {
-      unsigned long long kx[8];
+    // rank = members in earlier buckets + smaller keys in the member's own bucket; the
+    // bucket, from the z half and x of the key, never decreases as the key grows
+    const float bx0 = (float)cell_x0, bsc = (float)(kHalfB / cell_w);
+    int bk[kPer];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) kx[u] = s_key[e + u];
+    for (int k = 0; k < kPer; ++k) {
+      const int32_t e = t + kSortThreads * k;
+      bk[k] = 0;
+      if (k < kk && e < m) {
+        const float x = __uint_as_float((uint32_t)(my_key[k] >> 31) & 0x7fffffffu);
+        const int xb = min(max((int)((x - bx0) * bsc), 0), kHalfB - 1);
+        bk[k] = (int)(my_key[k] >> 63) * kHalfB + xb;
+        const int sl = atomicAdd(&s_bcnt[bk[k]], 1);
+        if (sl < kBucketMax)
+          s_blist[bk[k] * kBucketMax + sl] = (uint16_t)e;
+        else
+          s_over = 1;
+      }
+    }
+    __syncthreads();
+    if (s_over == 0) {
+      // bucket starts (one bucket per thread)
+      int32_t all;
+      const int32_t cb = s_bcnt[t];
+      const int32_t bs = block_scan_excl_w<kSortThreads / 64>(cb, s_tot, &all);
+      s_bstart[t] = bs;
+      __syncthreads();
 #pragma unroll
       for (int k = 0; k < kPer; ++k) {
-        if (k < kk) {
+        const int32_t e = t + kSortThreads * k;
+        if (k < kk && e < m) {
+          const int b = bk[k], nb = s_bcnt[b];
+          int r = s_bstart[b];
+          for (int j = 0; j < nb; ++j) r += s_key[s_blist[b * kBucketMax + j]] < my_key[k];
+          my_rank[k] = r;
+        }
+      }
+    } else {
+      // a crowded bucket: every member counts every smaller key of the cell
+      for (int32_t e = 0; e < m; e += 8) {
+        unsigned long long kx[8];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) my_rank[k] += kx[u] < my_key[k];
+        for (int u = 0; u < 8; ++u) kx[u] = s_key[e + u];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+          if (k < kk) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) my_rank[k] += kx[u] < my_key[k];
+          }
         }
       }
     }
