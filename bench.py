@@ -41,8 +41,8 @@ METRIC = "within-cutoff pair-interactions/s @92k atoms; p50/p99 latency mixed ba
 # HBM bytes per launch of the pair kernel at 92,224 atoms, from the FETCH_SIZE and
 # WRITE_SIZE counters scaled by a copy of known size (profiles/traffic_pair_fs_92k.md);
 # valid only for the kernel code they were taken on (kernel_code_sha256)
-PAIR_TRAFFIC = {"kernel_sha256": "9fabb6081ec0c0839daf1f960cc039407bf594cdc29df836b4821f9fe9ca8377",
-                "bytes": (15759 + 29421) * 1024}
+PAIR_TRAFFIC = {"kernel_sha256": "4794194dfbde576d4c0a25f8e99242fba4680fe2e709ecfbaf35c35fdde40eef",
+                "bytes": (15642 + 29421) * 1024}
 
 
 def parse():

@@ -237,21 +237,27 @@ __device__ inline void bin_hist(const SysArgs<Real>& a, int64_t blk) {
     if (tid == 0) a.bstat[blk] = (uint32_t)s_h[nc];
     return;
   }
-  // the block's start of each cell: cells 2 tid and 2 tid + 1 per thread (nc <= 1024)
-  static_assert(kScanFused <= 2 * kBinThreads, "two cells per thread");
+  // the block's start of each cell: kCellsPer consecutive cells per thread (nc <= 1024)
+  constexpr int kCellsPer = kScanFused / kBinThreads;
+  static_assert(kCellsPer * kBinThreads == kScanFused, "cells per thread");
   const uint32_t stb = (uint32_t)s_h[nc];
-  const int c0 = 2 * tid;
-  const int32_t v0 = c0 < nc ? s_h[c0] : 0, v1 = c0 + 1 < nc ? s_h[c0 + 1] : 0;
-  int32_t all;
-  const int32_t ex = block_scan_excl_w<kBinThreads / 64>(v0 + v1, s_tot, &all);
-  int32_t* lrow = a.bhist + blk * (int64_t)(nc + 1);
-  if (c0 < nc) {
-    s_h[c0] = ex;
-    lrow[c0] = ex;
+  const int c0 = kCellsPer * tid;
+  int32_t v[kCellsPer], sum = 0;
+#pragma unroll
+  for (int k = 0; k < kCellsPer; ++k) {
+    v[k] = c0 + k < nc ? s_h[c0 + k] : 0;
+    sum += v[k];
   }
-  if (c0 + 1 < nc) {
-    s_h[c0 + 1] = ex + v0;
-    lrow[c0 + 1] = ex + v0;
+  int32_t all;
+  int32_t ex = block_scan_excl_w<kBinThreads / 64>(sum, s_tot, &all);
+  int32_t* lrow = a.bhist + blk * (int64_t)(nc + 1);
+#pragma unroll
+  for (int k = 0; k < kCellsPer; ++k) {
+    if (c0 + k < nc) {
+      s_h[c0 + k] = ex;
+      lrow[c0 + k] = ex;
+    }
+    ex += v[k];
   }
   if (tid == 0) {
     lrow[nc] = all;
@@ -641,18 +647,21 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
   if (fused) {
     // block b's atoms of this cell are bhist[b][c + 1] - bhist[b][c] of its range, from
     // position b bin_chunk + bhist[b][c]; the cell starts at the sum over the blocks of
-    // bhist[b][c] (the atoms in earlier cells). Each thread takes blocks t, t + 256, ...;
-    // with at most 64 blocks the first wave does it all with lane sums and scans.
+    // bhist[b][c] (the atoms in earlier cells). With at most 256 blocks the first wave
+    // does it all, lane l taking blocks l, l + 64, l + 128, l + 192, with lane sums and
+    // scans; otherwise thread t takes blocks t, t + 256, ... and block scans.
     constexpr int kBPer = kBinMaxBlocks / kSortThreads;
     const int B = a.bin_blocks;
+    const bool one_wave = B <= 64 * kBPer;
+    const int bstride = one_wave ? 64 : kSortThreads;
     const int64_t row = a.n_cells + 1;
     int32_t ls[kBPer], cb[kBPer];
     int32_t sl = 0, sc = 0;
 #pragma unroll
     for (int k = 0; k < kBPer; ++k) {
-      const int b = t + kSortThreads * k;
+      const int b = t + bstride * k;
       ls[k] = cb[k] = 0;
-      if (b < B) {
+      if (b < B && (!one_wave || t < 64)) {
         const int32_t* r = a.bhist + b * row + c;
         ls[k] = r[0];
         cb[k] = r[1] - ls[k];
@@ -661,7 +670,7 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
       sc += cb[k];
     }
     int32_t off;
-    if (B <= 64) {
+    if (one_wave) {
       if (t < 64) {
         int32_t inc = sc;
 #pragma unroll
@@ -684,10 +693,10 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
     if (t == 0) a.start[c] = s0;
     // the members' positions in the unsorted arrays, in LDS, or for a cell of more than
     // kChunk atoms in rank[s0 .. s0 + m) (read back by this workgroup only)
-    if (B > 64 || t < 64) {
+    if (!one_wave || t < 64) {
 #pragma unroll
       for (int k = 0; k < kBPer; ++k) {
-        const int32_t p0 = (int32_t)((int64_t)(t + kSortThreads * k) * a.bin_chunk) + ls[k];
+        const int32_t p0 = (int32_t)((int64_t)(t + bstride * k) * a.bin_chunk) + ls[k];
         for (int32_t r = 0; r < cb[k]; ++r) {
           if (m <= kChunk)
             s_src[off + r] = p0 + r;

@@ -173,6 +173,28 @@ def test_binning_many_blocks(gpu):
     torch.cuda.empty_cache()
 
 
+def test_binning_fused_one_wave_gather(gpu):
+    """300,000 atoms in 10 x 10 x 8 cells: 147 histogram blocks of 2,048 atoms, so the
+    in-cell sort's first wave gathers each cell from three blocks per lane (up to 256
+    blocks take that path); sampled forces against the oracle."""
+    _say("case: binning of 300,000 atoms, 130 x 130 x 100 A")
+    import torch
+    s = W.gen_system(300_000, (130.0, 130.0, 100.0), seed=23)
+    p = s.params()
+    lay = api.workspace_layout(p, s.n)
+    assert tuple(lay["dims"]) == (10, 10, 8)
+    f, e, ws, _ = run(p, s.pos, s.types, s.charges, gpu)
+    assert api.read_status(ws) == 0
+    _check_binning(p, s.pos, ws, s.n)
+    idx = np.sort(np.random.default_rng(5).choice(s.n, 200, replace=False))
+    ref = oracle.forces_subset(p, s.pos, s.types, s.charges, idx)
+    err = force_errors(f[idx], ref.force, ref.abs_sum)
+    _say("sampled", err)
+    assert err["max_norm"] <= 1e-5 and err["rms"] <= 1e-5
+    del ws
+    torch.cuda.empty_cache()
+
+
 def test_binning_fused_several_rounds(gpu):
     """2,200,000 atoms, uniform in a 120 A cube of 9^3 cells (at most 1,024: each histogram
     block writes its atoms in cell order within its range and the in-cell sort gathers the
