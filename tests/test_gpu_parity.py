@@ -321,7 +321,9 @@ def test_fp64_tiny_grids(gpu, box, n, seed, flags):
 
 def test_clustered_cell_beyond_one_tile(gpu):
     """600 atoms packed into one 12 A cell of a 3x3x3 grid: the home cell holds more
-    atoms than one LDS tile, exercising the multi-tile path."""
+    atoms than one LDS tile, exercising the multi-tile path. Its atoms share 9 values of x,
+    about 33 per (z half, x) bucket of the in-cell sort's rank count, more than a bucket
+    takes, so that cell is ranked by counting all pairs; ties in x are ordered by index."""
     _say("case: clustered cell, 600 + 200 atoms")
     rng = np.random.default_rng(5)
     g = np.arange(0, 12.0, 1.45)
@@ -341,7 +343,8 @@ def test_clustered_cell_beyond_one_tile(gpu):
         assert e == pytest.approx(r.energy, rel=1e-12)
         assert np.array_equal(cnt, r.count)
         for f32_flags in ((flags,) if flags else (0, api.PAIR_FULL_SHELL)):
-            f32, e32, _, _ = run(p, pos, t, q, gpu, flags=f32_flags)
+            f32, e32, ws32, _ = run(p, pos, t, q, gpu, flags=f32_flags)
+            _check_binning(dict(p, flags=f32_flags), pos, ws32, n)
             err32 = force_errors(f32, r.force, r.abs_sum)
             assert err32["max_norm"] <= 1e-5 and err32["rms"] <= 1e-5, (f32_flags, err32)
             assert e32 == pytest.approx(r.energy, rel=1e-6), f32_flags
@@ -533,7 +536,7 @@ def test_batched_matches_alone(gpu):
     results of evaluating each alone. 14 systems exceed one launch batch, one predicated
     system is evaluated on its own inside the call, and two full-shell systems split
     the batches by kind. The last system has 1,728 cells, so its binning takes the path
-    for grids of more than 1024 cells while the others scan inside the scatter."""
+    for grids of more than 1024 cells while the others take the two-kernel binning."""
     _say("case: 13 serving requests and one 150,000-atom cube, batched vs alone")
     import torch
     from _gpu import to_dev
