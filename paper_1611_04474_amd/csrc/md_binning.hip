@@ -185,7 +185,8 @@ constexpr int kHistPer = kBinChunkUnit / kBinThreads;
 // unsorted arrays. A block of one round keeps its atoms in registers meanwhile; longer
 // blocks store each atom's cell and slot and read them back. The per-atom sums are cleared
 // by the in-cell sort then. Larger grids: the histogram goes to bhist[blk][0 .. n_cells - 1]
-// and the cell and slot of each atom to cell[] and rank[].
+// and the cell and slot of each atom to cell[] and rank[], and the block clears its atoms'
+// per-atom sums.
 template <typename Real>
 __device__ inline void bin_hist(const SysArgs<Real>& a, int64_t blk) {
   extern __shared__ int32_t s_h[];   // [n_cells] counts, then the status bits
