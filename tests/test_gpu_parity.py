@@ -195,6 +195,43 @@ def test_binning_fused_one_wave_gather(gpu):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("n, box, r_cut, cells, blocks", [
+    (524_288, (172.0, 172.0, 172.0), 17.0, 1000, 256),   # the most blocks one wave gathers
+    (524_289, (172.0, 172.0, 172.0), 17.0, 1000, 257),   # the fewest the block scans take
+    (181_000, (194.0, 97.0, 97.0), 12.0, 1024, 89),      # the largest grid of the fused scan
+])
+def test_binning_fused_limits(gpu, n, box, r_cut, cells, blocks):
+    """The edges of the two-kernel binning: 256 and 257 histogram blocks of 2,048 atoms
+    (the in-cell sort's single-wave gather and its block scans), and a grid of exactly 1,024
+    cells (16 x 8 x 8, each histogram block scanning 1,024 counts). Binning stage only, from
+    a workspace filled with a byte pattern, against the oracle's cells and order."""
+    _say("case: binning of", n, "atoms,", cells, "cells,", blocks, "histogram blocks")
+    import torch
+    from _gpu import to_dev
+    rng = np.random.default_rng(n % 1000)
+    pos = rng.uniform(0.0, 1.0, (n, 3)) * np.asarray(box)
+    pos = pos.astype(np.float32).astype(np.float64)
+    types = rng.integers(0, 2, n).astype(np.int32)
+    q = rng.normal(0, 0.2, n)
+    p = dict(box=box, r_cut=r_cut, r_switch=r_cut - 2.0, coulomb_k=W.COULOMB_K,
+             sigma=np.array([0.8, 0.9]), epsilon=np.array([0.05, 0.1]), flags=0)
+    lay = api.workspace_layout(p, n)
+    assert lay["n_cells"] == cells
+    chunk = -(-(-(-n // 1024)) // 2048) * 2048
+    assert -(-n // chunk) == blocks
+    d = to_dev((pos, types, q), gpu)
+    ws = api.alloc_workspace(p, n, gpu)
+    ws.fill_(0xAB)
+    force = torch.empty((n, 3), dtype=torch.float32, device=gpu)
+    energy = torch.empty(1, dtype=torch.float64, device=gpu)
+    api.forces_stages(p, *d, force, energy, ws, api.STAGE_BIN)
+    torch.cuda.synchronize()
+    assert api.read_status(ws) == 0
+    _check_binning(p, pos, ws, n)
+    del ws
+    torch.cuda.empty_cache()
+
+
 def test_binning_fused_several_rounds(gpu):
     """2,200,000 atoms, uniform in a 120 A cube of 9^3 cells (at most 1,024: each histogram
     block writes its atoms in cell order within its range and the in-cell sort gathers the
