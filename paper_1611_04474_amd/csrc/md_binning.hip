@@ -698,11 +698,12 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
 #pragma unroll
       for (int k = 0; k < kBPer; ++k) {
         const int32_t p0 = (int32_t)((int64_t)(t + bstride * k) * a.bin_chunk) + ls[k];
-        for (int32_t r = 0; r < cb[k]; ++r) {
-          if (m <= kChunk)
-            s_src[off + r] = p0 + r;
-          else
-            a.rank[s0 + off + r] = p0 + r;
+        if (m <= kChunk) {
+#pragma unroll 1
+          for (int32_t r = 0; r < cb[k]; ++r) s_src[off + r] = p0 + r;
+        } else {
+#pragma unroll 1
+          for (int32_t r = 0; r < cb[k]; ++r) a.rank[s0 + off + r] = p0 + r;
         }
         off += cb[k];
       }
@@ -775,11 +776,28 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
     }
     __syncthreads();
     if (s_over == 0) {
-      // bucket starts (one bucket per thread)
-      int32_t all;
-      const int32_t cb = s_bcnt[t];
-      const int32_t bs = block_scan_excl_w<kSortThreads / 64>(cb, s_tot, &all);
-      s_bstart[t] = bs;
+      // bucket starts: the first wave scans the counts, four consecutive buckets per lane
+      static_assert(2 * kHalfB == 4 * 64, "four buckets per lane");
+      if (t < 64) {
+        int32_t v[4], sum = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          v[k] = s_bcnt[4 * t + k];
+          sum += v[k];
+        }
+        int32_t inc = sum;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const int32_t y = __shfl_up(inc, o);
+          if (t >= o) inc += y;
+        }
+        int32_t ex = inc - sum;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          s_bstart[4 * t + k] = ex;
+          ex += v[k];
+        }
+      }
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < kPer; ++k) {
