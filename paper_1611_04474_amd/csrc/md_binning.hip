@@ -643,14 +643,18 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
   __shared__ uint16_t s_blist[2 * kHalfB * kBucketMax];
   __shared__ int32_t s_low, s_over;
   const bool fused = scan_fused(a);
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63;
   int32_t s0, m;
+  // the rank count's bucket counters, cleared before the first barrier
+  s_bcnt[t] = 0;
+  if (t == 0) s_over = 0;
   if (fused) {
     // block b's atoms of this cell are bhist[b][c + 1] - bhist[b][c] of its range, from
     // position b bin_chunk + bhist[b][c]; the cell starts at the sum over the blocks of
-    // bhist[b][c] (the atoms in earlier cells). With at most 256 blocks the first wave
-    // does it all, lane l taking blocks l, l + 64, l + 128, l + 192, with lane sums and
-    // scans; otherwise thread t takes blocks t, t + 256, ... and block scans.
+    // bhist[b][c] (the atoms in earlier cells). With at most 256 blocks every wave reads
+    // them, lane l taking blocks l, l + 64, l + 128, l + 192, and forms the start, the count
+    // and the lanes' offsets with lane sums and scans (the first wave then writes the member
+    // list); otherwise thread t takes blocks t, t + 256, ... and block scans.
     constexpr int kBPer = kBinMaxBlocks / kSortThreads;
     const int B = a.bin_blocks;
     const bool one_wave = B <= 64 * kBPer;
@@ -658,11 +662,12 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
     const int64_t row = a.n_cells + 1;
     int32_t ls[kBPer], cb[kBPer];
     int32_t sl = 0, sc = 0;
+    const int bi = one_wave ? lane : t;
 #pragma unroll
     for (int k = 0; k < kBPer; ++k) {
-      const int b = t + bstride * k;
+      const int b = bi + bstride * k;
       ls[k] = cb[k] = 0;
-      if (b < B && (!one_wave || t < 64)) {
+      if (b < B) {
         const int32_t* r = a.bhist + b * row + c;
         ls[k] = r[0];
         cb[k] = r[1] - ls[k];
@@ -672,21 +677,16 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
     }
     int32_t off;
     if (one_wave) {
-      if (t < 64) {
-        int32_t inc = sc;
+      int32_t inc = sc;
 #pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-          const int32_t y = __shfl_up(inc, o);
-          if (t >= o) inc += y;
-          sl += __shfl_xor(sl, o);
-        }
-        off = inc - sc;
-        if (t == 63) s_bstart[0] = inc;   // the cell's atom count
-        if (t == 0) s_bstart[1] = sl;     // its start
+      for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+        sl += __shfl_xor(sl, o);
       }
-      __syncthreads();
-      m = s_bstart[0];
-      s0 = s_bstart[1];
+      off = inc - sc;
+      m = __shfl(inc, 63);   // the cell's atom count
+      s0 = sl;               // its start
     } else {
       block_scan_excl_w<kSortThreads / 64>(sl, s_tot, &s0);
       off = block_scan_excl_w<kSortThreads / 64>(sc, s_tot, &m);
@@ -712,6 +712,7 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
   } else {
     s0 = a.start[c];
     m = a.start[c + 1] - s0;
+    __syncthreads();   // the bucket counters are cleared before any workgroup thread counts
   }
   // position of member e in the unsorted arrays
   auto src = [&](int32_t e) -> int32_t {
@@ -752,9 +753,6 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
 #pragma unroll
     for (int k = 0; k < kPer; ++k)
       if (k < kk) s_key[t + kSortThreads * k] = my_key[k];
-    s_bcnt[t] = 0;
-    if (t == 0) s_over = 0;
-    __syncthreads();
     // rank = members in earlier buckets + smaller keys in the member's own bucket; the
     // bucket, from the z half and x of the key, never decreases as the key grows
     const float bx0 = (float)cell_x0, bsc = (float)(kHalfB / cell_w);
