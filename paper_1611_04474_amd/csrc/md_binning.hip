@@ -154,8 +154,13 @@ __device__ inline void put_atom(const SysArgs<Real>& a, int64_t i, int c, int32_
   p.z = wrap_coord(z, a.L[2], st);
   p.w = q;
   if (t < 0 || t >= a.n_types) t = 0;
-  a.ukey[slot] = UKey{sort_key(a, (int32_t)i, (float)p.x, p.z, cz), t, 0};
-  a.upos[slot] = p;
+  // read once, by the in-cell sort: streaming stores
+  __builtin_nontemporal_store(sort_key(a, (int32_t)i, (float)p.x, p.z, cz), &a.ukey[slot].key);
+  __builtin_nontemporal_store(t, &a.ukey[slot].type);
+  __builtin_nontemporal_store(p.x, &a.upos[slot].x);
+  __builtin_nontemporal_store(p.y, &a.upos[slot].y);
+  __builtin_nontemporal_store(p.z, &a.upos[slot].z);
+  __builtin_nontemporal_store(p.w, &a.upos[slot].w);
 }
 
 // Clears the per-atom accumulators that the pair kernels add into.
