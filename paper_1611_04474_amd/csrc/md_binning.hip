@@ -163,6 +163,15 @@ __device__ inline void put_atom(const SysArgs<Real>& a, int64_t i, int c, int32_
   __builtin_nontemporal_store(p.w, &a.upos[slot].w);
 }
 
+// A four-component record with streaming stores (written once, read by the next kernels).
+template <typename Real>
+__device__ inline void store_nt(P4<Real>* dst, const P4<Real>& v) {
+  __builtin_nontemporal_store(v.x, &dst->x);
+  __builtin_nontemporal_store(v.y, &dst->y);
+  __builtin_nontemporal_store(v.z, &dst->z);
+  __builtin_nontemporal_store(v.w, &dst->w);
+}
+
 // Clears the per-atom accumulators that the pair kernels add into.
 template <typename Real>
 __device__ inline void clear_atom(const SysArgs<Real>& a, int64_t i) {
@@ -628,8 +637,8 @@ __device__ inline void write_hpre(const SysArgs<Real>& a, const P4<Real>& o, int
   h1.y = int_to_slot<Real>(t * a.n_types);
   h1.z = Real(0);
   h1.w = Real(0);
-  a.hpre[2 * (int64_t)d] = h0;
-  a.hpre[2 * (int64_t)d + 1] = h1;
+  store_nt(&a.hpre[2 * (int64_t)d], h0);
+  store_nt(&a.hpre[2 * (int64_t)d + 1], h1);
 }
 
 // Threads of a workgroup of k_cell_sort.
@@ -839,9 +848,9 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
       p.y = py[k];
       p.z = pz[k];
       p.w = pq[k];
-      a.pos[d] = p;
-      a.type[d] = my_t[k];
-      a.perm[d] = (int32_t)(my_key[k] & 0x7fffffffull);
+      store_nt(&a.pos[d], p);
+      __builtin_nontemporal_store(my_t[k], &a.type[d]);
+      __builtin_nontemporal_store((int32_t)(my_key[k] & 0x7fffffffull), &a.perm[d]);
       if (a.compact) write_hpre(a, o, d, p, my_t[k]);
       if (fused) clear_atom(a, d);
     }
@@ -882,9 +891,9 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
       const int32_t sp = src(e);
       const P4<Real> p = a.upos[sp];
       const int32_t ty = a.ukey[sp].type;
-      a.pos[d] = p;
-      a.type[d] = ty;
-      a.perm[d] = (int32_t)(my_key[k] & 0x7fffffffull);
+      store_nt(&a.pos[d], p);
+      __builtin_nontemporal_store(ty, &a.type[d]);
+      __builtin_nontemporal_store((int32_t)(my_key[k] & 0x7fffffffull), &a.perm[d]);
       if (a.compact) write_hpre(a, o, d, p, ty);
       if (fused) clear_atom(a, d);
     }
