@@ -143,7 +143,20 @@ __device__ inline unsigned long long sort_key(const SysArgs<Real>& a, int32_t i,
 
 // Atom i (of cell c) goes to slot `slot` of the cell-major arrays that precede the in-cell
 // sort: its sort key and type as one 16-byte record, and its wrapped (x, y, z, q).
+// A four-component record with streaming stores (written once, read by the next kernels).
 template <typename Real>
+__device__ inline void store_nt(P4<Real>* dst, const P4<Real>& v) {
+  __builtin_nontemporal_store(v.x, &dst->x);
+  __builtin_nontemporal_store(v.y, &dst->y);
+  __builtin_nontemporal_store(v.z, &dst->z);
+  __builtin_nontemporal_store(v.w, &dst->w);
+}
+
+// kNt: streaming stores (grids of at most kScanFused cells, where each block writes its own
+// range and they measured faster); larger grids' k_scatter needs L2 to merge the partial
+// lines of its scattered stores. A compile-time choice: a run-time branch between the two
+// store forms lets the compiler merge them and drop the hint.
+template <bool kNt, typename Real>
 __device__ inline void put_atom(const SysArgs<Real>& a, int64_t i, int c, int32_t slot, Real x,
                                 Real y, Real z, Real q, int t) {
   const int cz = c / (a.nx * a.ny);   // fewer than 2^24 cells
@@ -154,22 +167,15 @@ __device__ inline void put_atom(const SysArgs<Real>& a, int64_t i, int c, int32_
   p.z = wrap_coord(z, a.L[2], st);
   p.w = q;
   if (t < 0 || t >= a.n_types) t = 0;
-  // read once, by the in-cell sort: streaming stores
-  __builtin_nontemporal_store(sort_key(a, (int32_t)i, (float)p.x, p.z, cz), &a.ukey[slot].key);
-  __builtin_nontemporal_store(t, &a.ukey[slot].type);
-  __builtin_nontemporal_store(p.x, &a.upos[slot].x);
-  __builtin_nontemporal_store(p.y, &a.upos[slot].y);
-  __builtin_nontemporal_store(p.z, &a.upos[slot].z);
-  __builtin_nontemporal_store(p.w, &a.upos[slot].w);
-}
-
-// A four-component record with streaming stores (written once, read by the next kernels).
-template <typename Real>
-__device__ inline void store_nt(P4<Real>* dst, const P4<Real>& v) {
-  __builtin_nontemporal_store(v.x, &dst->x);
-  __builtin_nontemporal_store(v.y, &dst->y);
-  __builtin_nontemporal_store(v.z, &dst->z);
-  __builtin_nontemporal_store(v.w, &dst->w);
+  const UKey uk{sort_key(a, (int32_t)i, (float)p.x, p.z, cz), t, 0};
+  if constexpr (kNt) {
+    __builtin_nontemporal_store(uk.key, &a.ukey[slot].key);
+    __builtin_nontemporal_store(uk.type, &a.ukey[slot].type);
+    store_nt(&a.upos[slot], p);
+  } else {
+    a.ukey[slot] = uk;
+    a.upos[slot] = p;
+  }
 }
 
 // Clears the per-atom accumulators that the pair kernels add into.
@@ -283,13 +289,13 @@ __device__ inline void bin_hist(const SysArgs<Real>& a, int64_t blk) {
 #pragma unroll
     for (int u = 0; u < kHistPer; ++u) {
       const int64_t i = i0 + u * kBinThreads + tid;
-      if (i < i1) put_atom(a, i, c[u], (int32_t)(i0 + s_h[c[u]] + rk[u]), x[u], y[u], z[u], q[u], ty[u]);
+      if (i < i1) put_atom<true>(a, i, c[u], (int32_t)(i0 + s_h[c[u]] + rk[u]), x[u], y[u], z[u], q[u], ty[u]);
     }
     return;
   }
   for (int64_t i = i0 + tid; i < i1; i += kBinThreads) {
     const int ci = a.cell[i];
-    put_atom(a, i, ci, (int32_t)(i0 + s_h[ci] + a.rank[i]), a.pos_in[3 * i + 0],
+    put_atom<true>(a, i, ci, (int32_t)(i0 + s_h[ci] + a.rank[i]), a.pos_in[3 * i + 0],
              a.pos_in[3 * i + 1], a.pos_in[3 * i + 2], a.q_in[i], a.type_in[i]);
   }
 }
@@ -409,15 +415,15 @@ __device__ inline uint32_t cost_key(uint32_t ticks) { return ticks >> 4; }
 // 0 .. 63) carries the histogram blocks' status bits from block_status.
 template <int kThreads, typename Real, typename Key>
 __device__ inline void scan_tail(const SysArgs<Real>& a, const TypeTable& tt, int own_header,
-                                 int32_t* s_tot, Key key, uint32_t st_lane) {
+                                 int32_t* s_tot, int32_t* s_bin, Key key, uint32_t st_lane) {
   const int t = threadIdx.x;
   const int64_t nc = a.n_cells;
   // counting sort of the cells by decreasing key (keys clamped to kOrderBins - 1); the
   // order within a bin is arbitrary, which only changes which compute unit takes a cell,
   // never a result. Longest first lets the short cells fill the tail.
   constexpr int kOrderBins = 1024;
-  constexpr int kPerT = kOrderBins / kThreads;   // bins per thread, consecutive
-  __shared__ int32_t s_bin[kOrderBins];
+  constexpr int kPerT = kOrderBins / kThreads;   // bins per thread, consecutive (s_bin holds
+                                                 // kOrderBins)
 #pragma unroll
   for (int k = 0; k < kPerT; ++k) s_bin[kPerT * t + k] = 0;
   __syncthreads();
@@ -542,7 +548,8 @@ __device__ inline void bin_scan(const SysArgs<Real>& a, const TypeTable& tt, int
   if (t == 0) a.start[nc] = carry;
   // launch order by atom count: with more than 1024 cells there are several workgroups
   // per compute unit, and the short cells already fill the tail
-  scan_tail<1024>(a, tt, own_header, s_tot, [&](int64_t c) { return (uint32_t)count(c); },
+  __shared__ int32_t s_bin[1024];
+  scan_tail<1024>(a, tt, own_header, s_tot, s_bin, [&](int64_t c) { return (uint32_t)count(c); },
             st_blocks.bits());
 }
 
@@ -578,7 +585,7 @@ __device__ inline void scatter(const SysArgs<Real>& a, int64_t blk) {
   const int c = a.cell[i];
   int32_t slot = a.start[c] + a.rank[i];
   if (a.bin_blocks > 0) slot += a.bhist[(i / a.bin_chunk) * a.n_cells + c];
-  put_atom(a, i, c, slot, a.pos_in[3 * i + 0], a.pos_in[3 * i + 1], a.pos_in[3 * i + 2],
+  put_atom<false>(a, i, c, slot, a.pos_in[3 * i + 0], a.pos_in[3 * i + 1], a.pos_in[3 * i + 2],
            a.q_in[i], a.type_in[i]);
 }
 
@@ -622,7 +629,7 @@ __device__ inline P4<Real> cell_centre(const SysArgs<Real>& a, int64_t c) {
 // prefilter |r_j - r_i|^2 = c_j - 2 a.(r_j - o) + |a|^2 becomes
 // c_j + (-2 a).r_j < rc^2 + margin - |a|^2 + (-2 a).o; and k q and the atom's row of the
 // type-pair table.
-template <typename Real>
+template <bool kNt, typename Real>
 __device__ inline void write_hpre(const SysArgs<Real>& a, const P4<Real>& o, int32_t d,
                                   const P4<Real>& p, int t) {
   const Real rx = p.x - o.x, ry = p.y - o.y, rz = p.z - o.z;
@@ -637,25 +644,52 @@ __device__ inline void write_hpre(const SysArgs<Real>& a, const P4<Real>& o, int
   h1.y = int_to_slot<Real>(t * a.n_types);
   h1.z = Real(0);
   h1.w = Real(0);
-  store_nt(&a.hpre[2 * (int64_t)d], h0);
-  store_nt(&a.hpre[2 * (int64_t)d + 1], h1);
+  if constexpr (kNt) {
+    store_nt(&a.hpre[2 * (int64_t)d], h0);
+    store_nt(&a.hpre[2 * (int64_t)d + 1], h1);
+  } else {
+    a.hpre[2 * (int64_t)d] = h0;
+    a.hpre[2 * (int64_t)d + 1] = h1;
+  }
 }
 
 // Threads of a workgroup of k_cell_sort.
 constexpr int kSortThreads = 256;
+constexpr int kSortChunk = 1024;                      // members ranked in one LDS chunk
+constexpr int kHalfB = kSortThreads / 2;              // rank-count buckets per z half
+constexpr int kBucketMax = 8;                         // members a bucket holds
 
-template <typename Real>
+// LDS of a k_cell_sort workgroup, one object for every form of the kernel's code (the
+// sort's two store forms and the tail), so that it is allocated once: 18.5 KB leaves room
+// for eight workgroups per compute unit.
+struct SortLds {
+  unsigned long long key[kSortChunk];
+  int32_t src[kSortChunk];
+  int32_t bcnt[2 * kHalfB], bstart[2 * kHalfB];
+  uint16_t blist[2 * kHalfB * kBucketMax];
+  int32_t tot[kSortThreads / 64];
+  int32_t low, over;
+};
+__device__ inline SortLds& sort_lds() {
+  __shared__ SortLds l;
+  return l;
+}
+
+// kNt: the outputs with streaming stores (grids of at most kScanFused cells).
+template <bool kNt, typename Real>
 __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
-  constexpr int kChunk = 1024;
+  constexpr int kChunk = kSortChunk;
   constexpr int kPer = kChunk / kSortThreads;
   // buckets of the rank count: kHalfB per z half, in x order, at most kBucketMax members each
-  constexpr int kHalfB = kSortThreads / 2, kBucketMax = 8;
-  __shared__ unsigned long long s_key[kChunk];
-  __shared__ int32_t s_src[kChunk];
-  __shared__ int32_t s_tot[kSortThreads / 64];
-  __shared__ int32_t s_bcnt[2 * kHalfB], s_bstart[2 * kHalfB];
-  __shared__ uint16_t s_blist[2 * kHalfB * kBucketMax];
-  __shared__ int32_t s_low, s_over;
+  SortLds& L = sort_lds();
+  unsigned long long* s_key = L.key;
+  int32_t* s_src = L.src;
+  int32_t* s_tot = L.tot;
+  int32_t* s_bcnt = L.bcnt;
+  int32_t* s_bstart = L.bstart;
+  uint16_t* s_blist = L.blist;
+  int32_t& s_low = L.low;
+  int32_t& s_over = L.over;
   const bool fused = scan_fused(a);
   const int t = threadIdx.x, lane = t & 63;
   int32_t s0, m;
@@ -848,10 +882,16 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
       p.y = py[k];
       p.z = pz[k];
       p.w = pq[k];
-      store_nt(&a.pos[d], p);
-      __builtin_nontemporal_store(my_t[k], &a.type[d]);
-      __builtin_nontemporal_store((int32_t)(my_key[k] & 0x7fffffffull), &a.perm[d]);
-      if (a.compact) write_hpre(a, o, d, p, my_t[k]);
+      if constexpr (kNt) {
+        store_nt(&a.pos[d], p);
+        __builtin_nontemporal_store(my_t[k], &a.type[d]);
+        __builtin_nontemporal_store((int32_t)(my_key[k] & 0x7fffffffull), &a.perm[d]);
+      } else {
+        a.pos[d] = p;
+        a.type[d] = my_t[k];
+        a.perm[d] = (int32_t)(my_key[k] & 0x7fffffffull);
+      }
+      if (a.compact) write_hpre<kNt>(a, o, d, p, my_t[k]);
       if (fused) clear_atom(a, d);
     }
     __syncthreads();
@@ -891,10 +931,16 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
       const int32_t sp = src(e);
       const P4<Real> p = a.upos[sp];
       const int32_t ty = a.ukey[sp].type;
-      store_nt(&a.pos[d], p);
-      __builtin_nontemporal_store(ty, &a.type[d]);
-      __builtin_nontemporal_store((int32_t)(my_key[k] & 0x7fffffffull), &a.perm[d]);
-      if (a.compact) write_hpre(a, o, d, p, ty);
+      if constexpr (kNt) {
+        store_nt(&a.pos[d], p);
+        __builtin_nontemporal_store(ty, &a.type[d]);
+        __builtin_nontemporal_store((int32_t)(my_key[k] & 0x7fffffffull), &a.perm[d]);
+      } else {
+        a.pos[d] = p;
+        a.type[d] = ty;
+        a.perm[d] = (int32_t)(my_key[k] & 0x7fffffffull);
+      }
+      if (a.compact) write_hpre<kNt>(a, o, d, p, ty);
       if (fused) clear_atom(a, d);
     }
   }
@@ -908,8 +954,11 @@ __device__ inline void cell_sort(const SysArgs<Real>& a, int64_t c) {
 // its atom count summed over the histogram blocks.
 template <typename Real>
 __device__ inline void bin_tail(const SysArgs<Real>& a, const TypeTable& tt) {
-  __shared__ uint32_t s_k[kScanFused];
-  __shared__ int32_t s_tot[kSortThreads / 64];
+  static_assert(sizeof(SortLds::key) >= 4 * kScanFused && sizeof(SortLds::src) >= 4 * 1024,
+                "the tail's arrays fit the sort's");
+  SortLds& L = sort_lds();
+  uint32_t* s_k = reinterpret_cast<uint32_t*>(L.key);   // [kScanFused] order keys
+  int32_t* s_tot = L.tot;
   const int t = threadIdx.x;
   const int nc = (int)a.n_cells, B = a.bin_blocks;
   const int64_t row = nc + 1;
@@ -935,7 +984,8 @@ __device__ inline void bin_tail(const SysArgs<Real>& a, const TypeTable& tt) {
     s_k[c] = key;
   }
   __syncthreads();
-  scan_tail<kSortThreads>(a, tt, 1, s_tot, [&](int64_t c) { return s_k[c]; }, st_blocks.bits());
+  scan_tail<kSortThreads>(a, tt, 1, s_tot, L.src, [&](int64_t c) { return s_k[c]; },
+                          st_blocks.bits());
 }
 
 // Block blk of k_cell_sort: with the fused scan, block 0 ends the binning and block c + 1
@@ -943,11 +993,11 @@ __device__ inline void bin_tail(const SysArgs<Real>& a, const TypeTable& tt) {
 template <typename Real>
 __device__ inline void cell_sort_or_tail(const SysArgs<Real>& a, const TypeTable& tt, int64_t blk) {
   if (!scan_fused(a)) {
-    cell_sort(a, blk);
+    cell_sort<false>(a, blk);
   } else if (blk == 0) {
     bin_tail(a, tt);
   } else {
-    cell_sort(a, blk - 1);
+    cell_sort<true>(a, blk - 1);
   }
 }
 
