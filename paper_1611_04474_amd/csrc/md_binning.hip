@@ -141,8 +141,6 @@ __device__ inline unsigned long long sort_key(const SysArgs<Real>& a, int32_t i,
          ((unsigned long long)__builtin_bit_cast(uint32_t, x + 0.f) << 31) | (uint32_t)i;
 }
 
-// Atom i (of cell c) goes to slot `slot` of the cell-major arrays that precede the in-cell
-// sort: its sort key and type as one 16-byte record, and its wrapped (x, y, z, q).
 // A four-component record with streaming stores (written once, read by the next kernels).
 template <typename Real>
 __device__ inline void store_nt(P4<Real>* dst, const P4<Real>& v) {
@@ -152,6 +150,8 @@ __device__ inline void store_nt(P4<Real>* dst, const P4<Real>& v) {
   __builtin_nontemporal_store(v.w, &dst->w);
 }
 
+// Atom i (of cell c) goes to slot `slot` of the cell-major arrays that precede the in-cell
+// sort: its sort key and type as one 16-byte record, and its wrapped (x, y, z, q).
 // kNt: streaming stores (grids of at most kScanFused cells, where each block writes its own
 // range and they measured faster); larger grids' k_scatter needs L2 to merge the partial
 // lines of its scattered stores. A compile-time choice: a run-time branch between the two
